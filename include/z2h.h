@@ -1,0 +1,248 @@
+/*
+ * z2h -- Trotterized adiabatic state-vector evolution of the toric code in two
+ * transverse fields (the Z2 gauge-Higgs model in its mapped form) on one
+ * MI355X (gfx950) GPU.
+ *
+ * Model (Sec. II, Eq. (effi), with the star and plaquette couplings made
+ * parameters):
+ *     H(c) = -JA sum_v A_v - JB sum_p B_p - hx sum_l X_l - hz sum_l Z_l
+ * on the n = 2*Lx*Ly link qubits of a periodic Lx x Ly lattice.  The paper's
+ * point (g, lambda) with J = h = 1/2 is c = (1/2, 1/2, g, lambda).
+ *
+ * Method (Sec. III): an adiabatic ramp c(s) = (1-s) c_start + s c_end in M
+ * steps of equal duration dt, each a second-order Trotter-Suzuki step
+ * exp(-iH1 dt/2) exp(-iH2 dt/2) exp(-iH3 dt) exp(-iH2 dt/2) exp(-iH1 dt/2).
+ * Because every summand inside each factor commutes (Eq. (decom)), the step
+ * equals exp(-iHX dt/2) exp(-iHZ dt) exp(-iHX dt/2) with HX = star + x-field
+ * terms and HZ = plaquette + z-field terms; the library applies HZ as one
+ * diagonal phase in the computational basis and HX as one diagonal phase in
+ * the Hadamard basis reached by an in-place Walsh-Hadamard transform.
+ *
+ * Conventions
+ *   - Link numbering (library): h(x,y) = link from vertex (x,y) to (x+1,y),
+ *     bit y*Lx + x; v(x,y) = link from (x,y) to (x,y+1), bit Lx*Ly + y*Lx + x.
+ *     Star A(x,y) = X on {h(x,y), h(x-1,y), v(x,y), v(x,y-1)}; plaquette
+ *     B(x,y) = Z on {h(x,y), h(x,y+1), v(x,y), v(x+1,y)}.  z2h_link_bit()
+ *     gives the map; observables do not depend on it.
+ *   - Bit l of a basis index = 0 means sigma^z_l = +1.
+ *   - A state is 2^n interleaved complex numbers (re, im), complex64
+ *     (2 x float) or complex128 (2 x double), in device memory.
+ *
+ * Ownership: the caller owns every device buffer (state, workspace, outputs)
+ * and the stream; the library only borrows them for the call.  A plan or a
+ * batch owns its small device tables and frees them in *_destroy.  After
+ * creation no call allocates device memory.
+ *
+ * Errors: every function returns a z2h_status and never aborts.  Arguments
+ * are validated before anything is enqueued; on error nothing is enqueued
+ * and z2h_last_error() describes the problem.  Device work is asynchronous
+ * on the given stream; functions with host outputs synchronize that stream
+ * and report earlier device failures as Z2H_ERR_HIP.
+ */
+#ifndef Z2H_H
+#define Z2H_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t z2h_status;
+#define Z2H_OK 0
+#define Z2H_ERR_INVALID (-1)     /* bad argument (null pointer, size, range) */
+#define Z2H_ERR_UNSUPPORTED (-2) /* valid but not supported (n > 32, ...) */
+#define Z2H_ERR_OOM (-3)         /* host or device allocation failed at creation */
+#define Z2H_ERR_HIP (-4)         /* HIP runtime error, or no usable device */
+#define Z2H_ERR_NUMERIC (-5)     /* non-finite norm or energy */
+#define Z2H_ERR_WORKSPACE (-6)   /* workspace smaller than required */
+
+typedef int32_t z2h_dtype;
+#define Z2H_C64 0  /* complex64: FP32 butterflies, FP64 angles and reductions */
+#define Z2H_C128 1 /* complex128 */
+
+typedef int32_t z2h_init;
+#define Z2H_INIT_PSI1 0  /* Eq. (ini1): all plaquettes even, equal weights */
+#define Z2H_INIT_PSI1P 1 /* Eq. (ini2): all stars +1 (projected |0...0>) */
+#define Z2H_INIT_ZERO 2  /* |0...0> */
+#define Z2H_INIT_PLUS 3  /* |+...+> */
+
+typedef struct {
+    double JA, JB, hx, hz; /* H = -JA sum A - JB sum B - hx sum X - hz sum Z */
+} z2h_couplings;
+
+/*
+ * Schedule of an adiabatic ramp (Sec. III): M = steps steps of duration dt.
+ * Step k uses c(s) = (1-s) start + s end with s = s_k:
+ *   sampling 0: s_k = (k + 1/2)/M (midpoint), 1: s_k = (k + 1)/M (the
+ *   paper's g = k*dg, Appendix Eq. (target)).
+ * If sZ / sX are non-NULL (host arrays of length steps) they replace s_k for
+ * the z-type couplings (JB, hz) and the x-type couplings (JA, hx) of each
+ * step; these are the "schedule angles" the adjoint differentiates.
+ * Only steps k_begin <= k < k_end are applied (0, steps: the whole ramp), so
+ * a ramp can be split across calls and resumed from a saved state.
+ * order 0: x-z-x step (the paper's); 1: z-x-z (used by duality checks).
+ * renorm 1: rescale the state to unit norm once per step (from the norm
+ * measured during the previous diagonal pass); 0: unitary passes only.
+ */
+typedef struct {
+    z2h_couplings start, end;
+    int64_t steps;
+    double dt;
+    int64_t k_begin, k_end;
+    int32_t sampling;
+    int32_t order;
+    int32_t renorm;
+    int32_t reserved;
+    const double *sZ;
+    const double *sX;
+} z2h_schedule;
+
+#define Z2H_MAX_LOOPS 8
+#define Z2H_DOS_BINS 33
+/*
+ * Observables of a state psi (Sec. IV, V).  All expectations are divided by
+ * the norm <psi|psi>.  energy = <H(c)> for the couplings passed to observe.
+ * sumA = sum_v <A_v>, sumB = sum_p <B_p>; mx, mz = mean over links of <X_l>
+ * and <Z_l>.  zloop[j] = <prod over zmask_j of Z>, xloop[j] = <prod over
+ * xmask_j of X> (Wilson and 't Hooft loops).  dos[w] = weight of psi on the
+ * eigenvalue Ztilde = 2w - n of Ztilde = -sum_l Z_l (Sec. V), w = 0..n.
+ * The same 48 doubles are the device output layout (index order below).
+ */
+typedef struct {
+    double norm, energy, sumA, sumB, mx, mz; /* 0..5 */
+    double zloop[Z2H_MAX_LOOPS];             /* 6..13 */
+    double xloop[Z2H_MAX_LOOPS];             /* 14..21 */
+    double dos[Z2H_DOS_BINS];                /* 22..54 */
+    double xnorm;                            /* 55: norm measured in the X basis */
+} z2h_obs;
+#define Z2H_OBS_DOUBLES 56
+
+typedef struct z2h_plan z2h_plan;
+typedef struct z2h_batch z2h_batch;
+
+/* ------------------------------------------------------------------ lattice */
+
+/* Library bit of link h(x,y) (dir 0) or v(x,y) (dir 1); x, y taken modulo
+ * the lattice.  Host only. */
+z2h_status z2h_link_bit(int32_t Lx, int32_t Ly, int32_t x, int32_t y, int32_t dir,
+                        int32_t *bit);
+
+/* Star and plaquette masks (Sec. II) in library numbering, one uint64 per
+ * vertex (index y*Lx + x); caller arrays of Lx*Ly entries.  Host only. */
+z2h_status z2h_masks(int32_t Lx, int32_t Ly, uint64_t *stars, uint64_t *plaqs);
+
+/* ------------------------------------------------------------------ plans */
+
+/*
+ * Plan for one lattice and precision on the current HIP device: masks,
+ * syndrome data, pass schedule (tile geometry of every Walsh-Hadamard pass).
+ * Lx, Ly >= 2, n = 2 Lx Ly <= 32.  max_tile_bits 0 = automatic; a smaller
+ * value forces more passes per step (used to test the multi-group schedule
+ * at small n).
+ */
+z2h_status z2h_plan_create(int32_t Lx, int32_t Ly, z2h_dtype dtype, int32_t max_tile_bits,
+                           z2h_plan **out);
+void z2h_plan_destroy(z2h_plan *plan); /* NULL-safe */
+
+/* state_bytes = 2^n * sizeof(complex); ws_evolve_bytes = workspace needed by
+ * z2h_evolve; ws_observe_bytes = workspace needed by z2h_observe (includes a
+ * state-sized scratch copy); ws_adjoint_bytes = workspace for z2h_adjoint. */
+z2h_status z2h_plan_sizes(const z2h_plan *plan, size_t *state_bytes, size_t *ws_evolve_bytes,
+                          size_t *ws_observe_bytes, size_t *ws_adjoint_bytes);
+
+/* Passes (HBM sweeps of the state) per Trotter step, and the number of
+ * qubit groups the Walsh-Hadamard transform is split into. */
+z2h_status z2h_plan_info(const z2h_plan *plan, int32_t *n, int32_t *groups,
+                         int32_t *passes_per_step, int32_t *tile_bits);
+
+/* JSON description of the pass schedule (host only, for diagnostics and
+ * tests): R (log2 amplitudes per thread) and, per group, the tile bits m,
+ * carried low bits c, first transformed global bit b0, transformed local
+ * range [x0, x1), register layouts p[] and their butterfly ranges. */
+z2h_status z2h_plan_describe(const z2h_plan *plan, char *buf, size_t len);
+
+/* Fill d_state (256-byte aligned, state_bytes) with an initial state
+ * (Sec. IV, Eqs. (ini1), (ini2)). */
+z2h_status z2h_state_init(const z2h_plan *plan, void *d_state, z2h_init kind, void *stream);
+
+/*
+ * Apply steps [k_begin, k_end) of the schedule to d_state in place.
+ * d_ws: workspace of at least ws_evolve_bytes (device).  If d_norms is not
+ * NULL it receives, per applied step, the norm measured in that step's
+ * diagonal z pass (device doubles, k_end - k_begin entries).
+ */
+z2h_status z2h_evolve(const z2h_plan *plan, void *d_state, void *d_ws, size_t ws_bytes,
+                      const z2h_schedule *sched, double *d_norms, void *stream);
+
+/*
+ * Observables of d_state (not modified) for the couplings H (Sec. IV-V).
+ * zmasks/xmasks: up to Z2H_MAX_LOOPS loop masks each (library numbering,
+ * bits < n), may be NULL when the count is 0.  h_out (host) is filled after
+ * a stream synchronization if not NULL; d_out (device, Z2H_OBS_DOUBLES
+ * doubles, same order as z2h_obs) is filled asynchronously if not NULL.
+ * Returns Z2H_ERR_NUMERIC when h_out is requested and the norm or energy is
+ * not finite.
+ */
+z2h_status z2h_observe(const z2h_plan *plan, const void *d_state, void *d_ws, size_t ws_bytes,
+                       const z2h_couplings *H, const uint64_t *zmasks, int32_t nz,
+                       const uint64_t *xmasks, int32_t nx, z2h_obs *h_out, double *d_out,
+                       void *stream);
+
+/*
+ * Gradient of L = <psi_M| H(lossH) |psi_M> / <psi_M|psi_M> with respect to
+ * the per-step schedule values sZ[k] and sX[k] (see z2h_schedule), by
+ * reverse evolution with the inverse passes (every pass is unitary, so no
+ * intermediate state is stored).  d_psi_final: the state after the full
+ * forward ramp of sched (k_begin = 0, k_end = steps, renorm 0); it is not
+ * modified.  d_gradZ, d_gradX: device arrays of steps doubles.  d_ws: at
+ * least ws_adjoint_bytes.  h_loss (host, may be NULL): L, after a sync.
+ */
+z2h_status z2h_adjoint(const z2h_plan *plan, const void *d_psi_final, void *d_ws,
+                       size_t ws_bytes, const z2h_schedule *sched, const z2h_couplings *lossH,
+                       double *d_gradZ, double *d_gradX, double *h_loss, void *stream);
+
+/* ------------------------------------------------------------------ batches */
+
+/*
+ * A batch of independent ramps (phase-diagram points, lattices of uneven
+ * size) evolved together: lattice (Lx[j], Ly[j]), schedule sched[j] (sZ, sX
+ * must be NULL; k range must be the whole ramp), initial state init[j], and
+ * the couplings obsH[j] whose energy is reported.  All states live in one
+ * device buffer; state_offsets[j] (host output, bytes) is where state j
+ * starts.  The launch sequence of the whole batch (initialization, every
+ * pass of every job, observables) is recorded once in a HIP graph.
+ */
+z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
+                            const z2h_schedule *sched, const z2h_init *init,
+                            const z2h_couplings *obsH, z2h_dtype dtype, z2h_batch **out,
+                            size_t *states_bytes, size_t *ws_bytes, uint64_t *state_offsets);
+
+/* Run the batch: every state is initialized, evolved and observed.
+ * d_obs: device, njobs * Z2H_OBS_DOUBLES doubles.  zloop[0] of each job is
+ * the Wilson loop around the 1 x 3 (or 1 x Lx) strip of plaquettes in row 0,
+ * zloop[1] the L-shaped three-plaquette loop, zloop[2] and [3] the
+ * noncontractible Wilson loops, xloop[0..1] the 't Hooft loops. */
+z2h_status z2h_batch_run(z2h_batch *batch, void *d_states, void *d_ws, size_t ws_bytes,
+                         double *d_obs, void *stream);
+void z2h_batch_destroy(z2h_batch *batch); /* NULL-safe */
+
+/* ------------------------------------------------------------------ misc */
+
+/* Enable (1) or disable (0) per-kernel event timing of the pass kernels
+ * launched by this thread; z2h_timing_read returns the number of timed
+ * launches and the summed milliseconds per pass kind (0: z pass, 1: x pass,
+ * 2: plain transform pass, 3: other) and resets the counters.  Timing
+ * synchronizes each launch's end event when read. */
+z2h_status z2h_timing_enable(int32_t on);
+z2h_status z2h_timing_read(int64_t counts[4], double ms[4]);
+
+/* Library version string and the last error message of this thread. */
+const char *z2h_version(void);
+const char *z2h_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* Z2H_H */

@@ -1,0 +1,774 @@
+// Host runtime and C ABI of libz2h: lattice, pass planner, plans, launch
+// sequences, validation and error reporting.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/z2h.h"
+#include "z2h_internal.h"
+#include "z2h_kernels.h"
+
+using namespace z2h;
+
+// ------------------------------------------------------------------ errors
+
+static thread_local std::string g_err;
+
+static z2h_status fail(z2h_status code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                  \
+    do {                                                                               \
+        hipError_t e_ = (expr);                                                        \
+        if (e_ != hipSuccess)                                                          \
+            return fail(Z2H_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+    } while (0)
+
+// ------------------------------------------------------------------ lattice
+
+// Library numbering (see the header): h(x,y) = y*Lx + x, v(x,y) = Lx*Ly + y*Lx + x.
+static int link_bit(int Lx, int Ly, int x, int y, int dir) {
+    x = ((x % Lx) + Lx) % Lx;
+    y = ((y % Ly) + Ly) % Ly;
+    return (dir ? Lx * Ly : 0) + y * Lx + x;
+}
+
+static void build_masks(int Lx, int Ly, uint64_t *st, uint64_t *pl) {
+    for (int y = 0; y < Ly; ++y)
+        for (int x = 0; x < Lx; ++x) {
+            st[y * Lx + x] = (1ull << link_bit(Lx, Ly, x, y, 0)) | (1ull << link_bit(Lx, Ly, x - 1, y, 0)) |
+                             (1ull << link_bit(Lx, Ly, x, y, 1)) | (1ull << link_bit(Lx, Ly, x, y - 1, 1));
+            pl[y * Lx + x] = (1ull << link_bit(Lx, Ly, x, y, 0)) | (1ull << link_bit(Lx, Ly, x, y + 1, 0)) |
+                             (1ull << link_bit(Lx, Ly, x, y, 1)) | (1ull << link_bit(Lx, Ly, x + 1, y, 1));
+        }
+}
+
+static z2h_status check_lattice(int Lx, int Ly) {
+    if (Lx < 2 || Ly < 2) return fail(Z2H_ERR_INVALID, "lattice %dx%d: Lx and Ly must be >= 2", Lx, Ly);
+    if (2 * Lx * Ly > kMaxN)
+        return fail(Z2H_ERR_UNSUPPORTED, "lattice %dx%d has %d links; at most %d are supported", Lx, Ly,
+                    2 * Lx * Ly, kMaxN);
+    return Z2H_OK;
+}
+
+static LatticeDev make_latdev(int Lx, int Ly) {
+    LatticeDev L;
+    memset(&L, 0, sizeof L);
+    const int n = 2 * Lx * Ly, ns = Lx * Ly;
+    uint64_t st[kMaxStab], pl[kMaxStab];
+    build_masks(Lx, Ly, st, pl);
+    L.n = n;
+    L.nst = ns;
+    for (int k = 0; k < ns; ++k) {
+        L.zmask[k] = (uint32_t)pl[k];
+        L.xmask[k] = (uint32_t)st[k];
+        for (int l = 0; l < n; ++l) {
+            if (pl[k] >> l & 1) L.zsyn[l] |= 1u << k;
+            if (st[k] >> l & 1) L.xsyn[l] |= 1u << k;
+        }
+    }
+    return L;
+}
+
+// ------------------------------------------------------------------ planner
+
+struct Plan {
+    int Lx, Ly, n, nst;
+    bool c128;
+    size_t esize;
+    int K;                       // groups (1: whole state in one workgroup)
+    int R;                       // log2 register elements per thread
+    GroupGeom geom[kMaxGroups];
+    LatticeDev lat;
+    int device;
+};
+
+// Register-layout sequence covering local transform bits [x0, x1).
+static void plan_layouts(GroupGeom &g, int R) {
+    int p = g.x1 - R, prev = g.x1;
+    g.nlay = 0;
+    while (true) {
+        if (p < g.x0) p = g.x0;
+        g.p[g.nlay] = p;
+        g.blo[g.nlay] = 0;
+        g.bhi[g.nlay] = prev - p;
+        g.nlay++;
+        if (p == g.x0) break;
+        prev = p;
+        p -= R;
+    }
+}
+
+static int pick_R(bool c128, int m) {
+    int R = c128 ? 4 : 5;
+    while (R > 2 && m - R < 6) --R;  // keep at least one wave per workgroup
+    return R;
+}
+
+static z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P) {
+    z2h_status st = check_lattice(Lx, Ly);
+    if (st) return st;
+    P.Lx = Lx;
+    P.Ly = Ly;
+    P.n = 2 * Lx * Ly;
+    P.nst = Lx * Ly;
+    P.c128 = c128;
+    P.esize = c128 ? 16 : 8;
+    P.lat = make_latdev(Lx, Ly);
+    const int n = P.n;
+    const int c_min = c128 ? 3 : 4;          // 128-byte contiguous runs
+    const int m_lo = c128 ? 12 : 13;          // preferred tile (64 KiB + padding)
+    int m_hi = c128 ? 13 : 14;                // largest tile that fits in LDS
+    if (max_tile_bits) {
+        if (max_tile_bits < 8 || max_tile_bits > m_hi)
+            return fail(Z2H_ERR_INVALID, "max_tile_bits %d outside [8, %d]", max_tile_bits, m_hi);
+        m_hi = max_tile_bits;
+    }
+    const int m_pref = std::min(m_lo, m_hi);
+    memset(P.geom, 0, sizeof P.geom);
+    if (n <= m_hi) {
+        P.K = 1;
+        GroupGeom &g = P.geom[0];
+        g.m = n;
+        g.c = 0;
+        g.b0 = 0;
+        g.x0 = 0;
+        g.x1 = n;
+        g.tiles_log2 = 0;
+        P.R = pick_R(c128, n);
+        plan_layouts(g, P.R);
+        return Z2H_OK;
+    }
+    // Fewest groups first, then the smallest tile that reaches n bits.
+    int K = 0, m = 0;
+    for (int k = 2; k <= kMaxGroups && !K; ++k)
+        for (int mm = m_pref; mm <= m_hi; ++mm)
+            if (mm + (k - 1) * (mm - c_min) >= n) {
+                K = k;
+                m = mm;
+                break;
+            }
+    if (!K) return fail(Z2H_ERR_UNSUPPORTED, "no pass schedule for n = %d with tiles of 2^%d", n, m_hi);
+    P.K = K;
+    P.R = pick_R(c128, m);
+    // Balanced split of the n bits: group 0 takes up to m bits, the others up
+    // to m - c_min bits each.
+    int gbits[kMaxGroups];
+    int rest = n;
+    for (int j = 0; j < K; ++j) {
+        const int cap = j == 0 ? m : m - c_min;
+        const int share = (rest + (K - j) - 1) / (K - j);
+        gbits[j] = std::min(cap, share);
+        rest -= gbits[j];
+    }
+    if (rest > 0) {  // give the remainder to groups with spare capacity
+        for (int j = 0; j < K && rest > 0; ++j) {
+            const int cap = j == 0 ? m : m - c_min;
+            const int add = std::min(cap - gbits[j], rest);
+            gbits[j] += add;
+            rest -= add;
+        }
+    }
+    int b = 0;
+    for (int j = 0; j < K; ++j) {
+        GroupGeom &g = P.geom[j];
+        if (gbits[j] < P.R) return fail(Z2H_ERR_UNSUPPORTED, "group of %d bits below R = %d", gbits[j], P.R);
+        if (j == 0) {
+            g.m = std::max(gbits[0], std::min(m_pref, n));
+            g.c = 0;
+            g.b0 = 0;
+            g.x0 = 0;
+            g.x1 = gbits[0];
+        } else {
+            const int c = std::min(b, std::max(c_min, m_pref - gbits[j]));
+            g.c = c;
+            g.b0 = b;
+            g.m = c + gbits[j];
+            g.x0 = c;
+            g.x1 = c + gbits[j];
+        }
+        g.tiles_log2 = n - g.m;
+        plan_layouts(g, P.R);
+        b += gbits[j];
+    }
+    return Z2H_OK;
+}
+
+static size_t lds_bytes(const Plan &P, const GroupGeom &g, int R) {
+    const size_t elems = ((size_t)1 << g.m) + ((size_t)1 << (g.m - R));
+    size_t b = elems * P.esize;
+    b += (size_t)(P.nst + 1) * (P.n + 1) * P.esize;  // phase table
+    b = (b + 15) & ~(size_t)15;
+    b += (size_t)(P.nst + 1 + P.n + 1) * 16;         // FP64 factors
+    b += 16 * sizeof(double);                        // block reduction
+    return b;
+}
+
+static size_t obs_lds_bytes(const Plan &P, const GroupGeom &g, int R) {
+    const size_t elems = ((size_t)1 << g.m) + ((size_t)1 << (g.m - R));
+    return ((elems * P.esize + 15) & ~(size_t)15) + 16 * sizeof(double);
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+static const int kObsWorkersMax = 1024;
+
+static int obs_workers(const GroupGeom &g) {
+    const uint64_t tiles = 1ull << g.tiles_log2;
+    return (int)std::min<uint64_t>(tiles, kObsWorkersMax);
+}
+
+struct z2h_plan {
+    Plan P;
+};
+
+// ------------------------------------------------------------------ timing
+
+namespace {
+struct TimedLaunch {
+    hipEvent_t a, b;
+    int kind;
+};
+thread_local bool t_timing = false;
+thread_local std::vector<TimedLaunch> t_launches;
+thread_local std::vector<hipEvent_t> t_pool;
+
+hipEvent_t get_event() {
+    if (!t_pool.empty()) {
+        hipEvent_t e = t_pool.back();
+        t_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+}  // namespace
+
+// ------------------------------------------------------------------ launch sequences
+
+static z2h_status validate_state_ptr(const void *p, const char *what) {
+    if (!p) return fail(Z2H_ERR_INVALID, "%s is NULL", what);
+    if ((uintptr_t)p & 255) return fail(Z2H_ERR_INVALID, "%s is not 256-byte aligned", what);
+    return Z2H_OK;
+}
+
+static z2h_status validate_schedule(const Plan &P, const z2h_schedule *s) {
+    if (!s) return fail(Z2H_ERR_INVALID, "schedule is NULL");
+    if (s->steps < 0 || s->steps > (1ll << 30)) return fail(Z2H_ERR_INVALID, "steps = %lld out of range", (long long)s->steps);
+    if (!std::isfinite(s->dt)) return fail(Z2H_ERR_INVALID, "dt is not finite");
+    if (s->k_begin < 0 || s->k_end < s->k_begin || s->k_end > s->steps)
+        return fail(Z2H_ERR_INVALID, "step range [%lld, %lld) not inside [0, %lld)", (long long)s->k_begin,
+                    (long long)s->k_end, (long long)s->steps);
+    if (s->sampling != 0 && s->sampling != 1) return fail(Z2H_ERR_INVALID, "sampling must be 0 or 1");
+    if (s->order != 0 && s->order != 1) return fail(Z2H_ERR_INVALID, "order must be 0 or 1");
+    const double *c[2] = {&s->start.JA, &s->end.JA};
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 4; ++j)
+            if (!std::isfinite(c[i][j])) return fail(Z2H_ERR_INVALID, "coupling not finite");
+    (void)P;
+    return Z2H_OK;
+}
+
+static JobDev make_job(const z2h_schedule *s, uint64_t offset) {
+    JobDev J;
+    memset(&J, 0, sizeof J);
+    J.offset = offset;
+    J.steps = (int32_t)(s->k_end - s->k_begin);
+    J.k_begin = (int32_t)s->k_begin;
+    J.M = (int32_t)s->steps;
+    J.sampling = s->sampling;
+    J.order = s->order;
+    J.renorm = s->renorm;
+    J.dt = s->dt;
+    const double *a = &s->start.JA, *b = &s->end.JA;
+    for (int j = 0; j < 4; ++j) {
+        J.c0[j] = a[j];
+        J.c1[j] = b[j];
+    }
+    return J;
+}
+
+static int pass_kind_of(const LevelOp &op) {
+    if (op.kind == kPlainH) return 2;
+    if (op.kind == kIdle) return 3;
+    return op.basis == 0 ? 0 : 1;
+}
+
+// The jobs of one launch sequence: a device array (batches) or one inline
+// record carried in the kernel argument block (single state).
+struct JobSet {
+    const JobDev *d_jobs;   // device array or null
+    JobDev inl;             // used when d_jobs is null
+    const JobDev *h_jobs;   // host copies (step counts, order)
+    int njobs;
+};
+
+static void timed_begin(hipStream_t s, hipEvent_t &e0, hipEvent_t &e1) {
+    e0 = e1 = nullptr;
+    if (!t_timing) return;
+    e0 = get_event();
+    e1 = get_event();
+    if (e0) (void)hipEventRecord(e0, s);
+}
+
+static void timed_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int kind) {
+    if (!t_timing || !e0 || !e1) return;
+    (void)hipEventRecord(e1, s);
+    t_launches.push_back({e0, e1, kind});
+}
+
+// Launch one level for the jobs of J (all on the lattice of plan P).
+static z2h_status launch_one_level(const Plan &P, void *states, const JobSet &J, int lev, int group,
+                                   int rn_parts, bool force_plain, int kind, hipStream_t s) {
+    LevelArgs a;
+    memset(&a, 0, sizeof a);
+    a.states = states;
+    a.jobs = J.d_jobs;
+    a.job_inline = J.inl;
+    a.geom = P.geom[group];
+    a.lat = P.lat;
+    a.level = lev;
+    a.K = P.K;
+    a.group = group;
+    a.rn_parts = rn_parts;
+    a.force_plain = force_plain ? 1 : 0;
+    const uint64_t nblocks = (uint64_t)J.njobs << a.geom.tiles_log2;
+    if (nblocks > 0x7fffffffull) return fail(Z2H_ERR_UNSUPPORTED, "grid of %llu blocks", (unsigned long long)nblocks);
+    const size_t lds = lds_bytes(P, a.geom, P.R);
+    hipEvent_t e0, e1;
+    timed_begin(s, e0, e1);
+    hipError_t e = launch_level(P.c128, P.R, a, (unsigned)nblocks, lds, s);
+    if (e != hipSuccess) return fail(Z2H_ERR_HIP, "level kernel launch failed: %s", hipGetErrorString(e));
+    timed_end(s, e0, e1, kind);
+    return Z2H_OK;
+}
+
+// Unnormalized Walsh-Hadamard transform of every group (psi_1' preparation).
+static z2h_status full_transform(const Plan &P, void *states, const JobSet &J, hipStream_t s) {
+    for (int gidx = 0; gidx < P.K; ++gidx) {
+        z2h_status st = launch_one_level(P, states, J, 0, gidx, 0, true, 2, s);
+        if (st) return st;
+    }
+    return Z2H_OK;
+}
+
+// Evolve the states of J through their level sequences.
+static z2h_status run_levels(const Plan &P, void *states, const JobSet &J, hipStream_t s) {
+    int maxS = 0;
+    bool any0 = false;
+    for (int j = 0; j < J.njobs; ++j) {
+        maxS = std::max(maxS, J.h_jobs[j].steps);
+        if (J.h_jobs[j].order == 0) any0 = true;
+    }
+    if (maxS == 0) return Z2H_OK;
+    if (P.K == 1) {
+        ResidentArgs a;
+        memset(&a, 0, sizeof a);
+        a.states = states;
+        a.jobs = J.d_jobs;
+        a.job_inline = J.inl;
+        a.geom = P.geom[0];
+        a.lat = P.lat;
+        a.job0 = 0;
+        hipEvent_t e0, e1;
+        timed_begin(s, e0, e1);
+        hipError_t e = launch_resident(P.c128, P.R, a, (unsigned)J.njobs, lds_bytes(P, a.geom, P.R), s);
+        if (e != hipSuccess) return fail(Z2H_ERR_HIP, "resident kernel launch failed: %s", hipGetErrorString(e));
+        timed_end(s, e0, e1, 3);
+        return Z2H_OK;
+    }
+    const int Pp = 2 * (P.K - 1);
+    const int nlev = any0 ? Pp * (maxS + 1) + 1 : Pp * maxS + 1;
+    const int parts0 = 1 << P.geom[0].tiles_log2;
+    const bool big_parts = parts0 > 1024;
+    for (int lev = 0; lev < nlev; ++lev) {
+        // the visited group is the same for every job; the kind may differ
+        LevelOp op{};
+        bool any_norm = false;
+        for (int j = 0; j < J.njobs; ++j) {
+            LevelOp o = level_op_host(lev, P.K, J.h_jobs[j].steps, J.h_jobs[j].k_begin, J.h_jobs[j].order);
+            if (o.kind != kIdle) {
+                if (op.kind == kIdle) op = o;
+                any_norm = any_norm || o.norm;
+            }
+        }
+        if (op.kind == kIdle) continue;
+        z2h_status st = launch_one_level(P, states, J, lev, op.group, big_parts ? 1 : parts0, false,
+                                         pass_kind_of(op), s);
+        if (st) return st;
+        if (big_parts && any_norm) {
+            hipError_t e = launch_reduce_parts(J.d_jobs, J.inl, J.njobs, parts0, s);
+            if (e != hipSuccess) return fail(Z2H_ERR_HIP, "reduce kernel launch failed: %s", hipGetErrorString(e));
+        }
+    }
+    return Z2H_OK;
+}
+
+// Observables of njobs states; records and outputs in device memory.
+struct ObsBuffers {
+    void *scratch;                      // transformed copies (K > 1)
+    const uint64_t *src_off, *dst_off;  // device arrays or null (single state at offset 0)
+    double *partZ, *partX;              // njobs * workers * kObsQ
+    const double *H;                    // njobs * 4 (device) or null: H_inline
+    double H_inline[4];
+    double *out;                        // njobs * kObsQ
+};
+
+static z2h_status run_observe(const Plan &P, const void *states, int njobs, const ObsBuffers &B,
+                              const uint32_t *zl, int nz, const uint32_t *xl, int nx, hipStream_t s) {
+    ObsArgs a;
+    memset(&a, 0, sizeof a);
+    a.lat = P.lat;
+    for (int j = 0; j < nz; ++j) a.zloops[j] = zl[j];
+    for (int j = 0; j < nx; ++j) a.xloops[j] = xl[j];
+    a.nz = nz;
+    a.nx = nx;
+    int wZ = 0, wX = 0;
+    for (int gi = 0; gi < P.K; ++gi) {
+        a.geom = P.geom[gi];
+        const int w = obs_workers(a.geom);
+        a.src = gi == 0 ? states : B.scratch;
+        a.src_off = gi == 0 ? B.src_off : B.dst_off;
+        a.dst = gi == P.K - 1 ? nullptr : B.scratch;
+        a.dst_off = B.dst_off;
+        a.redZ = gi == 0;
+        a.doH = 1;
+        a.redX = gi == P.K - 1;
+        a.part_z = gi == 0 ? B.partZ : nullptr;
+        a.part_x = gi == P.K - 1 ? B.partX : nullptr;
+        if (gi == 0) wZ = w;
+        if (gi == P.K - 1) wX = w;
+        hipError_t e = launch_obs(P.c128, P.R, a, w, njobs, obs_lds_bytes(P, a.geom, P.R), s);
+        if (e != hipSuccess) return fail(Z2H_ERR_HIP, "observe kernel failed: %s", hipGetErrorString(e));
+    }
+    FinalArgs f;
+    memset(&f, 0, sizeof f);
+    f.partZ = B.partZ;
+    f.partX = B.partX;
+    f.nrecZ = wZ;
+    f.nrecX = wX;
+    f.n = P.n;
+    f.H = B.H;
+    for (int j = 0; j < 4; ++j) f.H_inline[j] = B.H_inline[j];
+    f.out = B.out;
+    hipError_t e = launch_obs_finalize(f, njobs, s);
+    if (e != hipSuccess) return fail(Z2H_ERR_HIP, "observe finalize failed: %s", hipGetErrorString(e));
+    return Z2H_OK;
+}
+
+// Workspace carve-up (256-byte aligned pieces).
+struct Carver {
+    char *base;
+    size_t off;
+    void *take(size_t bytes) {
+        off = align256(off);
+        void *p = base ? base + off : nullptr;
+        off += bytes;
+        return p;
+    }
+};
+
+static size_t obs_records(const Plan &P) {
+    return (size_t)obs_workers(P.geom[0]) + (size_t)obs_workers(P.geom[P.K - 1]);
+}
+
+static size_t norm_parts(const Plan &P) { return (size_t)1 << P.geom[0].tiles_log2; }
+
+static size_t ws_evolve_size(const Plan &P) {
+    Carver c{nullptr, 0};
+    c.take(sizeof(double) * norm_parts(P));
+    return align256(c.off);
+}
+
+static size_t ws_observe_size(const Plan &P) {
+    Carver c{nullptr, 0};
+    if (P.K > 1) c.take(P.esize << P.n);
+    c.take(sizeof(double) * kObsQ * obs_records(P));
+    c.take(sizeof(double) * kObsQ);
+    return align256(c.off);
+}
+
+// ------------------------------------------------------------------ C ABI
+
+static z2h_status check_device(const Plan &P) {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return fail(Z2H_ERR_HIP, "no HIP device");
+    if (P.device >= 0 && dev != P.device)
+        return fail(Z2H_ERR_INVALID, "current device %d differs from the plan's device %d", dev, P.device);
+    return Z2H_OK;
+}
+
+extern "C" {
+
+const char *z2h_version(void) { return "z2h 0.1 (gfx950)"; }
+
+const char *z2h_last_error(void) { return g_err.c_str(); }
+
+z2h_status z2h_link_bit(int32_t Lx, int32_t Ly, int32_t x, int32_t y, int32_t dir, int32_t *bit) {
+    z2h_status st = check_lattice(Lx, Ly);
+    if (st) return st;
+    if (!bit) return fail(Z2H_ERR_INVALID, "bit is NULL");
+    if (dir != 0 && dir != 1) return fail(Z2H_ERR_INVALID, "dir must be 0 or 1");
+    *bit = link_bit(Lx, Ly, x, y, dir);
+    return Z2H_OK;
+}
+
+z2h_status z2h_masks(int32_t Lx, int32_t Ly, uint64_t *stars, uint64_t *plaqs) {
+    z2h_status st = check_lattice(Lx, Ly);
+    if (st) return st;
+    if (!stars || !plaqs) return fail(Z2H_ERR_INVALID, "mask arrays are NULL");
+    build_masks(Lx, Ly, stars, plaqs);
+    return Z2H_OK;
+}
+
+z2h_status z2h_plan_create(int32_t Lx, int32_t Ly, z2h_dtype dtype, int32_t max_tile_bits, z2h_plan **out) {
+    try {
+        if (!out) return fail(Z2H_ERR_INVALID, "out is NULL");
+        *out = nullptr;
+        if (dtype != Z2H_C64 && dtype != Z2H_C128) return fail(Z2H_ERR_INVALID, "bad dtype %d", dtype);
+        z2h_plan *p = new (std::nothrow) z2h_plan;
+        if (!p) return fail(Z2H_ERR_OOM, "out of host memory");
+        z2h_status st = make_plan(Lx, Ly, dtype == Z2H_C128, max_tile_bits, p->P);
+        if (st) {
+            delete p;
+            return st;
+        }
+        p->P.device = -1;
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) == hipSuccess && ndev > 0) {
+            int dev = 0;
+            if (hipGetDevice(&dev) == hipSuccess) p->P.device = dev;
+        }
+        *out = p;
+        return Z2H_OK;
+    } catch (...) {
+        return fail(Z2H_ERR_OOM, "exception in plan creation");
+    }
+}
+
+void z2h_plan_destroy(z2h_plan *plan) { delete plan; }
+
+z2h_status z2h_plan_sizes(const z2h_plan *plan, size_t *state_bytes, size_t *ws_evolve_bytes,
+                          size_t *ws_observe_bytes, size_t *ws_adjoint_bytes) {
+    if (!plan) return fail(Z2H_ERR_INVALID, "plan is NULL");
+    const Plan &P = plan->P;
+    if (state_bytes) *state_bytes = P.esize << P.n;
+    if (ws_evolve_bytes) *ws_evolve_bytes = ws_evolve_size(P);
+    if (ws_observe_bytes) *ws_observe_bytes = ws_observe_size(P);
+    if (ws_adjoint_bytes) *ws_adjoint_bytes = 0;
+    return Z2H_OK;
+}
+
+z2h_status z2h_plan_info(const z2h_plan *plan, int32_t *n, int32_t *groups, int32_t *passes_per_step,
+                         int32_t *tile_bits) {
+    if (!plan) return fail(Z2H_ERR_INVALID, "plan is NULL");
+    const Plan &P = plan->P;
+    if (n) *n = P.n;
+    if (groups) *groups = P.K;
+    if (passes_per_step) *passes_per_step = P.K == 1 ? 0 : 2 * (P.K - 1);
+    if (tile_bits) *tile_bits = P.geom[0].m;
+    return Z2H_OK;
+}
+
+z2h_status z2h_plan_describe(const z2h_plan *plan, char *buf, size_t len) {
+    if (!plan || !buf || len == 0) return fail(Z2H_ERR_INVALID, "NULL argument");
+    const Plan &P = plan->P;
+    std::string s = "{\"n\": " + std::to_string(P.n) + ", \"R\": " + std::to_string(P.R) +
+                    ", \"K\": " + std::to_string(P.K) + ", \"c128\": " + (P.c128 ? "1" : "0") + ", \"groups\": [";
+    for (int j = 0; j < P.K; ++j) {
+        const GroupGeom &g = P.geom[j];
+        s += j ? ", " : "";
+        s += "{\"m\": " + std::to_string(g.m) + ", \"c\": " + std::to_string(g.c) +
+             ", \"b0\": " + std::to_string(g.b0) + ", \"x0\": " + std::to_string(g.x0) +
+             ", \"x1\": " + std::to_string(g.x1) + ", \"tiles_log2\": " + std::to_string(g.tiles_log2) +
+             ", \"p\": [";
+        for (int l = 0; l < g.nlay; ++l) s += (l ? ", " : "") + std::to_string(g.p[l]);
+        s += "], \"blo\": [";
+        for (int l = 0; l < g.nlay; ++l) s += (l ? ", " : "") + std::to_string(g.blo[l]);
+        s += "], \"bhi\": [";
+        for (int l = 0; l < g.nlay; ++l) s += (l ? ", " : "") + std::to_string(g.bhi[l]);
+        s += "], \"lds_bytes\": " + std::to_string(lds_bytes(P, g, P.R)) + "}";
+    }
+    s += "]}";
+    if (s.size() + 1 > len) return fail(Z2H_ERR_INVALID, "buffer of %zu bytes, %zu needed", len, s.size() + 1);
+    memcpy(buf, s.c_str(), s.size() + 1);
+    return Z2H_OK;
+}
+
+z2h_status z2h_state_init(const z2h_plan *plan, void *d_state, z2h_init kind, void *stream) {
+    if (!plan) return fail(Z2H_ERR_INVALID, "plan is NULL");
+    z2h_status st = validate_state_ptr(d_state, "d_state");
+    if (st) return st;
+    if (kind < Z2H_INIT_PSI1 || kind > Z2H_INIT_PLUS) return fail(Z2H_ERR_INVALID, "bad init kind %d", kind);
+    const Plan &P = plan->P;
+    if ((st = check_device(P))) return st;
+    hipStream_t s = (hipStream_t)stream;
+    InitArgs a;
+    memset(&a, 0, sizeof a);
+    a.states = d_state;
+    a.offset = 0;
+    a.lat = P.lat;
+    a.kind = kind;
+    // Eq. (ini1)/(ini2): equal weight on the 2^(n - Np + 1) configurations
+    // with every plaquette (star) even.
+    const double even = 1.0 / std::sqrt(std::ldexp(1.0, P.n - P.nst + 1));
+    if (kind == Z2H_INIT_PSI1) a.amp = even;
+    if (kind == Z2H_INIT_PSI1P) a.amp = even * std::ldexp(1.0, -P.n / 2);  // n is even
+    if (kind == Z2H_INIT_PLUS) a.amp = std::ldexp(1.0, -P.n / 2);
+    hipError_t e = launch_init(P.c128, a, s);
+    if (e != hipSuccess) return fail(Z2H_ERR_HIP, "init kernel failed: %s", hipGetErrorString(e));
+    if (kind == Z2H_INIT_PSI1P) {
+        // psi_1' = H^n (star-even superposition in the Hadamard basis)
+        JobSet J;
+        memset(&J, 0, sizeof J);
+        J.njobs = 1;
+        return full_transform(P, d_state, J, s);
+    }
+    return Z2H_OK;
+}
+
+z2h_status z2h_evolve(const z2h_plan *plan, void *d_state, void *d_ws, size_t ws_bytes,
+                      const z2h_schedule *sched, double *d_norms, void *stream) {
+    try {
+        if (!plan) return fail(Z2H_ERR_INVALID, "plan is NULL");
+        const Plan &P = plan->P;
+        z2h_status st = validate_state_ptr(d_state, "d_state");
+        if (st) return st;
+        if ((st = validate_schedule(P, sched))) return st;
+        if (!d_ws) return fail(Z2H_ERR_INVALID, "d_ws is NULL");
+        const bool arrays = sched->sZ || sched->sX;
+        size_t need = ws_evolve_size(P);
+        if (arrays) need += align256(sizeof(double) * 2 * (size_t)sched->steps) + 256;
+        if (ws_bytes < need)
+            return fail(Z2H_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+        if (arrays) {
+            for (int64_t k = 0; k < sched->steps; ++k) {
+                if ((sched->sZ && !std::isfinite(sched->sZ[k])) || (sched->sX && !std::isfinite(sched->sX[k])))
+                    return fail(Z2H_ERR_INVALID, "schedule value at step %lld not finite", (long long)k);
+            }
+        }
+        if ((st = check_device(P))) return st;
+        hipStream_t s = (hipStream_t)stream;
+        Carver c{(char *)d_ws, 0};
+        JobSet J;
+        memset(&J, 0, sizeof J);
+        J.inl = make_job(sched, 0);
+        J.inl.norm_part = (double *)c.take(sizeof(double) * norm_parts(P));
+        J.inl.norm_trace = d_norms;
+        if (arrays) {
+            double *dz = (double *)c.take(sizeof(double) * sched->steps);
+            double *dx = (double *)c.take(sizeof(double) * sched->steps);
+            if (sched->sZ) HIP_TRY(hipMemcpyAsync(dz, sched->sZ, sizeof(double) * sched->steps, hipMemcpyHostToDevice, s));
+            if (sched->sX) HIP_TRY(hipMemcpyAsync(dx, sched->sX, sizeof(double) * sched->steps, hipMemcpyHostToDevice, s));
+            // the host arrays may be reused as soon as this call returns
+            HIP_TRY(hipStreamSynchronize(s));
+            J.inl.sZ = sched->sZ ? dz : nullptr;
+            J.inl.sX = sched->sX ? dx : nullptr;
+        }
+        J.h_jobs = &J.inl;
+        J.njobs = 1;
+        return run_levels(P, d_state, J, s);
+    } catch (...) {
+        return fail(Z2H_ERR_OOM, "exception in z2h_evolve");
+    }
+}
+
+static z2h_status check_loop_masks(const Plan &P, const uint64_t *m, int32_t cnt, const char *what,
+                                   uint32_t *out) {
+    if (cnt < 0 || cnt > Z2H_MAX_LOOPS) return fail(Z2H_ERR_INVALID, "%s count %d outside [0, %d]", what, cnt, Z2H_MAX_LOOPS);
+    if (cnt && !m) return fail(Z2H_ERR_INVALID, "%s is NULL", what);
+    for (int j = 0; j < cnt; ++j) {
+        if (P.n < 64 && (m[j] >> P.n)) return fail(Z2H_ERR_INVALID, "%s[%d] has bits >= n", what, j);
+        out[j] = (uint32_t)m[j];
+    }
+    return Z2H_OK;
+}
+
+z2h_status z2h_observe(const z2h_plan *plan, const void *d_state, void *d_ws, size_t ws_bytes,
+                       const z2h_couplings *H, const uint64_t *zmasks, int32_t nz, const uint64_t *xmasks,
+                       int32_t nx, z2h_obs *h_out, double *d_out, void *stream) {
+    try {
+        if (!plan) return fail(Z2H_ERR_INVALID, "plan is NULL");
+        const Plan &P = plan->P;
+        z2h_status st = validate_state_ptr(d_state, "d_state");
+        if (st) return st;
+        if (!H) return fail(Z2H_ERR_INVALID, "H is NULL");
+        if (!d_ws) return fail(Z2H_ERR_INVALID, "d_ws is NULL");
+        if (!h_out && !d_out) return fail(Z2H_ERR_INVALID, "no output requested");
+        uint32_t zl[Z2H_MAX_LOOPS], xl[Z2H_MAX_LOOPS];
+        if ((st = check_loop_masks(P, zmasks, nz, "zmasks", zl))) return st;
+        if ((st = check_loop_masks(P, xmasks, nx, "xmasks", xl))) return st;
+        const size_t need = ws_observe_size(P);
+        if (ws_bytes < need) return fail(Z2H_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+        if ((st = check_device(P))) return st;
+        hipStream_t s = (hipStream_t)stream;
+        Carver c{(char *)d_ws, 0};
+        ObsBuffers B;
+        memset(&B, 0, sizeof B);
+        if (P.K > 1) B.scratch = c.take(P.esize << P.n);
+        const size_t wz = obs_workers(P.geom[0]);
+        double *parts = (double *)c.take(sizeof(double) * kObsQ * obs_records(P));
+        B.partZ = parts;
+        B.partX = parts + wz * kObsQ;
+        double *outbuf = (double *)c.take(sizeof(double) * kObsQ);
+        B.out = d_out ? d_out : outbuf;
+        B.H_inline[0] = H->JA;
+        B.H_inline[1] = H->JB;
+        B.H_inline[2] = H->hx;
+        B.H_inline[3] = H->hz;
+        if ((st = run_observe(P, d_state, 1, B, zl, nz, xl, nx, s))) return st;
+        if (h_out) {
+            double tmp[kObsQ];
+            HIP_TRY(hipMemcpyAsync(tmp, B.out, sizeof tmp, hipMemcpyDeviceToHost, s));
+            HIP_TRY(hipStreamSynchronize(s));
+            memcpy(h_out, tmp, sizeof(z2h_obs));
+            if (!std::isfinite(h_out->norm) || !std::isfinite(h_out->energy))
+                return fail(Z2H_ERR_NUMERIC, "non-finite norm (%g) or energy (%g)", h_out->norm, h_out->energy);
+        }
+        return Z2H_OK;
+    } catch (...) {
+        return fail(Z2H_ERR_OOM, "exception in z2h_observe");
+    }
+}
+
+z2h_status z2h_timing_enable(int32_t on) {
+    t_timing = on != 0;
+    return Z2H_OK;
+}
+
+z2h_status z2h_timing_read(int64_t counts[4], double ms[4]) {
+    if (!counts || !ms) return fail(Z2H_ERR_INVALID, "NULL output");
+    for (int k = 0; k < 4; ++k) {
+        counts[k] = 0;
+        ms[k] = 0;
+    }
+    z2h_status st = Z2H_OK;
+    for (auto &L : t_launches) {
+        float x = 0;
+        if (hipEventSynchronize(L.b) != hipSuccess || hipEventElapsedTime(&x, L.a, L.b) != hipSuccess)
+            st = fail(Z2H_ERR_HIP, "event timing failed");
+        counts[L.kind] += 1;
+        ms[L.kind] += x;
+        t_pool.push_back(L.a);
+        t_pool.push_back(L.b);
+    }
+    t_launches.clear();
+    return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,766 @@
+// Device kernels of libz2h: the Trotter step of Sec. III as diagonal phase
+// passes around an in-place Walsh-Hadamard transform, for gfx950.
+//
+// A tile of 2^m complex amplitudes is held by 2^(m-R) threads, 2^R amplitudes
+// per thread in registers.  Butterflies over the register bits need no
+// communication; the other bits of the tile are brought into registers by an
+// exchange through LDS ("layout" change).  Global memory is touched once per
+// pass: one coalesced load and one coalesced store of the tile.
+//
+// The diagonal factors of Eq. (decom) are applied as a table lookup: in the
+// computational basis the phase of basis state i depends only on the number
+// of odd plaquettes k(i) and the Hamming weight w(i); in the Hadamard basis
+// the same holds for stars.  The (k, w) table is built in FP64 by every
+// workgroup from the couplings of its step and cast to the storage type.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "z2h_internal.h"
+#include "z2h_kernels.h"
+
+namespace z2h {
+
+template <typename Real>
+struct __attribute__((aligned(2 * sizeof(Real)))) Cx {
+    Real x, y;
+};
+
+template <typename Real>
+__device__ __forceinline__ Cx<Real> cadd(Cx<Real> a, Cx<Real> b) { return {a.x + b.x, a.y + b.y}; }
+template <typename Real>
+__device__ __forceinline__ Cx<Real> csub(Cx<Real> a, Cx<Real> b) { return {a.x - b.x, a.y - b.y}; }
+template <typename Real>
+__device__ __forceinline__ Cx<Real> cmul(Cx<Real> a, Cx<Real> b) {
+    return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+
+__device__ __forceinline__ int popc(uint32_t v) { return __builtin_popcount(v); }
+
+// Next 16-byte boundary at or after p (LDS sub-buffers; the host sizes the
+// dynamic LDS block with the same rounding).
+template <typename T, typename U>
+__device__ __forceinline__ T *align16(U *p) {
+    return reinterpret_cast<T *>((reinterpret_cast<uintptr_t>(p) + 15) & ~(uintptr_t)15);
+}
+
+// Local index of register element q of thread t in layout p.
+template <int R>
+__device__ __forceinline__ uint32_t lay_base(int p, uint32_t t) {
+    return (t & ((1u << p) - 1u)) | ((t >> p) << (p + R));
+}
+
+// LDS slot of local index e: one pad element every 2^R elements keeps every
+// layout's accesses free of bank conflicts.
+template <int R>
+__device__ __forceinline__ uint32_t slot(uint32_t e) { return e + (e >> R); }
+
+// Global index (within the state) of local index e of tile "tile".
+__device__ __forceinline__ uint64_t glob(const GroupGeom &g, uint64_t tile, uint32_t e) {
+    const uint32_t cm = (1u << g.c) - 1u;
+    const int tlo_bits = g.b0 - g.c;
+    const uint64_t tlo = tile & ((1ull << tlo_bits) - 1ull);
+    const uint64_t thi = tile >> tlo_bits;
+    return (uint64_t)(e & cm) | (tlo << g.c) | ((uint64_t)(e >> g.c) << g.b0) |
+           (thi << (g.b0 + g.m - g.c));
+}
+
+// Global bit position of local bit x.
+__device__ __forceinline__ int gbit(const GroupGeom &g, int x) { return x < g.c ? x : g.b0 + (x - g.c); }
+
+template <typename Real, int R>
+__device__ __forceinline__ void butterflies(Cx<Real> (&v)[1 << R], int blo, int bhi) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+        if (j >= blo && j < bhi) {
+#pragma unroll
+            for (int q = 0; q < (1 << R); ++q) {
+                if (!(q & (1 << j))) {
+                    Cx<Real> a = v[q], b = v[q | (1 << j)];
+                    v[q] = cadd(a, b);
+                    v[q | (1 << j)] = csub(a, b);
+                }
+            }
+        }
+    }
+}
+
+template <typename Real, int R>
+__device__ __forceinline__ void exchange(Cx<Real> (&v)[1 << R], Cx<Real> *lds, int pf, int pt,
+                                         uint32_t t) {
+    const uint32_t bf = lay_base<R>(pf, t), bt = lay_base<R>(pt, t);
+#pragma unroll
+    for (int q = 0; q < (1 << R); ++q) {
+        uint32_t e = bf | ((uint32_t)q << pf);
+        lds[slot<R>(e)] = v[q];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < (1 << R); ++q) {
+        uint32_t e = bt | ((uint32_t)q << pt);
+        v[q] = lds[slot<R>(e)];
+    }
+    __syncthreads();
+}
+
+// Per-thread constants of one layout.  The register bits of a layout are
+// global bits [gs, gs + R) (the planner never lets a layout straddle the
+// carried/transformed boundary), so register element q sits at global index
+// i0 + (q << gs).  s0z/s0x are the plaquette/star syndromes of i0 and lz/lx
+// the syndrome columns of the R register bits (uniform across the block).
+template <int R>
+struct LayCtx {
+    uint64_t i0;
+    int gs, w0;
+    uint32_t s0z, s0x;
+    uint32_t lz[R], lx[R];
+};
+
+__device__ __forceinline__ uint32_t syndrome_direct(const uint32_t *masks, int nst, uint64_t i) {
+    uint32_t s = 0;
+    const uint32_t ii = (uint32_t)i;
+    for (int k = 0; k < nst; ++k) s |= (uint32_t)(popc(ii & masks[k]) & 1) << k;
+    return s;
+}
+
+template <int R>
+__device__ __forceinline__ void lay_ctx(LayCtx<R> &L, const GroupGeom &g, const LatticeDev &lat,
+                                        uint64_t tile, int p, uint32_t t, bool want_syn) {
+    L.i0 = glob(g, tile, lay_base<R>(p, t));
+    L.gs = gbit(g, p);
+    L.w0 = __builtin_popcountll(L.i0);
+    if (want_syn) {
+        L.s0z = syndrome_direct(lat.zmask, lat.nst, L.i0);
+        L.s0x = syndrome_direct(lat.xmask, lat.nst, L.i0);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            L.lz[r] = lat.zsyn[L.gs + r];
+            L.lx[r] = lat.xsyn[L.gs + r];
+        }
+    }
+}
+
+template <typename Real, int R>
+__device__ __forceinline__ void load_tile(Cx<Real> (&v)[1 << R], const Cx<Real> *st,
+                                          const LayCtx<R> &L) {
+    const Cx<Real> *b = st + L.i0;
+#pragma unroll
+    for (int q = 0; q < (1 << R); ++q) v[q] = b[(uint64_t)q << L.gs];
+}
+
+// The base index is passed through an empty asm statement so that the
+// compiler recomputes the 2^R store addresses instead of keeping the load
+// addresses alive through the whole pass (2 VGPRs each).
+template <typename Real, int R>
+__device__ __forceinline__ void store_tile(const Cx<Real> (&v)[1 << R], Cx<Real> *st,
+                                           const LayCtx<R> &L) {
+    uint64_t i0 = L.i0;
+    asm volatile("" : "+v"(i0));
+    Cx<Real> *b = st + i0;
+#pragma unroll
+    for (int q = 0; q < (1 << R); ++q) b[(uint64_t)q << L.gs] = v[q];
+}
+
+// Build the phase table T[k][w] = scale * exp(i (alpha (nst - 2k) + beta (n - 2w)))
+// in LDS (FP64 angles and products, cast to Real).
+template <typename Real>
+__device__ void build_table(Cx<Real> *tab, double2 *fac, int nst, int n, double alpha,
+                            double beta, double scale) {
+    const int t = threadIdx.x, nt = blockDim.x;
+    for (int j = t; j < nst + 1 + n + 1; j += nt) {
+        double ang = j <= nst ? alpha * (double)(nst - 2 * j) : beta * (double)(n - 2 * (j - nst - 1));
+        double s, c;
+        sincos(ang, &s, &c);
+        fac[j] = make_double2(c, s);
+    }
+    __syncthreads();
+    const int W = n + 1;
+    for (int j = t; j < (nst + 1) * W; j += nt) {
+        const int k = j / W, w = j - k * W;
+        const double2 a = fac[k], b = fac[nst + 1 + w];
+        const double re = (a.x * b.x - a.y * b.y) * scale;
+        const double im = (a.x * b.y + a.y * b.x) * scale;
+        tab[j] = Cx<Real>{(Real)re, (Real)im};
+    }
+    __syncthreads();
+}
+
+// Multiply every register element by T[k][w]: elements are visited in
+// Gray-code order so each step updates the syndrome by one uniform column.
+template <typename Real, int R>
+__device__ __forceinline__ void apply_phase(Cx<Real> (&v)[1 << R], const LayCtx<R> &L, int basis,
+                                            int n, const Cx<Real> *tab) {
+    uint32_t s = basis ? L.s0x : L.s0z;
+    const Cx<Real> *tw = tab + L.w0;
+    const int W = n + 1;
+#pragma unroll
+    for (int idx = 0; idx < (1 << R); ++idx) {
+        const int q = idx ^ (idx >> 1);
+        if (idx) s ^= basis ? L.lx[__builtin_ctz(idx)] : L.lz[__builtin_ctz(idx)];
+        v[q] = cmul(v[q], tw[popc(s) * W + __builtin_popcount(q)]);
+    }
+}
+
+template <typename Real, int R>
+__device__ __forceinline__ double sumsq(const Cx<Real> (&v)[1 << R]) {
+    double acc = 0.0;
+#pragma unroll
+    for (int q = 0; q < (1 << R); ++q) {
+        const Real a = v[q].x * v[q].x + v[q].y * v[q].y;
+        acc += (double)a;
+    }
+    return acc;
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+// Deterministic block sum; every thread gets the result.
+__device__ double block_sum(double x, double *red) {
+    x = wave_sum(x);
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
+    __syncthreads();
+    if (lane == 0) red[wv] = x;
+    __syncthreads();
+    double s = 0.0;
+    for (int j = 0; j < nw; ++j) s += red[j];
+    __syncthreads();
+    return s;
+}
+
+// ---------------------------------------------------------------- schedule
+
+__device__ __forceinline__ double sched_s(const JobDev &J, int k, int zkind) {
+    const double *arr = zkind ? J.sZ : J.sX;
+    if (arr) return arr[k];
+    return J.sampling ? (double)(k + 1) / (double)J.M : ((double)k + 0.5) / (double)J.M;
+}
+
+// (coupling, field) of the given basis at step k: inner (Z) basis uses
+// (JB, hz) at sZ, outer (X) basis uses (JA, hx) at sX.
+__device__ __forceinline__ void coup(const JobDev &J, int basis, int k, double &Jc, double &h) {
+    const double s = sched_s(J, k, basis == 0);
+    const int ij = basis == 0 ? 1 : 0, ih = basis == 0 ? 3 : 2;
+    Jc = (1.0 - s) * J.c0[ij] + s * J.c1[ij];
+    h = (1.0 - s) * J.c0[ih] + s * J.c1[ih];
+}
+
+// Angles of a phase pass: full step ka (duration dt) or half steps ka, kb.
+__device__ __forceinline__ void phase_angles(const JobDev &J, const LevelOp &op, double &alpha,
+                                             double &beta) {
+    double Ja, ha, Jb = 0, hb = 0;
+    coup(J, op.basis, op.ka, Ja, ha);
+    if (op.full) {
+        alpha = J.dt * Ja;
+        beta = J.dt * ha;
+        return;
+    }
+    if (op.kb >= 0) coup(J, op.basis, op.kb, Jb, hb);
+    alpha = 0.5 * J.dt * (Ja + Jb);
+    beta = 0.5 * J.dt * (ha + hb);
+}
+
+// Level sequence of one job (see the host planner for the derivation): the
+// visited group zig-zags between group 0 (computational basis reached) and
+// group K-1 (Hadamard basis reached).
+__host__ __device__ inline LevelOp level_op(int lev, int K, int S, int k0, int order) {
+    LevelOp op{0, kIdle, 0, -1, -1, 0, 0, 0};
+    const int P = 2 * (K - 1);
+    const int nlev = order == 0 ? P * (S + 1) + 1 : P * S + 1;
+    if (S <= 0 || lev < 0 || lev >= nlev) return op;
+    const int r = lev % P;
+    op.group = r <= K - 1 ? r : P - r;
+    const int j = lev / P;
+    if (op.group != 0 && op.group != K - 1) {
+        op.kind = kPlainH;
+        return op;
+    }
+    if (op.group == K - 1 && r == K - 1) {
+        // outer visit j
+        op.basis = 1;
+        if (order == 0) {
+            op.kind = kPhaseB;
+            if (j == 0) {
+                op.ka = k0; op.kb = -1; op.full = 0;
+            } else if (j == S) {
+                op.ka = k0 + S - 1; op.kb = -1; op.full = 0;
+            } else {
+                op.ka = k0 + j - 1; op.kb = k0 + j; op.full = 0;
+            }
+            op.renorm = j >= 1 ? 1 : 0;
+        } else {
+            op.kind = kPhaseB;
+            op.ka = k0 + j; op.full = 1;
+            op.renorm = 1;
+        }
+        return op;
+    }
+    // inner visit j (group 0)
+    op.basis = 0;
+    if (order == 0) {
+        if (j == 0 || j == S + 1) {
+            op.kind = kPlainH;
+        } else {
+            op.kind = kPhaseB;
+            op.ka = k0 + j - 1; op.full = 1;
+            op.norm = 1;
+        }
+    } else {
+        if (j == 0) {
+            op.kind = kHalfIn; op.ka = k0; op.kb = -1; op.full = 0; op.norm = 1;
+        } else if (j == S) {
+            op.kind = kHalfOut; op.ka = k0 + S - 1; op.kb = -1; op.full = 0;
+        } else {
+            op.kind = kPhaseB; op.ka = k0 + j - 1; op.kb = k0 + j; op.full = 0; op.norm = 1;
+        }
+    }
+    return op;
+}
+
+// ---------------------------------------------------------------- level kernel
+
+template <typename Real, int R>
+__global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const GroupGeom &g = a.geom;
+    const uint32_t t = threadIdx.x;
+    const uint64_t tiles = 1ull << g.tiles_log2;
+    const uint64_t bid = blockIdx.x;
+    const int jb = (int)(bid >> g.tiles_log2);
+    const uint64_t tile = bid & (tiles - 1);
+    const JobDev J = a.jobs ? a.jobs[jb] : a.job_inline;
+    const LevelOp op = a.force_plain ? LevelOp{a.group, kPlainH, 0, -1, -1, 0, 0, 0}
+                                     : level_op(a.level, a.K, J.steps, J.k_begin, J.order);
+    if (op.kind == kIdle || op.group != a.group) return;  // uniform per block
+
+    Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
+    const uint32_t lds_elems = (1u << g.m) + (1u << (g.m - R));
+    Cx<Real> *tab = lds + lds_elems;
+    const int W = a.lat.n + 1;
+    double2 *fac = align16<double2>(tab + (a.lat.nst + 1) * W);
+    double *red = reinterpret_cast<double *>(fac + (a.lat.nst + 1 + W));
+
+    const bool has_phase = op.kind != kPlainH;
+    const bool preH = op.kind != kHalfIn;
+    const bool postH = op.kind == kPhaseB || op.kind == kHalfIn;
+
+    // Phase table (FP64 angles), including the renormalization factor.
+    if (has_phase) {
+        double alpha, beta;
+        phase_angles(J, op, alpha, beta);
+        double scale = op.basis ? ldexp(1.0, -a.lat.n) : 1.0;
+        if (op.renorm && J.norm_part) {
+            double s = 0.0;
+            for (int j = (int)t; j < a.rn_parts; j += blockDim.x) s += J.norm_part[j];
+            s = block_sum(s, red);
+            if (J.renorm) scale *= 1.0 / sqrt(s);
+            if (tile == 0 && t == 0 && J.norm_trace) J.norm_trace[op.ka - J.k_begin] = s;
+        }
+        build_table<Real>(tab, fac, a.lat.nst, a.lat.n, alpha, beta, scale);
+    }
+
+    Cx<Real> v[1 << R];
+    Cx<Real> *st = reinterpret_cast<Cx<Real> *>(a.states) + J.offset;
+
+    LayCtx<R> L0;
+    lay_ctx<R>(L0, g, a.lat, tile, g.p[0], t, false);
+    load_tile<Real, R>(v, st, L0);
+
+    int cur = 0;
+    if (preH) {
+        for (int j = 0; j < g.nlay; ++j) {
+            if (j > 0) exchange<Real, R>(v, lds, g.p[j - 1], g.p[j], t);
+            butterflies<Real, R>(v, g.blo[j], g.bhi[j]);
+        }
+        cur = g.nlay - 1;
+    }
+    if (has_phase || op.norm) {
+        LayCtx<R> Lm;
+        lay_ctx<R>(Lm, g, a.lat, tile, g.p[cur], t, has_phase);
+        if (op.norm) {
+            double s = block_sum(sumsq<Real, R>(v), red);
+            if (t == 0 && J.norm_part) J.norm_part[tile] = s;
+        }
+        if (has_phase) apply_phase<Real, R>(v, Lm, op.basis, a.lat.n, tab);
+    }
+    if (postH) {
+        if (cur == g.nlay - 1) {
+            for (int j = g.nlay - 1; j >= 0; --j) {
+                if (j != cur) {
+                    exchange<Real, R>(v, lds, g.p[cur], g.p[j], t);
+                    cur = j;
+                }
+                butterflies<Real, R>(v, g.blo[j], g.bhi[j]);
+            }
+        } else {
+            for (int j = 0; j < g.nlay; ++j) {
+                if (j != cur) {
+                    exchange<Real, R>(v, lds, g.p[cur], g.p[j], t);
+                    cur = j;
+                }
+                butterflies<Real, R>(v, g.blo[j], g.bhi[j]);
+            }
+        }
+    }
+    if (cur != 0) exchange<Real, R>(v, lds, g.p[cur], g.p[0], t);
+    store_tile<Real, R>(v, st, L0);
+}
+
+// ---------------------------------------------------------------- resident kernel
+//
+// Whole ramp of a small lattice inside one workgroup: the state never leaves
+// registers between steps.  Same operation order, angles and renormalization
+// rule as the level sequence of the pass kernels.
+
+template <typename Real, int R>
+__global__ void __launch_bounds__(512) resident_kernel(ResidentArgs a) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const GroupGeom &g = a.geom;
+    const uint32_t t = threadIdx.x;
+    const JobDev J = a.jobs ? a.jobs[a.job0 + blockIdx.x] : a.job_inline;
+    const int S = J.steps, k0 = J.k_begin;
+    if (S <= 0) return;
+    const int n = a.lat.n, nst = a.lat.nst, W = n + 1;
+
+    Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
+    const uint32_t lds_elems = (1u << g.m) + (1u << (g.m - R));
+    Cx<Real> *tab = lds + lds_elems;
+    double2 *fac = align16<double2>(tab + (nst + 1) * W);
+    double *red = reinterpret_cast<double *>(fac + (nst + 1 + W));
+
+    Cx<Real> v[1 << R];
+    Cx<Real> *st = reinterpret_cast<Cx<Real> *>(a.states) + J.offset;
+    LayCtx<R> L0, Lt;
+    lay_ctx<R>(L0, g, a.lat, 0, g.p[0], t, true);
+    lay_ctx<R>(Lt, g, a.lat, 0, g.p[g.nlay - 1], t, true);
+    load_tile<Real, R>(v, st, L0);
+
+    double last_norm = 1.0;
+    bool have_norm = false;
+    const double two_mn = ldexp(1.0, -n);
+
+    auto outer = [&](const LevelOp &op) {
+        double alpha, beta;
+        phase_angles(J, op, alpha, beta);
+        double scale = two_mn;
+        if (op.renorm && have_norm) {
+            if (J.renorm) scale *= 1.0 / sqrt(last_norm);
+            if (t == 0 && J.norm_trace) J.norm_trace[op.ka - k0] = last_norm;
+        }
+        build_table<Real>(tab, fac, nst, n, alpha, beta, scale);
+        int cur = 0;
+        for (int j = 0; j < g.nlay; ++j) {
+            if (j > 0) exchange<Real, R>(v, lds, g.p[j - 1], g.p[j], t);
+            butterflies<Real, R>(v, g.blo[j], g.bhi[j]);
+            cur = j;
+        }
+        apply_phase<Real, R>(v, Lt, 1, n, tab);
+        for (int j = g.nlay - 1; j >= 0; --j) {
+            if (j != cur) {
+                exchange<Real, R>(v, lds, g.p[cur], g.p[j], t);
+                cur = j;
+            }
+            butterflies<Real, R>(v, g.blo[j], g.bhi[j]);
+        }
+    };
+    auto inner = [&](const LevelOp &op) {
+        double alpha, beta;
+        phase_angles(J, op, alpha, beta);
+        if (op.norm) {
+            last_norm = block_sum(sumsq<Real, R>(v), red);
+            have_norm = true;
+        }
+        build_table<Real>(tab, fac, nst, n, alpha, beta, 1.0);
+        apply_phase<Real, R>(v, L0, 0, n, tab);
+    };
+
+    // Walk the same level sequence as the pass kernels with K = 2 groups;
+    // plain-transform visits of group 0 are no-ops here because the whole
+    // transform happens inside the outer visit.
+    const int nlev = J.order == 0 ? 2 * (S + 1) + 1 : 2 * S + 1;
+    for (int lev = 0; lev < nlev; ++lev) {
+        const LevelOp op = level_op(lev, 2, S, k0, J.order);
+        if (op.kind == kIdle || op.kind == kPlainH) continue;
+        if (op.group == 1) outer(op);
+        else inner(op);
+    }
+    store_tile<Real, R>(v, st, L0);
+}
+
+// ---------------------------------------------------------------- observables
+
+// Per-thread accumulation of one basis' observables for the elements in
+// registers: [0] sum |a|^2, [1] sum |a|^2 (nst - 2k), [2] sum |a|^2 (n - 2w),
+// [3..10] loop parities, [11..11+n] weight histogram (computational basis).
+template <typename Real, int R>
+__device__ __forceinline__ void obs_accum(const Cx<Real> (&v)[1 << R], const LayCtx<R> &L,
+                                          int basis, const LatticeDev &lat, const uint32_t *loops,
+                                          int nloops, bool dos, double *acc) {
+    uint32_t s = basis ? L.s0x : L.s0z;
+    double dl[R + 1];
+#pragma unroll
+    for (int j = 0; j <= R; ++j) dl[j] = 0.0;
+    uint32_t lp[kMaxLoops];
+#pragma unroll
+    for (int j = 0; j < kMaxLoops; ++j) lp[j] = j < nloops ? (popc((uint32_t)L.i0 & loops[j]) & 1) : 0;
+#pragma unroll
+    for (int idx = 0; idx < (1 << R); ++idx) {
+        const int q = idx ^ (idx >> 1);
+        if (idx) {
+            const int r = __builtin_ctz(idx);
+            s ^= basis ? L.lx[r] : L.lz[r];
+#pragma unroll
+            for (int j = 0; j < kMaxLoops; ++j)
+                if (j < nloops) lp[j] ^= (loops[j] >> (L.gs + r)) & 1u;
+        }
+        const double p2 = (double)v[q].x * (double)v[q].x + (double)v[q].y * (double)v[q].y;
+        const int k = popc(s);
+        const int w = L.w0 + __builtin_popcount(q);
+        acc[0] += p2;
+        acc[1] += p2 * (double)(lat.nst - 2 * k);
+        acc[2] += p2 * (double)(lat.n - 2 * w);
+#pragma unroll
+        for (int j = 0; j < kMaxLoops; ++j)
+            if (j < nloops) acc[3 + j] += lp[j] ? -p2 : p2;
+        dl[__builtin_popcount(q)] += p2;
+    }
+    if (dos) {
+#pragma unroll
+        for (int b = 0; b < kDosBins; ++b) {
+            double x = 0.0;
+#pragma unroll
+            for (int j = 0; j <= R; ++j) x += (L.w0 + j == b) ? dl[j] : 0.0;
+            acc[11 + b] += x;
+        }
+    }
+}
+
+template <typename Real, int R>
+__global__ void __launch_bounds__(512) obs_kernel(ObsArgs a) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const GroupGeom &g = a.geom;
+    const uint32_t t = threadIdx.x;
+    const int job = blockIdx.y;
+    const uint64_t tiles = 1ull << g.tiles_log2;
+    Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
+    const uint32_t lds_elems = (1u << g.m) + (1u << (g.m - R));
+    double *red = reinterpret_cast<double *>(lds + lds_elems);
+    const Cx<Real> *src = reinterpret_cast<const Cx<Real> *>(a.src) + (a.src_off ? a.src_off[job] : 0);
+    Cx<Real> *dst = a.dst ? reinterpret_cast<Cx<Real> *>(a.dst) + (a.dst_off ? a.dst_off[job] : 0) : nullptr;
+
+    constexpr int NA = 11 + kDosBins;
+    double accz[NA], accx[11];
+#pragma unroll
+    for (int j = 0; j < NA; ++j) accz[j] = 0.0;
+#pragma unroll
+    for (int j = 0; j < 11; ++j) accx[j] = 0.0;
+
+    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        Cx<Real> v[1 << R];
+        LayCtx<R> L0;
+        lay_ctx<R>(L0, g, a.lat, tile, g.p[0], t, a.redZ != 0);
+        load_tile<Real, R>(v, src, L0);
+        if (a.redZ) obs_accum<Real, R>(v, L0, 0, a.lat, a.zloops, a.nz, true, accz);
+        int cur = 0;
+        if (a.doH) {
+            for (int j = 0; j < g.nlay; ++j) {
+                if (j > 0) exchange<Real, R>(v, lds, g.p[j - 1], g.p[j], t);
+                butterflies<Real, R>(v, g.blo[j], g.bhi[j]);
+                cur = j;
+            }
+        }
+        if (a.redX) {
+            LayCtx<R> Lm;
+            lay_ctx<R>(Lm, g, a.lat, tile, g.p[cur], t, true);
+            obs_accum<Real, R>(v, Lm, 1, a.lat, a.xloops, a.nx, false, accx);
+        }
+        if (dst) {
+            if (cur != 0) exchange<Real, R>(v, lds, g.p[cur], g.p[0], t);
+            store_tile<Real, R>(v, dst, L0);
+        }
+    }
+    const size_t rec = ((size_t)job * gridDim.x + blockIdx.x) * kObsQ;
+    if (a.redZ && a.part_z) {
+        for (int j = 0; j < NA; ++j) {
+            const double s = block_sum(accz[j], red);
+            if (t == 0) a.part_z[rec + j] = s;
+        }
+    }
+    if (a.redX && a.part_x) {
+        for (int j = 0; j < 11; ++j) {
+            const double s = block_sum(accx[j], red);
+            if (t == 0) a.part_x[rec + j] = s;
+        }
+    }
+}
+
+// Sum the per-workgroup records of every job and form the observables.
+__global__ void obs_finalize_kernel(FinalArgs a) {
+    const int job = blockIdx.x;
+    const int t = threadIdx.x;
+    __shared__ double sz[kObsQ], sx[kObsQ];
+    if (t < kObsQ) {
+        double s = 0.0, x = 0.0;
+        const double *pz = a.partZ + (size_t)job * a.nrecZ * kObsQ;
+        const double *px = a.partX + (size_t)job * a.nrecX * kObsQ;
+        for (int r = 0; r < a.nrecZ; ++r) s += pz[(size_t)r * kObsQ + t];
+        for (int r = 0; r < a.nrecX; ++r) x += px[(size_t)r * kObsQ + t];
+        sz[t] = s;
+        sx[t] = x;
+    }
+    __syncthreads();
+    if (t == 0) {
+        const int n = a.n;
+        double *o = a.out + (size_t)job * kObsQ;
+        const double *c = a.H ? a.H + 4 * job : a.H_inline;
+        const double nz = sz[0], nxr = sx[0];
+        const double sumB = sz[1] / nz, mz = sz[2] / (n * nz);
+        const double sumA = sx[1] / nxr, mx = sx[2] / (n * nxr);
+        o[0] = nz;
+        o[2] = sumA;
+        o[3] = sumB;
+        o[4] = mx;
+        o[5] = mz;
+        o[1] = -c[0] * sumA - c[1] * sumB - c[2] * n * mx - c[3] * n * mz;
+        for (int j = 0; j < kMaxLoops; ++j) {
+            o[6 + j] = sz[3 + j] / nz;
+            o[14 + j] = sx[3 + j] / nxr;
+        }
+        for (int b = 0; b < kDosBins; ++b) o[22 + b] = sz[11 + b] / nz;
+        o[55] = nxr * ldexp(1.0, -n);
+    }
+}
+
+// ---------------------------------------------------------------- init / misc
+
+template <typename Real>
+__global__ void init_kernel(InitArgs a) {
+    Cx<Real> *st = reinterpret_cast<Cx<Real> *>(a.states) + a.offset;
+    const uint64_t N = 1ull << a.lat.n;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
+         i += (uint64_t)gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (a.kind == 0) {
+            v = syndrome_direct(a.lat.zmask, a.lat.nst, i) == 0 ? a.amp : 0.0;
+        } else if (a.kind == 1) {
+            v = syndrome_direct(a.lat.xmask, a.lat.nst, i) == 0 ? a.amp : 0.0;
+        } else if (a.kind == 2) {
+            v = i == 0 ? 1.0 : 0.0;
+        } else {
+            v = a.amp;
+        }
+        st[i] = Cx<Real>{(Real)v, (Real)0};
+    }
+}
+
+// In-place sum of each job's partial norms into entry 0 (fixed order).
+__global__ void reduce_parts_kernel(const JobDev *jobs, JobDev inl, int parts) {
+    __shared__ double red[16];
+    const JobDev J = jobs ? jobs[blockIdx.x] : inl;
+    if (!J.norm_part) return;
+    double s = 0.0;
+    for (int j = threadIdx.x; j < parts; j += blockDim.x) s += J.norm_part[j];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) J.norm_part[0] = s;
+}
+
+// ---------------------------------------------------------------- launchers
+
+template <typename Real, int R>
+static hipError_t set_lds(const void *fn, size_t lds) {
+    (void)sizeof(Real);
+    if (lds > 65536) return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+    return hipSuccess;
+}
+
+template <typename Real, int R>
+static hipError_t do_level(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    const void *fn = reinterpret_cast<const void *>(&level_kernel<Real, R>);
+    hipError_t e = set_lds<Real, R>(fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((level_kernel<Real, R>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename Real, int R>
+static hipError_t do_resident(const ResidentArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    const void *fn = reinterpret_cast<const void *>(&resident_kernel<Real, R>);
+    hipError_t e = set_lds<Real, R>(fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((resident_kernel<Real, R>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename Real, int R>
+static hipError_t do_obs(const ObsArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    const void *fn = reinterpret_cast<const void *>(&obs_kernel<Real, R>);
+    hipError_t e = set_lds<Real, R>(fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((obs_kernel<Real, R>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
+    return hipGetLastError();
+}
+
+#define Z2H_DISPATCH(FN, ARGS, GRID, LDS, S)                               \
+    do {                                                                   \
+        if (c128) {                                                        \
+            switch (R) {                                                   \
+                case 2: return FN<double, 2>(ARGS, GRID, LDS, S);          \
+                case 3: return FN<double, 3>(ARGS, GRID, LDS, S);          \
+                case 4: return FN<double, 4>(ARGS, GRID, LDS, S);          \
+                case 5: return FN<double, 5>(ARGS, GRID, LDS, S);          \
+            }                                                              \
+        } else {                                                           \
+            switch (R) {                                                   \
+                case 2: return FN<float, 2>(ARGS, GRID, LDS, S);           \
+                case 3: return FN<float, 3>(ARGS, GRID, LDS, S);           \
+                case 4: return FN<float, 4>(ARGS, GRID, LDS, S);           \
+                case 5: return FN<float, 5>(ARGS, GRID, LDS, S);           \
+            }                                                              \
+        }                                                                  \
+        return hipErrorInvalidValue;                                       \
+    } while (0)
+
+hipError_t launch_level(bool c128, int R, const LevelArgs &a, unsigned nblocks, size_t lds,
+                        hipStream_t s) {
+    Z2H_DISPATCH(do_level, a, dim3(nblocks), lds, s);
+}
+
+hipError_t launch_resident(bool c128, int R, const ResidentArgs &a, unsigned njobs, size_t lds,
+                           hipStream_t s) {
+    Z2H_DISPATCH(do_resident, a, dim3(njobs), lds, s);
+}
+
+hipError_t launch_obs(bool c128, int R, const ObsArgs &a, unsigned workers, unsigned njobs,
+                      size_t lds, hipStream_t s) {
+    Z2H_DISPATCH(do_obs, a, dim3(workers, njobs), lds, s);
+}
+
+hipError_t launch_obs_finalize(const FinalArgs &a, unsigned njobs, hipStream_t s) {
+    hipLaunchKernelGGL(obs_finalize_kernel, dim3(njobs), dim3(64), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(bool c128, const InitArgs &a, hipStream_t s) {
+    const uint64_t N = 1ull << a.lat.n;
+    uint64_t blocks = (N + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    if (c128)
+        hipLaunchKernelGGL(init_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(init_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+LevelOp level_op_host(int lev, int K, int S, int k0, int order) {
+    return level_op(lev, K, S, k0, order);
+}
+
+hipError_t launch_reduce_parts(const JobDev *jobs, const JobDev &inl, int njobs, int parts,
+                               hipStream_t s) {
+    hipLaunchKernelGGL(reduce_parts_kernel, dim3(njobs), dim3(256), 0, s, jobs, inl, parts);
+    return hipGetLastError();
+}
+
+}  // namespace z2h

@@ -1,0 +1,336 @@
+"""Thin ctypes binding of libz2h (include/z2h.h): same names, argument
+marshalling only.  Device buffers are torch tensors (PyTorch supplies device
+memory and streams); every computation runs in the HIP library.
+
+There is no fallback: if libz2h.so is missing or fails to load, every entry
+point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libz2h.so")
+
+Z2H_OK = 0
+Z2H_ERR_INVALID = -1
+Z2H_ERR_UNSUPPORTED = -2
+Z2H_ERR_OOM = -3
+Z2H_ERR_HIP = -4
+Z2H_ERR_NUMERIC = -5
+Z2H_ERR_WORKSPACE = -6
+
+Z2H_C64 = 0
+Z2H_C128 = 1
+
+Z2H_INIT_PSI1 = 0
+Z2H_INIT_PSI1P = 1
+Z2H_INIT_ZERO = 2
+Z2H_INIT_PLUS = 3
+
+Z2H_MAX_LOOPS = 8
+Z2H_DOS_BINS = 33
+Z2H_OBS_DOUBLES = 56
+
+
+class Z2HError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"z2h error {code}: {msg}")
+        self.code = code
+
+
+class z2h_couplings(ctypes.Structure):
+    _fields_ = [("JA", ctypes.c_double), ("JB", ctypes.c_double),
+                ("hx", ctypes.c_double), ("hz", ctypes.c_double)]
+
+
+class z2h_schedule(ctypes.Structure):
+    _fields_ = [("start", z2h_couplings), ("end", z2h_couplings),
+                ("steps", ctypes.c_int64), ("dt", ctypes.c_double),
+                ("k_begin", ctypes.c_int64), ("k_end", ctypes.c_int64),
+                ("sampling", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("renorm", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sZ", ctypes.POINTER(ctypes.c_double)), ("sX", ctypes.POINTER(ctypes.c_double))]
+
+
+class z2h_obs(ctypes.Structure):
+    _fields_ = [("norm", ctypes.c_double), ("energy", ctypes.c_double),
+                ("sumA", ctypes.c_double), ("sumB", ctypes.c_double),
+                ("mx", ctypes.c_double), ("mz", ctypes.c_double),
+                ("zloop", ctypes.c_double * Z2H_MAX_LOOPS),
+                ("xloop", ctypes.c_double * Z2H_MAX_LOOPS),
+                ("dos", ctypes.c_double * Z2H_DOS_BINS),
+                ("xnorm", ctypes.c_double)]
+
+
+# Every symbol the header declares, with its ctypes signature.
+_P = ctypes.c_void_p
+_i32, _i64, _sz, _dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.c_double
+SIGNATURES = {
+    "z2h_link_bit": (_i32, [_i32, _i32, _i32, _i32, _i32, ctypes.POINTER(_i32)]),
+    "z2h_masks": (_i32, [_i32, _i32, _P, _P]),
+    "z2h_plan_create": (_i32, [_i32, _i32, _i32, _i32, ctypes.POINTER(_P)]),
+    "z2h_plan_destroy": (None, [_P]),
+    "z2h_plan_sizes": (_i32, [_P, ctypes.POINTER(_sz), ctypes.POINTER(_sz), ctypes.POINTER(_sz),
+                              ctypes.POINTER(_sz)]),
+    "z2h_plan_info": (_i32, [_P, ctypes.POINTER(_i32), ctypes.POINTER(_i32), ctypes.POINTER(_i32),
+                             ctypes.POINTER(_i32)]),
+    "z2h_plan_describe": (_i32, [_P, ctypes.c_char_p, _sz]),
+    "z2h_state_init": (_i32, [_P, _P, _i32, _P]),
+    "z2h_evolve": (_i32, [_P, _P, _P, _sz, ctypes.POINTER(z2h_schedule), _P, _P]),
+    "z2h_observe": (_i32, [_P, _P, _P, _sz, ctypes.POINTER(z2h_couplings), _P, _i32, _P, _i32,
+                           ctypes.POINTER(z2h_obs), _P, _P]),
+    "z2h_adjoint": (_i32, [_P, _P, _P, _sz, ctypes.POINTER(z2h_schedule), ctypes.POINTER(z2h_couplings),
+                           _P, _P, ctypes.POINTER(_dbl), _P]),
+    "z2h_batch_create": (_i32, [_i32, _P, _P, ctypes.POINTER(z2h_schedule), _P,
+                                ctypes.POINTER(z2h_couplings), _i32, ctypes.POINTER(_P),
+                                ctypes.POINTER(_sz), ctypes.POINTER(_sz), _P]),
+    "z2h_batch_run": (_i32, [_P, _P, _P, _sz, _P, _P]),
+    "z2h_batch_destroy": (None, [_P]),
+    "z2h_timing_enable": (_i32, [_i32]),
+    "z2h_timing_read": (_i32, [_P, _P]),
+    "z2h_version": (ctypes.c_char_p, []),
+    "z2h_last_error": (ctypes.c_char_p, []),
+}
+
+_lib = None
+
+
+def lib():
+    """Load libz2h.so (raises if it is missing: there is no CPU fallback)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
+                               "or python -m paper_2108_13410_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(code):
+    if code != Z2H_OK:
+        raise Z2HError(code, lib().z2h_last_error().decode())
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is not None:
+        return ctypes.c_void_p(stream)
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def couplings(JA=1.0, JB=1.0, hx=0.0, hz=0.0):
+    return z2h_couplings(float(JA), float(JB), float(hx), float(hz))
+
+
+def schedule(start, end, steps, dt, k_begin=0, k_end=None, sampling=0, order=0, renorm=0,
+             sZ=None, sX=None):
+    """Build a z2h_schedule; sZ/sX are kept alive on the returned object."""
+    s = z2h_schedule()
+    s.start = start if isinstance(start, z2h_couplings) else couplings(*start)
+    s.end = end if isinstance(end, z2h_couplings) else couplings(*end)
+    s.steps = int(steps)
+    s.dt = float(dt)
+    s.k_begin = int(k_begin)
+    s.k_end = int(steps if k_end is None else k_end)
+    s.sampling = int(sampling)
+    s.order = int(order)
+    s.renorm = int(renorm)
+    keep = []
+    for name, arr in (("sZ", sZ), ("sX", sX)):
+        if arr is not None:
+            a = np.ascontiguousarray(arr, dtype=np.float64)
+            keep.append(a)
+            setattr(s, name, a.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    s._keep = keep
+    return s
+
+
+# ------------------------------------------------------------------ entry points
+
+def z2h_version():
+    return lib().z2h_version().decode()
+
+
+def z2h_last_error():
+    return lib().z2h_last_error().decode()
+
+
+def z2h_link_bit(Lx, Ly, x, y, d):
+    b = ctypes.c_int32()
+    _check(lib().z2h_link_bit(Lx, Ly, x, y, d, ctypes.byref(b)))
+    return b.value
+
+
+def z2h_masks(Lx, Ly):
+    st = np.zeros(Lx * Ly, np.uint64)
+    pl = np.zeros(Lx * Ly, np.uint64)
+    _check(lib().z2h_masks(Lx, Ly, st.ctypes.data_as(_P), pl.ctypes.data_as(_P)))
+    return st, pl
+
+
+class Plan:
+    """Owns a z2h_plan*; destroyed with the object."""
+
+    def __init__(self, handle, Lx, Ly, dtype):
+        self.handle = handle
+        self.Lx, self.Ly, self.dtype = Lx, Ly, dtype
+        self.n = 2 * Lx * Ly
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.z2h_plan_destroy(self.handle)
+            self.handle = None
+
+
+def z2h_plan_create(Lx, Ly, dtype, max_tile_bits=0):
+    h = ctypes.c_void_p()
+    _check(lib().z2h_plan_create(Lx, Ly, dtype, max_tile_bits, ctypes.byref(h)))
+    return Plan(h, Lx, Ly, dtype)
+
+
+def z2h_plan_destroy(plan):
+    if plan.handle:
+        lib().z2h_plan_destroy(plan.handle)
+        plan.handle = None
+
+
+def z2h_plan_sizes(plan):
+    v = [ctypes.c_size_t() for _ in range(4)]
+    _check(lib().z2h_plan_sizes(plan.handle, *[ctypes.byref(x) for x in v]))
+    return dict(zip(("state", "ws_evolve", "ws_observe", "ws_adjoint"), [x.value for x in v]))
+
+
+def z2h_plan_info(plan):
+    v = [ctypes.c_int32() for _ in range(4)]
+    _check(lib().z2h_plan_info(plan.handle, *[ctypes.byref(x) for x in v]))
+    return dict(zip(("n", "groups", "passes_per_step", "tile_bits"), [x.value for x in v]))
+
+
+def z2h_plan_describe(plan):
+    import json
+    buf = ctypes.create_string_buffer(8192)
+    _check(lib().z2h_plan_describe(plan.handle, buf, len(buf)))
+    return json.loads(buf.value.decode())
+
+
+def z2h_state_init(plan, state, kind, stream=None):
+    _check(lib().z2h_state_init(plan.handle, _ptr(state), kind, _stream(stream)))
+
+
+def z2h_evolve(plan, state, ws, sched, norms=None, stream=None):
+    _check(lib().z2h_evolve(plan.handle, _ptr(state), _ptr(ws), ws.numel() * ws.element_size(),
+                            ctypes.byref(sched), _ptr(norms), _stream(stream)))
+
+
+def _masks_arg(masks):
+    if masks is None or len(masks) == 0:
+        return None, 0, None
+    a = np.ascontiguousarray(np.asarray(masks, dtype=np.uint64))
+    return a.ctypes.data_as(_P), int(a.size), a
+
+
+def obs_to_dict(o):
+    return {
+        "norm": o.norm, "energy": o.energy, "sumA": o.sumA, "sumB": o.sumB, "mx": o.mx, "mz": o.mz,
+        "zloop": list(o.zloop), "xloop": list(o.xloop), "dos": list(o.dos), "xnorm": o.xnorm,
+    }
+
+
+def z2h_observe(plan, state, ws, H, zmasks=None, xmasks=None, d_out=None, host=True, stream=None):
+    zp, nz, za = _masks_arg(zmasks)
+    xp, nx, xa = _masks_arg(xmasks)
+    out = z2h_obs() if host else None
+    Hc = H if isinstance(H, z2h_couplings) else couplings(*H)
+    _check(lib().z2h_observe(plan.handle, _ptr(state), _ptr(ws), ws.numel() * ws.element_size(),
+                             ctypes.byref(Hc), zp, nz, xp, nx,
+                             ctypes.byref(out) if out is not None else None, _ptr(d_out), _stream(stream)))
+    del za, xa
+    return obs_to_dict(out) if out is not None else None
+
+
+def z2h_adjoint(plan, psi_final, ws, sched, lossH, gradZ, gradX, stream=None):
+    loss = ctypes.c_double()
+    Hc = lossH if isinstance(lossH, z2h_couplings) else couplings(*lossH)
+    _check(lib().z2h_adjoint(plan.handle, _ptr(psi_final), _ptr(ws), ws.numel() * ws.element_size(),
+                             ctypes.byref(sched), ctypes.byref(Hc), _ptr(gradZ), _ptr(gradX),
+                             ctypes.byref(loss), _stream(stream)))
+    return loss.value
+
+
+class Batch:
+    def __init__(self, handle, njobs, states_bytes, ws_bytes, offsets):
+        self.handle = handle
+        self.njobs = njobs
+        self.states_bytes = states_bytes
+        self.ws_bytes = ws_bytes
+        self.offsets = offsets
+
+    def __del__(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.z2h_batch_destroy(self.handle)
+            self.handle = None
+
+
+def z2h_batch_create(Lx, Ly, scheds, inits, obsH, dtype):
+    nj = len(scheds)
+    Lxa = np.ascontiguousarray(Lx, dtype=np.int32)
+    Lya = np.ascontiguousarray(Ly, dtype=np.int32)
+    ina = np.ascontiguousarray(inits, dtype=np.int32)
+    S = (z2h_schedule * nj)(*scheds)
+    Hs = (z2h_couplings * nj)(*[h if isinstance(h, z2h_couplings) else couplings(*h) for h in obsH])
+    h = ctypes.c_void_p()
+    sb, wb = ctypes.c_size_t(), ctypes.c_size_t()
+    offs = np.zeros(nj, np.uint64)
+    _check(lib().z2h_batch_create(nj, Lxa.ctypes.data_as(_P), Lya.ctypes.data_as(_P), S,
+                                  ina.ctypes.data_as(_P), Hs, dtype, ctypes.byref(h),
+                                  ctypes.byref(sb), ctypes.byref(wb), offs.ctypes.data_as(_P)))
+    return Batch(h, nj, sb.value, wb.value, offs)
+
+
+def z2h_batch_run(batch, states, ws, d_obs, stream=None):
+    _check(lib().z2h_batch_run(batch.handle, _ptr(states), _ptr(ws), ws.numel() * ws.element_size(),
+                               _ptr(d_obs), _stream(stream)))
+
+
+def z2h_batch_destroy(batch):
+    if batch.handle:
+        lib().z2h_batch_destroy(batch.handle)
+        batch.handle = None
+
+
+def z2h_timing_enable(on):
+    _check(lib().z2h_timing_enable(1 if on else 0))
+
+
+def z2h_timing_read():
+    c = np.zeros(4, np.int64)
+    m = np.zeros(4, np.float64)
+    _check(lib().z2h_timing_read(c.ctypes.data_as(_P), m.ctypes.data_as(_P)))
+    return c, m
+
+
+# ------------------------------------------------------------------ plumbing helpers
+
+def alloc_state(plan, device="cuda"):
+    """Uninitialized device tensor of 2^n complex elements for a plan."""
+    import torch
+    dt = torch.complex128 if plan.dtype == Z2H_C128 else torch.complex64
+    return torch.empty(1 << plan.n, dtype=dt, device=device)
+
+
+def alloc_bytes(nbytes, device="cuda"):
+    import torch
+    return torch.empty(max(int(nbytes), 256), dtype=torch.uint8, device=device)

@@ -1,0 +1,159 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle on the
+same seeded inputs.
+
+Tolerances: complex128 fidelity loss <= 1e-12 with amplitudes within 1e-10;
+complex64 fidelity loss <= 1e-5 with intensive observables within 1e-5
+(energy per link, mean fields, loops, weight histogram).
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2108_13410_amd import z2h
+
+from helpers import (compare_observables, fidelity_loss, gpu_run, oracle_observables, oracle_run,
+                     to_oracle_order)
+
+pytestmark = pytest.mark.gpu
+
+C128, C64 = z2h.Z2H_C128, z2h.Z2H_C64
+TC = (1.0, 1.0, 0.0, 0.0)
+
+_cache = {}
+
+
+def _oracle(key, fn):
+    if key not in _cache:
+        _cache[key] = fn()
+    return _cache[key]
+
+
+def _check(Lx, Ly, dtype, g_psi, g_obs, o_psi, H):
+    n = 2 * Lx * Ly
+    o_lib = to_oracle_order(Lx, Ly, g_psi)
+    loss = fidelity_loss(o_psi, o_lib)
+    o_obs = oracle_observables(Lx, Ly, o_psi, H)
+    if dtype == C128:
+        assert loss <= 1e-12, loss
+        assert np.max(np.abs(o_lib - o_psi)) <= 1e-10
+        compare_observables(g_obs, o_obs, 1e-10, n)
+    else:
+        assert loss <= 1e-5, loss
+        compare_observables(g_obs, o_obs, 1e-5, n)
+    return loss
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
+def test_2x2_adiabatic_ramp(dtype):
+    """2x2 torus, T = 10, M = 100, ramp from the toric code to (0.2, 0.2)."""
+    c1 = (1.0, 1.0, 0.2, 0.2)
+    print(f"case 2x2 dtype={dtype}", flush=True)
+    g_psi, g_obs, _ = gpu_run(2, 2, dtype, TC, c1, 100, 0.1)
+    o = _oracle(("2x2",), lambda: oracle_run(2, 2, TC, c1, 100, 0.1))
+    _check(2, 2, dtype, g_psi, g_obs, o, c1)
+
+
+@pytest.mark.parametrize("dtype", [C128, C64])
+def test_3x3_point(dtype):
+    """3x3 torus, one point (0.3, 0.3), T = 20, 1000 steps (full size)."""
+    c1 = (1.0, 1.0, 0.3, 0.3)
+    print(f"case 3x3 M=1000 dtype={dtype}", flush=True)
+    g_psi, g_obs, norms = gpu_run(3, 3, dtype, TC, c1, 1000, 0.02, renorm=1 if dtype == C64 else 0)
+    o = _oracle(("3x3",), lambda: oracle_run(3, 3, TC, c1, 1000, 0.02))
+    _check(3, 3, dtype, g_psi, g_obs, o, c1)
+    assert np.all(np.abs(norms - 1) < (1e-12 if dtype == C128 else 1e-5))
+
+
+@pytest.mark.parametrize("dtype,mtb", [(C128, 8), (C64, 8), (C128, 10)])
+def test_multigroup_schedules(dtype, mtb):
+    """Small tiles force 3-4 transform groups (the 4x4 pass structure) at n = 18."""
+    c1 = (1.0, 0.8, 0.35, 0.25)
+    print(f"case 3x3 groups mtb={mtb} dtype={dtype}", flush=True)
+    plan = z2h.z2h_plan_create(3, 3, dtype, mtb)
+    assert z2h.z2h_plan_info(plan)["groups"] >= 3
+    g_psi, g_obs, _ = gpu_run(3, 3, dtype, TC, c1, 30, 0.05, max_tile_bits=mtb)
+    o = _oracle(("3x3-30",), lambda: oracle_run(3, 3, TC, c1, 30, 0.05))
+    _check(3, 3, dtype, g_psi, g_obs, o, c1)
+
+
+@pytest.mark.parametrize("Lx,Ly,dtype", [(2, 3, C128), (2, 3, C64), (3, 2, C128), (2, 4, C64)])
+def test_rectangular(Lx, Ly, dtype):
+    c1 = (0.9, 1.1, 0.4, 0.15)
+    print(f"case {Lx}x{Ly} dtype={dtype}", flush=True)
+    g_psi, g_obs, _ = gpu_run(Lx, Ly, dtype, TC, c1, 40, 0.1)
+    o = _oracle((Lx, Ly, "rect"), lambda: oracle_run(Lx, Ly, TC, c1, 40, 0.1))
+    _check(Lx, Ly, dtype, g_psi, g_obs, o, c1)
+
+
+@pytest.mark.parametrize("order,sampling", [(1, 0), (0, 1), (1, 1)])
+def test_order_and_sampling(order, sampling):
+    c0, c1 = (1.0, 1.0, 0.05, 0.0), (0.5, 0.5, 0.5, 0.1)
+    print(f"case order={order} sampling={sampling}", flush=True)
+    for Lx, Ly in ((2, 2), (3, 3)):
+        g_psi, g_obs, _ = gpu_run(Lx, Ly, C128, c0, c1, 25, 0.08, order=order, sampling=sampling)
+        o = oracle_run(Lx, Ly, c0, c1, 25, 0.08, order=order, sampling=sampling)
+        _check(Lx, Ly, C128, g_psi, g_obs, o, c1)
+
+
+def test_schedule_arrays():
+    """Per-step schedule values sZ, sX (the adjoint's parameters)."""
+    rng = np.random.default_rng(13410)
+    M = 20
+    sZ = (np.arange(M) + 0.5) / M + rng.normal(0, 0.05, M)
+    sX = (np.arange(M) + 0.5) / M + rng.normal(0, 0.05, M)
+    c1 = (1.0, 1.0, 0.3, 0.3)
+    for Lx, Ly in ((2, 2), (3, 3)):
+        print(f"case arrays {Lx}x{Ly}", flush=True)
+        g_psi, g_obs, _ = gpu_run(Lx, Ly, C128, TC, c1, M, 0.1, sZ=sZ, sX=sX)
+        o = oracle_run(Lx, Ly, TC, c1, M, 0.1, sZ=sZ, sX=sX)
+        _check(Lx, Ly, C128, g_psi, g_obs, o, c1)
+
+
+@pytest.mark.parametrize("init", [z2h.Z2H_INIT_PSI1, z2h.Z2H_INIT_PSI1P, z2h.Z2H_INIT_ZERO, z2h.Z2H_INIT_PLUS])
+def test_initial_states(init):
+    """Eqs. (ini1), (ini2) and the product states, evolved a few steps."""
+    c1 = (1.0, 1.0, 0.25, 0.3)
+    for Lx, Ly in ((2, 2), (3, 3)):
+        print(f"case init={init} {Lx}x{Ly}", flush=True)
+        g_psi, g_obs, _ = gpu_run(Lx, Ly, C128, TC, c1, 6, 0.1, init=init)
+        n = 2 * Lx * Ly
+        if init == z2h.Z2H_INIT_PSI1:
+            o0 = oracle.init_psi1(Lx, Ly)
+        elif init == z2h.Z2H_INIT_PSI1P:
+            o0 = oracle.init_psi1p(Lx, Ly)
+        elif init == z2h.Z2H_INIT_ZERO:
+            o0 = oracle.state(n)
+            o0[0] = 1
+        else:
+            o0 = np.full(1 << n, 2.0 ** (-n / 2), np.complex128)
+        o = oracle_run(Lx, Ly, TC, c1, 6, 0.1, init=o0)
+        _check(Lx, Ly, C128, g_psi, g_obs, o, c1)
+
+
+def test_split_ramp_equals_whole():
+    """Checkpoint/resume: steps [0,k) then [k,M) reproduce the whole ramp."""
+    c1 = (1.0, 1.0, 0.3, 0.3)
+    a, _, _ = gpu_run(3, 3, C128, TC, c1, 40, 0.05)
+    b, _, _ = gpu_run(3, 3, C128, TC, c1, 40, 0.05, chunks=[7, 23])
+    assert fidelity_loss(a, b) < 1e-14
+    assert np.max(np.abs(a - b)) < 1e-13
+
+
+def test_zero_steps_is_identity():
+    c1 = (1.0, 1.0, 0.3, 0.3)
+    g_psi, g_obs, _ = gpu_run(3, 3, C128, TC, c1, 0, 0.1)
+    o = oracle.init_psi1(3, 3)
+    np.testing.assert_allclose(to_oracle_order(3, 3, g_psi), o, atol=1e-15)
+    assert abs(g_obs["energy"] + 18) < 1e-12
+
+
+def test_zero_field_is_a_phase_at_4x4_shape_small():
+    """Zero field: only a global phase exp(+i(JA Ns + JB Np) T); observables stay
+    at the toric-code values (checked on 3x3 with a 3-group schedule)."""
+    c = (1.0, 0.7, 0.0, 0.0)
+    g_psi, g_obs, _ = gpu_run(3, 3, C128, c, c, 50, 0.1, max_tile_bits=8)
+    o0 = oracle.init_psi1(3, 3)
+    ph = np.exp(1j * 1.7 * 9 * 5.0)
+    np.testing.assert_allclose(to_oracle_order(3, 3, g_psi), ph * o0, atol=1e-12)
+    assert abs(g_obs["energy"] + 1.7 * 9) < 1e-11
+    assert abs(g_obs["xloop"][0] - 1) < 1e-12 and abs(g_obs["xloop"][1] - 1) < 1e-12

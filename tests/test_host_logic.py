@@ -1,0 +1,183 @@
+"""Host-side checks of the HIP library that need no GPU: the C ABI exports,
+the lattice builder, the pass planner and, by a CPU re-enactment of the
+kernels' index arithmetic, that every pass touches each amplitude exactly
+once and stays inside its buffers (state, LDS, phase table, partials)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2108_13410_amd import z2h
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+LDS_LIMIT = 160 * 1024
+
+
+def header_symbols():
+    txt = open(os.path.join(ROOT, "include", "z2h.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(z2h_[a-z_]+)\s*\(", txt)))
+
+
+def test_library_exports_every_header_symbol():
+    L = ctypes.CDLL(z2h.LIB_PATH)
+    syms = header_symbols()
+    assert len(syms) >= 15
+    for s in syms:
+        assert hasattr(L, s), s
+    assert set(syms) <= set(z2h.SIGNATURES), set(syms) - set(z2h.SIGNATURES)
+    assert z2h.z2h_version().startswith("z2h")
+
+
+@pytest.mark.parametrize("Lx,Ly", [(2, 2), (2, 3), (3, 3), (3, 4), (4, 4), (2, 8)])
+def test_library_lattice(Lx, Ly):
+    """Library numbering: stars/plaquettes of four links, each link on two of
+    each, even star-plaquette overlaps, products of all stars (plaquettes) = I."""
+    st, pl = z2h.z2h_masks(Lx, Ly)
+    n = 2 * Lx * Ly
+    seen = set()
+    for y in range(Ly):
+        for x in range(Lx):
+            for d in (0, 1):
+                seen.add(z2h.z2h_link_bit(Lx, Ly, x, y, d))
+    assert seen == set(range(n))
+    for m in list(st) + list(pl):
+        assert bin(int(m)).count("1") == 4
+    for l in range(n):
+        assert sum(int(m) >> l & 1 for m in st) == 2
+        assert sum(int(m) >> l & 1 for m in pl) == 2
+    for a in st:
+        for b in pl:
+            assert bin(int(a) & int(b)).count("1") % 2 == 0
+    xs = xp = 0
+    for a, b in zip(st, pl):
+        xs ^= int(a)
+        xp ^= int(b)
+    assert xs == 0 and xp == 0
+
+
+def test_invalid_arguments_rejected_without_gpu():
+    with pytest.raises(z2h.Z2HError) as e:
+        z2h.z2h_plan_create(1, 3, z2h.Z2H_C64)
+    assert e.value.code == z2h.Z2H_ERR_INVALID
+    with pytest.raises(z2h.Z2HError) as e:
+        z2h.z2h_plan_create(4, 5, z2h.Z2H_C64)
+    assert e.value.code == z2h.Z2H_ERR_UNSUPPORTED
+    with pytest.raises(z2h.Z2HError):
+        z2h.z2h_plan_create(3, 3, 7)
+    with pytest.raises(z2h.Z2HError):
+        z2h.z2h_plan_create(3, 3, z2h.Z2H_C64, 20)
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C64)
+    L = z2h.lib()
+    s = z2h.schedule((1, 1, 0, 0), (1, 1, .3, .3), 10, 0.1)
+    # null state / workspace, misaligned state, bad step range, bad dt
+    assert L.z2h_evolve(plan.handle, None, ctypes.c_void_p(4096), 1 << 20, ctypes.byref(s), None, None) == z2h.Z2H_ERR_INVALID
+    assert L.z2h_evolve(plan.handle, ctypes.c_void_p(4096 + 8), ctypes.c_void_p(4096), 1 << 20, ctypes.byref(s), None, None) == z2h.Z2H_ERR_INVALID
+    assert L.z2h_evolve(plan.handle, ctypes.c_void_p(4096), None, 1 << 20, ctypes.byref(s), None, None) == z2h.Z2H_ERR_INVALID
+    assert L.z2h_evolve(plan.handle, ctypes.c_void_p(4096), ctypes.c_void_p(8192), 8, ctypes.byref(s), None, None) == z2h.Z2H_ERR_WORKSPACE
+    bad = z2h.schedule((1, 1, 0, 0), (1, 1, .3, .3), 10, 0.1, k_begin=5, k_end=3)
+    assert L.z2h_evolve(plan.handle, ctypes.c_void_p(4096), ctypes.c_void_p(8192), 1 << 20, ctypes.byref(bad), None, None) == z2h.Z2H_ERR_INVALID
+    bad = z2h.schedule((1, 1, 0, 0), (1, 1, .3, .3), 10, float("nan"))
+    assert L.z2h_evolve(plan.handle, ctypes.c_void_p(4096), ctypes.c_void_p(8192), 1 << 20, ctypes.byref(bad), None, None) == z2h.Z2H_ERR_INVALID
+    bad = z2h.schedule((1, 1, 0, 0), (1, 1, .3, .3), 10, 0.1, order=2)
+    assert L.z2h_evolve(plan.handle, ctypes.c_void_p(4096), ctypes.c_void_p(8192), 1 << 20, ctypes.byref(bad), None, None) == z2h.Z2H_ERR_INVALID
+    bad = z2h.schedule((1, 1, 0, 0), (1, 1, .3, .3), 3, 0.1, sZ=[0.1, float("inf"), 0.2])
+    assert L.z2h_evolve(plan.handle, ctypes.c_void_p(4096), ctypes.c_void_p(8192), 1 << 20, ctypes.byref(bad), None, None) == z2h.Z2H_ERR_INVALID
+    H = z2h.couplings(1, 1, .3, .3)
+    big = (ctypes.c_uint64 * 1)(1 << 40)
+    assert L.z2h_observe(plan.handle, ctypes.c_void_p(4096), ctypes.c_void_p(8192), 1 << 30, ctypes.byref(H), big, 1, None, 0, None, ctypes.c_void_p(4096), None) == z2h.Z2H_ERR_INVALID
+    assert L.z2h_observe(plan.handle, ctypes.c_void_p(4096), ctypes.c_void_p(8192), 1 << 30, ctypes.byref(H), None, 9, None, 0, None, ctypes.c_void_p(4096), None) == z2h.Z2H_ERR_INVALID
+    assert L.z2h_observe(plan.handle, ctypes.c_void_p(4096), ctypes.c_void_p(8192), 16, ctypes.byref(H), None, 0, None, 0, None, ctypes.c_void_p(4096), None) == z2h.Z2H_ERR_WORKSPACE
+    assert L.z2h_state_init(plan.handle, ctypes.c_void_p(4096), 9, None) == z2h.Z2H_ERR_INVALID
+    assert "init kind" in z2h.z2h_last_error()
+
+
+# ------------------------------------------------------------------ planner re-enactment
+
+def lay_base(p, t, R):
+    return (t & ((1 << p) - 1)) | ((t >> p) << (p + R))
+
+
+def glob(g, tile, e):
+    c, b0, m = g["c"], g["b0"], g["m"]
+    tlo_bits = b0 - c
+    tlo = tile & ((1 << tlo_bits) - 1)
+    thi = tile >> tlo_bits
+    return (e & ((1 << c) - 1)) | (tlo << c) | ((e >> c) << b0) | (thi << (b0 + m - c))
+
+
+def gbit(g, x):
+    return x if x < g["c"] else g["b0"] + (x - g["c"])
+
+
+PLANS = [(2, 2, 0, 0), (2, 2, 1, 0), (2, 3, 0, 0), (2, 3, 1, 0), (3, 3, 0, 0), (3, 3, 1, 0),
+         (3, 3, 0, 8), (3, 3, 1, 8), (3, 3, 1, 10), (3, 3, 0, 9), (2, 4, 0, 0), (3, 2, 1, 0),
+         (3, 4, 0, 0), (3, 4, 1, 0), (2, 7, 1, 0), (4, 4, 0, 0), (4, 4, 1, 0)]
+
+
+@pytest.mark.parametrize("Lx,Ly,dt,mtb", PLANS)
+def test_pass_geometry(Lx, Ly, dt, mtb):
+    plan = z2h.z2h_plan_create(Lx, Ly, dt, mtb)
+    d = z2h.z2h_plan_describe(plan)
+    n, R, K = d["n"], d["R"], d["K"]
+    assert K == len(d["groups"])
+    covered = []
+    for gi, g in enumerate(d["groups"]):
+        m, c, b0, x0, x1 = g["m"], g["c"], g["b0"], g["x0"], g["x1"]
+        threads = 1 << (m - R)
+        assert 64 <= threads <= 512
+        assert g["lds_bytes"] <= LDS_LIMIT
+        assert g["tiles_log2"] == n - m
+        # local bits [0,c) and [c,m) map to global [0,c) and [b0, b0+m-c); tile bits fill the rest
+        local = set(range(c)) | set(range(b0, b0 + m - c))
+        tilebits = set(range(c, b0)) | set(range(b0 + m - c, n))
+        assert not (local & tilebits) and (local | tilebits) == set(range(n))
+        covered += [gbit(g, x) for x in range(x0, x1)]
+        # layouts: windows of R local bits inside the transform range, never
+        # straddling the carried boundary; butterflies cover [x0, x1) once
+        done = set()
+        for p, lo, hi in zip(g["p"], g["blo"], g["bhi"]):
+            assert x0 <= p and p + R <= m
+            assert p >= c or p + R <= c
+            bits = set(range(p + lo, p + hi))
+            assert bits <= set(range(x0, x1)) and not (bits & done)
+            done |= bits
+        assert done == set(range(x0, x1))
+        # every layout maps (thread, q) onto the 2^m local indices exactly once,
+        # and the LDS slot stays inside the padded buffer
+        t = np.arange(threads)
+        for p in g["p"]:
+            e = np.concatenate([lay_base(p, t, R) | (q << p) for q in range(1 << R)])
+            assert np.array_equal(np.sort(e), np.arange(1 << m))
+            slot = e + (e >> R)
+            assert slot.max() < (1 << m) + (1 << (m - R))
+            gs = gbit(g, p)
+            # register element q is at global index i0 + (q << gs)
+            for q in (1, (1 << R) - 1):
+                for tile in (0, (1 << g["tiles_log2"]) - 1):
+                    i_direct = glob(g, tile, lay_base(p, t, R) | (q << p))
+                    i_split = glob(g, tile, lay_base(p, t, R)) + (q << gs)
+                    assert np.array_equal(i_direct, i_split)
+                    assert i_direct.max() < (1 << n)
+        if n <= 18:
+            # all tiles together cover the state exactly once
+            e = np.arange(1 << m)
+            allidx = np.concatenate([glob(g, tile, e) for tile in range(1 << g["tiles_log2"])])
+            assert np.array_equal(np.sort(allidx), np.arange(1 << n))
+    assert sorted(covered) == list(range(n))
+    # phase table: index popc(syndrome) * (n + 1) + w stays below (nst + 1)(n + 1)
+    nst = n // 2
+    assert nst * (n + 1) + n < (nst + 1) * (n + 1)
+
+
+def test_level_sequence_counts():
+    """Levels per ramp: x-z-x visits the outer group S+1 times and the inner
+    group S times with a phase; every step's phases appear exactly once."""
+    for K in (2, 3, 4):
+        for S in (1, 2, 5):
+            plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C64, {2: 0, 3: 10, 4: 8}[K])
+            assert z2h.z2h_plan_info(plan)["groups"] == K
+            info = z2h.z2h_plan_info(plan)
+            assert info["passes_per_step"] == 2 * (K - 1)
