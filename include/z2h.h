@@ -133,6 +133,15 @@ z2h_status z2h_link_bit(int32_t Lx, int32_t Ly, int32_t x, int32_t y, int32_t di
  * vertex (index y*Lx + x); caller arrays of Lx*Ly entries.  Host only. */
 z2h_status z2h_masks(int32_t Lx, int32_t Ly, uint64_t *stars, uint64_t *plaqs);
 
+/* Loop masks reported by batches (library numbering): zl = {Wilson loop
+ * around the 1 x min(3, Lx) strip of plaquettes in row 0, around the
+ * L-shaped plaquettes (0,0), (1,0), (0,1), noncontractible W1 along x, W2
+ * along y}; xl = {'t Hooft loops V1 (crossing the vertical links of row 0),
+ * V2 (crossing the horizontal links of column 0)} (Sec. IV).  Caller arrays
+ * of Z2H_MAX_LOOPS entries.  Host only. */
+z2h_status z2h_loop_masks(int32_t Lx, int32_t Ly, uint64_t *zl, int32_t *nz, uint64_t *xl,
+                          int32_t *nx);
+
 /* ------------------------------------------------------------------ plans */
 
 /*
@@ -227,6 +236,13 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
 z2h_status z2h_batch_run(z2h_batch *batch, void *d_states, void *d_ws, size_t ws_bytes,
                          double *d_obs, void *stream);
 void z2h_batch_destroy(z2h_batch *batch); /* NULL-safe */
+
+/* Per-kind pass-kernel times (see z2h_timing_read) of the most recent
+ * z2h_batch_run made while timing was enabled.  With timing enabled a batch
+ * run issues its launch sequence directly on the stream, with an event pair
+ * around every pass kernel, instead of replaying its HIP graph (the kernels
+ * and their order are the same).  Synchronizes. */
+z2h_status z2h_batch_timing(z2h_batch *batch, int64_t counts[4], double ms[4]);
 
 /* ------------------------------------------------------------------ misc */
 

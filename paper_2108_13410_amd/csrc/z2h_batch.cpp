@@ -1,0 +1,430 @@
+// Batched ramps: many phase-diagram points and lattices of uneven size
+// evolved together and recorded once in a HIP graph.
+//
+// Jobs are grouped by lattice.  Groups whose states need several passes per
+// step run level by level on the caller's stream: one launch per level covers
+// every tile of every job still running (jobs are sorted by decreasing step
+// count so the running jobs are a prefix).  Groups small enough to live in one
+// workgroup run on a second stream inside the same graph, concurrently with
+// the level launches.  Observables follow on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <new>
+#include <vector>
+
+#include "z2h_runtime.h"
+
+using namespace z2h;
+using namespace z2h::rt;
+
+namespace {
+
+struct Group {
+    Plan P;
+    std::vector<int> jobs;        // global job indices, decreasing level count
+    std::vector<JobDev> h_jobs;   // host copies (norm_part filled per workspace)
+    std::vector<InitJob> h_init;
+    std::vector<JobDev> h_p1p;    // jobs whose initial state needs the transform
+    std::vector<uint64_t> h_off;  // element offsets
+    std::vector<double> h_H;      // observed couplings, 4 per job
+    std::vector<int32_t> h_out;   // output row per job
+    uint32_t zl[kMaxLoops], xl[kMaxLoops];
+    int nz, nx;
+    // device copies (inside the batch's table allocation)
+    JobDev *d_jobs, *d_p1p;
+    InitJob *d_init;
+    uint64_t *d_off;
+    double *d_H;
+    int32_t *d_out;
+    // workspace pieces (set per workspace)
+    double *parts_norm, *partZ, *partX;
+};
+
+}  // namespace
+
+struct z2h_batch {
+    int njobs;
+    bool c128;
+    size_t esize;
+    std::vector<Group> groups;
+    std::vector<uint64_t> byte_off;
+    size_t states_bytes, ws_bytes;
+    void *d_tables;
+    size_t tables_bytes;
+    hipStream_t side;            // second branch of the graph (one-workgroup lattices)
+    hipStream_t cap;             // stream the graph is recorded on
+    hipEvent_t fork, join;
+    // graph cache
+    hipGraphExec_t exec;
+    void *g_states, *g_ws;
+    double *g_obs;
+    void *up_ws;                     // workspace the device job records point into
+    std::vector<TimedLaunch> timed;  // event pairs of the last timed run
+    int device;
+};
+
+static void loops_for(const Plan &P, uint32_t *zl, int &nz, uint32_t *xl, int &nx) {
+    uint64_t z[kMaxLoops], x[kMaxLoops];
+    int32_t a = 0, c = 0;
+    z2h_loop_masks(P.Lx, P.Ly, z, &a, x, &c);
+    for (int j = 0; j < a; ++j) zl[j] = (uint32_t)z[j];
+    for (int j = 0; j < c; ++j) xl[j] = (uint32_t)x[j];
+    nz = a;
+    nx = c;
+}
+
+static void free_batch(z2h_batch *b) {
+    if (!b) return;
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    for (auto &t : b->timed) {
+        (void)hipEventDestroy(t.a);
+        (void)hipEventDestroy(t.b);
+    }
+    if (b->d_tables) (void)hipFree(b->d_tables);
+    if (b->side) (void)hipStreamDestroy(b->side);
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    if (b->fork) (void)hipEventDestroy(b->fork);
+    if (b->join) (void)hipEventDestroy(b->join);
+    delete b;
+}
+
+// Workspace layout of a batch: transformed-copy scratch mirroring the state
+// buffer, then per group the norm partials and observable records.
+static size_t layout_ws(z2h_batch *b, char *base) {
+    Carver c{base, 0};
+    void *scratch = c.take(b->states_bytes);
+    (void)scratch;
+    for (auto &g : b->groups) {
+        const size_t nj = g.jobs.size();
+        g.parts_norm = (double *)c.take(sizeof(double) * nj * norm_parts(g.P));
+        g.partZ = (double *)c.take(sizeof(double) * nj * obs_workers(g.P.geom[0]) * kObsQ);
+        g.partX = (double *)c.take(sizeof(double) * nj * obs_workers(g.P.geom[g.P.K - 1]) * kObsQ);
+    }
+    return align256(c.off);
+}
+
+// Record (or run) the whole batch on stream s.
+static z2h_status enqueue(z2h_batch *b, void *states, void *ws, double *obs, hipStream_t s) {
+    void *scratch = ws;  // first piece of the workspace
+    // initial states
+    for (auto &g : b->groups) {
+        InitArgs a;
+        memset(&a, 0, sizeof a);
+        a.states = states;
+        a.jobs = g.d_init;
+        a.lat = g.P.lat;
+        hipError_t e = launch_init(g.P.c128, a, (unsigned)g.jobs.size(), s);
+        if (e != hipSuccess) return fail(Z2H_ERR_HIP, "init launch failed: %s", hipGetErrorString(e));
+        if (!g.h_p1p.empty()) {
+            JobSet J;
+            memset(&J, 0, sizeof J);
+            J.d_jobs = g.d_p1p;
+            J.h_jobs = g.h_p1p.data();
+            J.njobs = (int)g.h_p1p.size();
+            z2h_status st = full_transform(g.P, states, J, s);
+            if (st) return st;
+        }
+    }
+    // evolution: resident groups on the side stream, level groups on s
+    bool forked = false;
+    for (auto &g : b->groups) {
+        JobSet J;
+        memset(&J, 0, sizeof J);
+        J.d_jobs = g.d_jobs;
+        J.h_jobs = g.h_jobs.data();
+        J.njobs = (int)g.jobs.size();
+        if (g.P.K == 1) {
+            if (!forked) {
+                HIP_TRY(hipEventRecord(b->fork, s));
+                HIP_TRY(hipStreamWaitEvent(b->side, b->fork, 0));
+                forked = true;
+            }
+            z2h_status st = run_levels(g.P, states, J, b->side);
+            if (st) return st;
+        }
+    }
+    for (auto &g : b->groups) {
+        if (g.P.K == 1) continue;
+        JobSet J;
+        memset(&J, 0, sizeof J);
+        J.d_jobs = g.d_jobs;
+        J.h_jobs = g.h_jobs.data();
+        J.njobs = (int)g.jobs.size();
+        z2h_status st = run_levels(g.P, states, J, s);
+        if (st) return st;
+    }
+    if (forked) {
+        HIP_TRY(hipEventRecord(b->join, b->side));
+        HIP_TRY(hipStreamWaitEvent(s, b->join, 0));
+    }
+    // observables
+    for (auto &g : b->groups) {
+        ObsBuffers B;
+        memset(&B, 0, sizeof B);
+        B.scratch = scratch;
+        B.src_off = g.d_off;
+        B.dst_off = g.d_off;
+        B.partZ = g.partZ;
+        B.partX = g.partX;
+        B.H = g.d_H;
+        B.out = obs;
+        B.out_index = g.d_out;
+        z2h_status st = run_observe(g.P, states, (int)g.jobs.size(), B, g.zl, g.nz, g.xl, g.nx, s);
+        if (st) return st;
+    }
+    return Z2H_OK;
+}
+
+static z2h_status upload_jobs(z2h_batch *b, void *ws) {
+    HIP_TRY(prepare_kernels());
+    layout_ws(b, (char *)ws);
+    for (auto &g : b->groups) {
+        for (size_t j = 0; j < g.h_jobs.size(); ++j)
+            g.h_jobs[j].norm_part = g.parts_norm + j * norm_parts(g.P);
+        HIP_TRY(hipMemcpy(g.d_jobs, g.h_jobs.data(), sizeof(JobDev) * g.h_jobs.size(), hipMemcpyHostToDevice));
+    }
+    return Z2H_OK;
+}
+
+extern "C" {
+
+z2h_status z2h_loop_masks(int32_t Lx, int32_t Ly, uint64_t *zl, int32_t *nz, uint64_t *xl, int32_t *nx) {
+    z2h_status st = check_lattice(Lx, Ly);
+    if (st) return st;
+    if (!zl || !nz || !xl || !nx) return fail(Z2H_ERR_INVALID, "NULL argument");
+    uint64_t stars[kMaxStab], pl[kMaxStab];
+    build_masks(Lx, Ly, stars, pl);
+    uint64_t strip = 0, W1 = 0, W2 = 0, V1 = 0, V2 = 0;
+    for (int x = 0; x < std::min(3, Lx); ++x) strip ^= pl[x];
+    const uint64_t ell = pl[0] ^ pl[1] ^ pl[Lx];
+    for (int x = 0; x < Lx; ++x) {
+        W1 |= 1ull << link_bit(Lx, Ly, x, 0, 0);
+        V1 |= 1ull << link_bit(Lx, Ly, x, 0, 1);
+    }
+    for (int y = 0; y < Ly; ++y) {
+        W2 |= 1ull << link_bit(Lx, Ly, 0, y, 1);
+        V2 |= 1ull << link_bit(Lx, Ly, 0, y, 0);
+    }
+    zl[0] = strip;
+    zl[1] = ell;
+    zl[2] = W1;
+    zl[3] = W2;
+    *nz = 4;
+    xl[0] = V1;
+    xl[1] = V2;
+    *nx = 2;
+    return Z2H_OK;
+}
+
+z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly, const z2h_schedule *sched,
+                            const z2h_init *init, const z2h_couplings *obsH, z2h_dtype dtype, z2h_batch **out,
+                            size_t *states_bytes, size_t *ws_bytes, uint64_t *state_offsets) {
+    try {
+        if (!out) return fail(Z2H_ERR_INVALID, "out is NULL");
+        *out = nullptr;
+        if (njobs <= 0 || njobs > (1 << 20)) return fail(Z2H_ERR_INVALID, "njobs = %d", njobs);
+        if (!Lx || !Ly || !sched || !init || !obsH || !states_bytes || !ws_bytes || !state_offsets)
+            return fail(Z2H_ERR_INVALID, "NULL argument");
+        if (dtype != Z2H_C64 && dtype != Z2H_C128) return fail(Z2H_ERR_INVALID, "bad dtype %d", dtype);
+        const bool c128 = dtype == Z2H_C128;
+        z2h_batch *b = new (std::nothrow) z2h_batch();
+        if (!b) return fail(Z2H_ERR_OOM, "out of host memory");
+        b->njobs = njobs;
+        b->c128 = c128;
+        b->esize = c128 ? 16 : 8;
+        b->device = -1;
+        (void)hipGetDevice(&b->device);
+        // group by lattice, validate
+        std::map<std::pair<int, int>, int> gid;
+        for (int j = 0; j < njobs; ++j) {
+            z2h_status st = check_lattice(Lx[j], Ly[j]);
+            if (st) { free_batch(b); return st; }
+            auto key = std::make_pair(Lx[j], Ly[j]);
+            if (!gid.count(key)) {
+                Group g{};
+                st = make_plan(Lx[j], Ly[j], c128, 0, g.P);
+                if (st) { free_batch(b); return st; }
+                g.P.device = b->device;
+                gid[key] = (int)b->groups.size();
+                b->groups.push_back(g);
+            }
+            if ((st = validate_schedule(b->groups[gid[key]].P, &sched[j]))) { free_batch(b); return st; }
+            if (sched[j].sZ || sched[j].sX) { free_batch(b); return fail(Z2H_ERR_INVALID, "job %d: per-step schedule arrays are not supported in batches", j); }
+            if (sched[j].k_begin != 0 || sched[j].k_end != sched[j].steps) { free_batch(b); return fail(Z2H_ERR_INVALID, "job %d: batches run whole ramps", j); }
+            if (init[j] < Z2H_INIT_PSI1 || init[j] > Z2H_INIT_PLUS) { free_batch(b); return fail(Z2H_ERR_INVALID, "job %d: bad init kind", j); }
+            const double *h = &obsH[j].JA;
+            for (int k = 0; k < 4; ++k)
+                if (!std::isfinite(h[k])) { free_batch(b); return fail(Z2H_ERR_INVALID, "job %d: observed couplings not finite", j); }
+            b->groups[gid[key]].jobs.push_back(j);
+        }
+        // state offsets in job order
+        b->byte_off.resize(njobs);
+        size_t off = 0;
+        for (int j = 0; j < njobs; ++j) {
+            off = align256(off);
+            b->byte_off[j] = off;
+            state_offsets[j] = off;
+            off += b->esize << (2 * Lx[j] * Ly[j]);
+        }
+        b->states_bytes = align256(off);
+        // per group: order jobs by decreasing level count, build records
+        size_t tbytes = 0;
+        for (auto &g : b->groups) {
+            const int Pp = 2 * (g.P.K - 1);
+            auto nlev = [&](int j) {
+                const z2h_schedule &s = sched[j];
+                return s.steps <= 0 ? 0 : (s.order == 0 ? Pp * (s.steps + 1) + 1 : Pp * s.steps + 1);
+            };
+            std::stable_sort(g.jobs.begin(), g.jobs.end(), [&](int a, int c) {
+                return g.P.K == 1 ? sched[a].steps > sched[c].steps : nlev(a) > nlev(c);
+            });
+            for (int j : g.jobs) {
+                const uint64_t eoff = b->byte_off[j] / b->esize;
+                g.h_jobs.push_back(make_job(&sched[j], eoff));
+                g.h_init.push_back(init_job(g.P, init[j], eoff));
+                if (init[j] == Z2H_INIT_PSI1P) g.h_p1p.push_back(make_job(&sched[j], eoff));
+                g.h_off.push_back(eoff);
+                g.h_H.insert(g.h_H.end(), {obsH[j].JA, obsH[j].JB, obsH[j].hx, obsH[j].hz});
+                g.h_out.push_back(j);
+            }
+            loops_for(g.P, g.zl, g.nz, g.xl, g.nx);
+            const size_t nj = g.jobs.size();
+            tbytes += align256(sizeof(JobDev) * nj) + align256(sizeof(JobDev) * std::max<size_t>(1, g.h_p1p.size())) +
+                      align256(sizeof(InitJob) * nj) + align256(sizeof(uint64_t) * nj) +
+                      align256(sizeof(double) * 4 * nj) + align256(sizeof(int32_t) * nj);
+        }
+        b->ws_bytes = layout_ws(b, nullptr);
+        // device tables (the batch's only allocation)
+        b->tables_bytes = tbytes;
+        if (hipMalloc(&b->d_tables, tbytes) != hipSuccess) {
+            free_batch(b);
+            return fail(Z2H_ERR_OOM, "device allocation of %zu bytes failed", tbytes);
+        }
+        Carver c{(char *)b->d_tables, 0};
+        for (auto &g : b->groups) {
+            const size_t nj = g.jobs.size();
+            g.d_jobs = (JobDev *)c.take(sizeof(JobDev) * nj);
+            g.d_p1p = (JobDev *)c.take(sizeof(JobDev) * std::max<size_t>(1, g.h_p1p.size()));
+            g.d_init = (InitJob *)c.take(sizeof(InitJob) * nj);
+            g.d_off = (uint64_t *)c.take(sizeof(uint64_t) * nj);
+            g.d_H = (double *)c.take(sizeof(double) * 4 * nj);
+            g.d_out = (int32_t *)c.take(sizeof(int32_t) * nj);
+            bool ok = hipMemcpy(g.d_init, g.h_init.data(), sizeof(InitJob) * nj, hipMemcpyHostToDevice) == hipSuccess &&
+                      hipMemcpy(g.d_off, g.h_off.data(), sizeof(uint64_t) * nj, hipMemcpyHostToDevice) == hipSuccess &&
+                      hipMemcpy(g.d_H, g.h_H.data(), sizeof(double) * 4 * nj, hipMemcpyHostToDevice) == hipSuccess &&
+                      hipMemcpy(g.d_out, g.h_out.data(), sizeof(int32_t) * nj, hipMemcpyHostToDevice) == hipSuccess &&
+                      (g.h_p1p.empty() || hipMemcpy(g.d_p1p, g.h_p1p.data(), sizeof(JobDev) * g.h_p1p.size(),
+                                                    hipMemcpyHostToDevice) == hipSuccess);
+            if (!ok) {
+                free_batch(b);
+                return fail(Z2H_ERR_HIP, "upload of batch tables failed");
+            }
+        }
+        if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||
+            hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess) {
+            free_batch(b);
+            return fail(Z2H_ERR_HIP, "stream/event creation failed");
+        }
+        *states_bytes = b->states_bytes;
+        *ws_bytes = b->ws_bytes;
+        *out = b;
+        return Z2H_OK;
+    } catch (...) {
+        return fail(Z2H_ERR_OOM, "exception in z2h_batch_create");
+    }
+}
+
+z2h_status z2h_batch_run(z2h_batch *b, void *d_states, void *d_ws, size_t ws_bytes, double *d_obs, void *stream) {
+    try {
+        if (!b) return fail(Z2H_ERR_INVALID, "batch is NULL");
+        z2h_status st = validate_state_ptr(d_states, "d_states");
+        if (st) return st;
+        if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(Z2H_ERR_INVALID, "d_ws NULL or not 256-byte aligned");
+        if (!d_obs) return fail(Z2H_ERR_INVALID, "d_obs is NULL");
+        if (ws_bytes < b->ws_bytes) return fail(Z2H_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, b->ws_bytes);
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess || (b->device >= 0 && dev != b->device))
+            return fail(Z2H_ERR_INVALID, "batch used on another device");
+        hipStream_t s = (hipStream_t)stream;
+        if (t_timing) {
+            // Timed run: the same launch sequence issued directly on the
+            // caller's stream with an event pair around every pass kernel
+            // (event records inside a graph carry no timestamps).
+            HIP_TRY(hipStreamSynchronize(s));
+            for (auto &t : b->timed) {
+                (void)hipEventDestroy(t.a);
+                (void)hipEventDestroy(t.b);
+            }
+            b->timed.clear();
+            if (b->up_ws != d_ws) {
+                if ((st = upload_jobs(b, d_ws))) return st;
+                b->up_ws = d_ws;
+            }
+            std::vector<TimedLaunch> saved;
+            saved.swap(t_launches);
+            st = enqueue(b, d_states, d_ws, d_obs, s);
+            b->timed.swap(t_launches);
+            t_launches.swap(saved);
+            return st;
+        }
+        if (!b->exec || b->g_states != d_states || b->g_ws != d_ws || b->g_obs != d_obs) {
+            if (b->exec) {
+                HIP_TRY(hipStreamSynchronize(s));
+                (void)hipGraphExecDestroy(b->exec);
+                b->exec = nullptr;
+            }
+            if (b->up_ws != d_ws) {
+                HIP_TRY(hipStreamSynchronize(s));
+                if ((st = upload_jobs(b, d_ws))) return st;
+                b->up_ws = d_ws;
+            }
+            // recorded on the batch's own stream (the caller's may be the
+            // legacy default stream, which cannot be captured)
+            HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+            st = enqueue(b, d_states, d_ws, d_obs, b->cap);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(b->cap, &graph);
+            if (st) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return fail(Z2H_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&b->exec, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return fail(Z2H_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+            b->g_states = d_states;
+            b->g_ws = d_ws;
+            b->g_obs = d_obs;
+        }
+        HIP_TRY(hipGraphLaunch(b->exec, s));
+        return Z2H_OK;
+    } catch (...) {
+        return fail(Z2H_ERR_OOM, "exception in z2h_batch_run");
+    }
+}
+
+z2h_status z2h_batch_timing(z2h_batch *b, int64_t counts[4], double ms[4]) {
+    if (!b || !counts || !ms) return fail(Z2H_ERR_INVALID, "NULL argument");
+    for (int k = 0; k < 4; ++k) {
+        counts[k] = 0;
+        ms[k] = 0;
+    }
+    for (auto &t : b->timed) {
+        float x = 0;
+        if (hipEventSynchronize(t.b) != hipSuccess || hipEventElapsedTime(&x, t.a, t.b) != hipSuccess)
+            return fail(Z2H_ERR_HIP, "event timing failed");
+        counts[t.kind] += 1;
+        ms[t.kind] += x;
+    }
+    return Z2H_OK;
+}
+
+void z2h_batch_destroy(z2h_batch *b) { free_batch(b); }
+
+}  // extern "C"

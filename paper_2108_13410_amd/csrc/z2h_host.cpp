@@ -11,17 +11,16 @@
 #include <string>
 #include <vector>
 
-#include "../../include/z2h.h"
-#include "z2h_internal.h"
-#include "z2h_kernels.h"
+#include "z2h_runtime.h"
 
-using namespace z2h;
+namespace z2h {
+namespace rt {
 
 // ------------------------------------------------------------------ errors
 
-static thread_local std::string g_err;
+thread_local std::string g_err;
 
-static z2h_status fail(z2h_status code, const char *fmt, ...) {
+z2h_status fail(z2h_status code, const char *fmt, ...) {
     char buf[512];
     va_list ap;
     va_start(ap, fmt);
@@ -41,13 +40,13 @@ static z2h_status fail(z2h_status code, const char *fmt, ...) {
 // ------------------------------------------------------------------ lattice
 
 // Library numbering (see the header): h(x,y) = y*Lx + x, v(x,y) = Lx*Ly + y*Lx + x.
-static int link_bit(int Lx, int Ly, int x, int y, int dir) {
+int link_bit(int Lx, int Ly, int x, int y, int dir) {
     x = ((x % Lx) + Lx) % Lx;
     y = ((y % Ly) + Ly) % Ly;
     return (dir ? Lx * Ly : 0) + y * Lx + x;
 }
 
-static void build_masks(int Lx, int Ly, uint64_t *st, uint64_t *pl) {
+void build_masks(int Lx, int Ly, uint64_t *st, uint64_t *pl) {
     for (int y = 0; y < Ly; ++y)
         for (int x = 0; x < Lx; ++x) {
             st[y * Lx + x] = (1ull << link_bit(Lx, Ly, x, y, 0)) | (1ull << link_bit(Lx, Ly, x - 1, y, 0)) |
@@ -57,7 +56,7 @@ static void build_masks(int Lx, int Ly, uint64_t *st, uint64_t *pl) {
         }
 }
 
-static z2h_status check_lattice(int Lx, int Ly) {
+z2h_status check_lattice(int Lx, int Ly) {
     if (Lx < 2 || Ly < 2) return fail(Z2H_ERR_INVALID, "lattice %dx%d: Lx and Ly must be >= 2", Lx, Ly);
     if (2 * Lx * Ly > kMaxN)
         return fail(Z2H_ERR_UNSUPPORTED, "lattice %dx%d has %d links; at most %d are supported", Lx, Ly,
@@ -65,7 +64,7 @@ static z2h_status check_lattice(int Lx, int Ly) {
     return Z2H_OK;
 }
 
-static LatticeDev make_latdev(int Lx, int Ly) {
+LatticeDev make_latdev(int Lx, int Ly) {
     LatticeDev L;
     memset(&L, 0, sizeof L);
     const int n = 2 * Lx * Ly, ns = Lx * Ly;
@@ -86,16 +85,6 @@ static LatticeDev make_latdev(int Lx, int Ly) {
 
 // ------------------------------------------------------------------ planner
 
-struct Plan {
-    int Lx, Ly, n, nst;
-    bool c128;
-    size_t esize;
-    int K;                       // groups (1: whole state in one workgroup)
-    int R;                       // log2 register elements per thread
-    GroupGeom geom[kMaxGroups];
-    LatticeDev lat;
-    int device;
-};
 
 // Register-layout sequence covering local transform bits [x0, x1).
 static void plan_layouts(GroupGeom &g, int R) {
@@ -119,7 +108,7 @@ static int pick_R(bool c128, int m) {
     return R;
 }
 
-static z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P) {
+z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P) {
     z2h_status st = check_lattice(Lx, Ly);
     if (st) return st;
     P.Lx = Lx;
@@ -208,7 +197,7 @@ static z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &
     return Z2H_OK;
 }
 
-static size_t lds_bytes(const Plan &P, const GroupGeom &g, int R) {
+size_t lds_bytes(const Plan &P, const GroupGeom &g, int R) {
     const size_t elems = ((size_t)1 << g.m) + ((size_t)1 << (g.m - R));
     size_t b = elems * P.esize;
     b += (size_t)(P.nst + 1) * (P.n + 1) * P.esize;  // phase table
@@ -218,31 +207,26 @@ static size_t lds_bytes(const Plan &P, const GroupGeom &g, int R) {
     return b;
 }
 
-static size_t obs_lds_bytes(const Plan &P, const GroupGeom &g, int R) {
+size_t obs_lds_bytes(const Plan &P, const GroupGeom &g, int R) {
     const size_t elems = ((size_t)1 << g.m) + ((size_t)1 << (g.m - R));
     return ((elems * P.esize + 15) & ~(size_t)15) + 16 * sizeof(double);
 }
 
-static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 static const int kObsWorkersMax = 1024;
 
-static int obs_workers(const GroupGeom &g) {
+int obs_workers(const GroupGeom &g) {
     const uint64_t tiles = 1ull << g.tiles_log2;
     return (int)std::min<uint64_t>(tiles, kObsWorkersMax);
 }
 
-struct z2h_plan {
-    Plan P;
-};
 
 // ------------------------------------------------------------------ timing
 
 namespace {
-struct TimedLaunch {
-    hipEvent_t a, b;
-    int kind;
-};
+thread_local bool t_timing_unused = false;
+}  // namespace
+
 thread_local bool t_timing = false;
 thread_local std::vector<TimedLaunch> t_launches;
 thread_local std::vector<hipEvent_t> t_pool;
@@ -257,17 +241,16 @@ hipEvent_t get_event() {
     if (hipEventCreate(&e) != hipSuccess) return nullptr;
     return e;
 }
-}  // namespace
 
 // ------------------------------------------------------------------ launch sequences
 
-static z2h_status validate_state_ptr(const void *p, const char *what) {
+z2h_status validate_state_ptr(const void *p, const char *what) {
     if (!p) return fail(Z2H_ERR_INVALID, "%s is NULL", what);
     if ((uintptr_t)p & 255) return fail(Z2H_ERR_INVALID, "%s is not 256-byte aligned", what);
     return Z2H_OK;
 }
 
-static z2h_status validate_schedule(const Plan &P, const z2h_schedule *s) {
+z2h_status validate_schedule(const Plan &P, const z2h_schedule *s) {
     if (!s) return fail(Z2H_ERR_INVALID, "schedule is NULL");
     if (s->steps < 0 || s->steps > (1ll << 30)) return fail(Z2H_ERR_INVALID, "steps = %lld out of range", (long long)s->steps);
     if (!std::isfinite(s->dt)) return fail(Z2H_ERR_INVALID, "dt is not finite");
@@ -284,7 +267,22 @@ static z2h_status validate_schedule(const Plan &P, const z2h_schedule *s) {
     return Z2H_OK;
 }
 
-static JobDev make_job(const z2h_schedule *s, uint64_t offset) {
+// Eq. (ini1)/(ini2): equal weight on the 2^(n - Np + 1) configurations with
+// every plaquette (star) even; psi_1' is then Hadamard-transformed, whose
+// 2^(-n/2) normalization (n even) is folded into the amplitude.
+InitJob init_job(const Plan &P, int kind, uint64_t offset) {
+    InitJob j;
+    memset(&j, 0, sizeof j);
+    j.offset = offset;
+    j.kind = kind;
+    const double even = 1.0 / std::sqrt(std::ldexp(1.0, P.n - P.nst + 1));
+    if (kind == Z2H_INIT_PSI1) j.amp = even;
+    if (kind == Z2H_INIT_PSI1P) j.amp = even * std::ldexp(1.0, -P.n / 2);
+    if (kind == Z2H_INIT_PLUS) j.amp = std::ldexp(1.0, -P.n / 2);
+    return j;
+}
+
+JobDev make_job(const z2h_schedule *s, uint64_t offset) {
     JobDev J;
     memset(&J, 0, sizeof J);
     J.offset = offset;
@@ -303,22 +301,14 @@ static JobDev make_job(const z2h_schedule *s, uint64_t offset) {
     return J;
 }
 
-static int pass_kind_of(const LevelOp &op) {
+int pass_kind_of(const LevelOp &op) {
     if (op.kind == kPlainH) return 2;
     if (op.kind == kIdle) return 3;
     return op.basis == 0 ? 0 : 1;
 }
 
-// The jobs of one launch sequence: a device array (batches) or one inline
-// record carried in the kernel argument block (single state).
-struct JobSet {
-    const JobDev *d_jobs;   // device array or null
-    JobDev inl;             // used when d_jobs is null
-    const JobDev *h_jobs;   // host copies (step counts, order)
-    int njobs;
-};
 
-static void timed_begin(hipStream_t s, hipEvent_t &e0, hipEvent_t &e1) {
+void timed_begin(hipStream_t s, hipEvent_t &e0, hipEvent_t &e1) {
     e0 = e1 = nullptr;
     if (!t_timing) return;
     e0 = get_event();
@@ -326,14 +316,14 @@ static void timed_begin(hipStream_t s, hipEvent_t &e0, hipEvent_t &e1) {
     if (e0) (void)hipEventRecord(e0, s);
 }
 
-static void timed_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int kind) {
+void timed_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int kind) {
     if (!t_timing || !e0 || !e1) return;
     (void)hipEventRecord(e1, s);
     t_launches.push_back({e0, e1, kind});
 }
 
 // Launch one level for the jobs of J (all on the lattice of plan P).
-static z2h_status launch_one_level(const Plan &P, void *states, const JobSet &J, int lev, int group,
+z2h_status launch_one_level(const Plan &P, void *states, const JobSet &J, int lev, int group,
                                    int rn_parts, bool force_plain, int kind, hipStream_t s) {
     LevelArgs a;
     memset(&a, 0, sizeof a);
@@ -359,7 +349,7 @@ static z2h_status launch_one_level(const Plan &P, void *states, const JobSet &J,
 }
 
 // Unnormalized Walsh-Hadamard transform of every group (psi_1' preparation).
-static z2h_status full_transform(const Plan &P, void *states, const JobSet &J, hipStream_t s) {
+z2h_status full_transform(const Plan &P, void *states, const JobSet &J, hipStream_t s) {
     for (int gidx = 0; gidx < P.K; ++gidx) {
         z2h_status st = launch_one_level(P, states, J, 0, gidx, 0, true, 2, s);
         if (st) return st;
@@ -368,7 +358,7 @@ static z2h_status full_transform(const Plan &P, void *states, const JobSet &J, h
 }
 
 // Evolve the states of J through their level sequences.
-static z2h_status run_levels(const Plan &P, void *states, const JobSet &J, hipStream_t s) {
+z2h_status run_levels(const Plan &P, void *states, const JobSet &J, hipStream_t s) {
     int maxS = 0;
     bool any0 = false;
     for (int j = 0; j < J.njobs; ++j) {
@@ -396,11 +386,23 @@ static z2h_status run_levels(const Plan &P, void *states, const JobSet &J, hipSt
     const int nlev = any0 ? Pp * (maxS + 1) + 1 : Pp * maxS + 1;
     const int parts0 = 1 << P.geom[0].tiles_log2;
     const bool big_parts = parts0 > 1024;
+    // Levels of each job; jobs are ordered by decreasing level count, so the
+    // jobs still running at a level are a prefix of the array.
+    std::vector<int> jl(J.njobs);
+    for (int j = 0; j < J.njobs; ++j) {
+        const JobDev &h = J.h_jobs[j];
+        jl[j] = h.steps <= 0 ? 0 : (h.order == 0 ? Pp * (h.steps + 1) + 1 : Pp * h.steps + 1);
+        if (j > 0 && jl[j] > jl[j - 1])
+            return fail(Z2H_ERR_INVALID, "internal: jobs not ordered by decreasing step count");
+    }
+    int active = J.njobs;
     for (int lev = 0; lev < nlev; ++lev) {
+        while (active > 0 && jl[active - 1] <= lev) --active;
+        if (active == 0) break;
         // the visited group is the same for every job; the kind may differ
         LevelOp op{};
         bool any_norm = false;
-        for (int j = 0; j < J.njobs; ++j) {
+        for (int j = 0; j < active; ++j) {
             LevelOp o = level_op_host(lev, P.K, J.h_jobs[j].steps, J.h_jobs[j].k_begin, J.h_jobs[j].order);
             if (o.kind != kIdle) {
                 if (op.kind == kIdle) op = o;
@@ -408,28 +410,21 @@ static z2h_status run_levels(const Plan &P, void *states, const JobSet &J, hipSt
             }
         }
         if (op.kind == kIdle) continue;
-        z2h_status st = launch_one_level(P, states, J, lev, op.group, big_parts ? 1 : parts0, false,
+        JobSet Ja = J;
+        Ja.njobs = active;
+        z2h_status st = launch_one_level(P, states, Ja, lev, op.group, big_parts ? 1 : parts0, false,
                                          pass_kind_of(op), s);
         if (st) return st;
         if (big_parts && any_norm) {
-            hipError_t e = launch_reduce_parts(J.d_jobs, J.inl, J.njobs, parts0, s);
+            hipError_t e = launch_reduce_parts(J.d_jobs, J.inl, active, parts0, s);
             if (e != hipSuccess) return fail(Z2H_ERR_HIP, "reduce kernel launch failed: %s", hipGetErrorString(e));
         }
     }
     return Z2H_OK;
 }
 
-// Observables of njobs states; records and outputs in device memory.
-struct ObsBuffers {
-    void *scratch;                      // transformed copies (K > 1)
-    const uint64_t *src_off, *dst_off;  // device arrays or null (single state at offset 0)
-    double *partZ, *partX;              // njobs * workers * kObsQ
-    const double *H;                    // njobs * 4 (device) or null: H_inline
-    double H_inline[4];
-    double *out;                        // njobs * kObsQ
-};
 
-static z2h_status run_observe(const Plan &P, const void *states, int njobs, const ObsBuffers &B,
+z2h_status run_observe(const Plan &P, const void *states, int njobs, const ObsBuffers &B,
                               const uint32_t *zl, int nz, const uint32_t *xl, int nx, hipStream_t s) {
     ObsArgs a;
     memset(&a, 0, sizeof a);
@@ -466,36 +461,26 @@ static z2h_status run_observe(const Plan &P, const void *states, int njobs, cons
     f.H = B.H;
     for (int j = 0; j < 4; ++j) f.H_inline[j] = B.H_inline[j];
     f.out = B.out;
+    f.out_index = B.out_index;
     hipError_t e = launch_obs_finalize(f, njobs, s);
     if (e != hipSuccess) return fail(Z2H_ERR_HIP, "observe finalize failed: %s", hipGetErrorString(e));
     return Z2H_OK;
 }
 
-// Workspace carve-up (256-byte aligned pieces).
-struct Carver {
-    char *base;
-    size_t off;
-    void *take(size_t bytes) {
-        off = align256(off);
-        void *p = base ? base + off : nullptr;
-        off += bytes;
-        return p;
-    }
-};
 
-static size_t obs_records(const Plan &P) {
+size_t obs_records(const Plan &P) {
     return (size_t)obs_workers(P.geom[0]) + (size_t)obs_workers(P.geom[P.K - 1]);
 }
 
-static size_t norm_parts(const Plan &P) { return (size_t)1 << P.geom[0].tiles_log2; }
+size_t norm_parts(const Plan &P) { return (size_t)1 << P.geom[0].tiles_log2; }
 
-static size_t ws_evolve_size(const Plan &P) {
+size_t ws_evolve_size(const Plan &P) {
     Carver c{nullptr, 0};
     c.take(sizeof(double) * norm_parts(P));
     return align256(c.off);
 }
 
-static size_t ws_observe_size(const Plan &P) {
+size_t ws_observe_size(const Plan &P) {
     Carver c{nullptr, 0};
     if (P.K > 1) c.take(P.esize << P.n);
     c.take(sizeof(double) * kObsQ * obs_records(P));
@@ -503,13 +488,30 @@ static size_t ws_observe_size(const Plan &P) {
     return align256(c.off);
 }
 
+}  // namespace rt
+}  // namespace z2h
+
+using namespace z2h;
+using namespace z2h::rt;
+
 // ------------------------------------------------------------------ C ABI
 
-static z2h_status check_device(const Plan &P) {
+z2h_status z2h::rt::check_device_(const Plan &P) {
     int dev = -1;
     if (hipGetDevice(&dev) != hipSuccess) return fail(Z2H_ERR_HIP, "no HIP device");
     if (P.device >= 0 && dev != P.device)
         return fail(Z2H_ERR_INVALID, "current device %d differs from the plan's device %d", dev, P.device);
+    return Z2H_OK;
+}
+
+z2h_status z2h::rt::check_loop_masks(const Plan &P, const uint64_t *m, int32_t cnt, const char *what,
+                                   uint32_t *out) {
+    if (cnt < 0 || cnt > Z2H_MAX_LOOPS) return fail(Z2H_ERR_INVALID, "%s count %d outside [0, %d]", what, cnt, Z2H_MAX_LOOPS);
+    if (cnt && !m) return fail(Z2H_ERR_INVALID, "%s is NULL", what);
+    for (int j = 0; j < cnt; ++j) {
+        if (P.n < 64 && (m[j] >> P.n)) return fail(Z2H_ERR_INVALID, "%s[%d] has bits >= n", what, j);
+        out[j] = (uint32_t)m[j];
+    }
     return Z2H_OK;
 }
 
@@ -616,21 +618,14 @@ z2h_status z2h_state_init(const z2h_plan *plan, void *d_state, z2h_init kind, vo
     if (st) return st;
     if (kind < Z2H_INIT_PSI1 || kind > Z2H_INIT_PLUS) return fail(Z2H_ERR_INVALID, "bad init kind %d", kind);
     const Plan &P = plan->P;
-    if ((st = check_device(P))) return st;
+    if ((st = check_device_(P))) return st;
     hipStream_t s = (hipStream_t)stream;
     InitArgs a;
     memset(&a, 0, sizeof a);
     a.states = d_state;
-    a.offset = 0;
     a.lat = P.lat;
-    a.kind = kind;
-    // Eq. (ini1)/(ini2): equal weight on the 2^(n - Np + 1) configurations
-    // with every plaquette (star) even.
-    const double even = 1.0 / std::sqrt(std::ldexp(1.0, P.n - P.nst + 1));
-    if (kind == Z2H_INIT_PSI1) a.amp = even;
-    if (kind == Z2H_INIT_PSI1P) a.amp = even * std::ldexp(1.0, -P.n / 2);  // n is even
-    if (kind == Z2H_INIT_PLUS) a.amp = std::ldexp(1.0, -P.n / 2);
-    hipError_t e = launch_init(P.c128, a, s);
+    a.one_job = init_job(P, kind, 0);
+    hipError_t e = launch_init(P.c128, a, 1, s);
     if (e != hipSuccess) return fail(Z2H_ERR_HIP, "init kernel failed: %s", hipGetErrorString(e));
     if (kind == Z2H_INIT_PSI1P) {
         // psi_1' = H^n (star-even superposition in the Hadamard basis)
@@ -662,7 +657,7 @@ z2h_status z2h_evolve(const z2h_plan *plan, void *d_state, void *d_ws, size_t ws
                     return fail(Z2H_ERR_INVALID, "schedule value at step %lld not finite", (long long)k);
             }
         }
-        if ((st = check_device(P))) return st;
+        if ((st = check_device_(P))) return st;
         hipStream_t s = (hipStream_t)stream;
         Carver c{(char *)d_ws, 0};
         JobSet J;
@@ -688,17 +683,6 @@ z2h_status z2h_evolve(const z2h_plan *plan, void *d_state, void *d_ws, size_t ws
     }
 }
 
-static z2h_status check_loop_masks(const Plan &P, const uint64_t *m, int32_t cnt, const char *what,
-                                   uint32_t *out) {
-    if (cnt < 0 || cnt > Z2H_MAX_LOOPS) return fail(Z2H_ERR_INVALID, "%s count %d outside [0, %d]", what, cnt, Z2H_MAX_LOOPS);
-    if (cnt && !m) return fail(Z2H_ERR_INVALID, "%s is NULL", what);
-    for (int j = 0; j < cnt; ++j) {
-        if (P.n < 64 && (m[j] >> P.n)) return fail(Z2H_ERR_INVALID, "%s[%d] has bits >= n", what, j);
-        out[j] = (uint32_t)m[j];
-    }
-    return Z2H_OK;
-}
-
 z2h_status z2h_observe(const z2h_plan *plan, const void *d_state, void *d_ws, size_t ws_bytes,
                        const z2h_couplings *H, const uint64_t *zmasks, int32_t nz, const uint64_t *xmasks,
                        int32_t nx, z2h_obs *h_out, double *d_out, void *stream) {
@@ -715,7 +699,7 @@ z2h_status z2h_observe(const z2h_plan *plan, const void *d_state, void *d_ws, si
         if ((st = check_loop_masks(P, xmasks, nx, "xmasks", xl))) return st;
         const size_t need = ws_observe_size(P);
         if (ws_bytes < need) return fail(Z2H_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
-        if ((st = check_device(P))) return st;
+        if ((st = check_device_(P))) return st;
         hipStream_t s = (hipStream_t)stream;
         Carver c{(char *)d_ws, 0};
         ObsBuffers B;

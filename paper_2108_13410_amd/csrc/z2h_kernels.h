@@ -10,6 +10,7 @@
 namespace z2h {
 
 constexpr int kDosBins = 33;
+constexpr int kMaxLdsBytes = 160 * 1024;
 
 struct LevelArgs {
     void *states;              // base of the state buffer (complex elements)
@@ -54,16 +55,22 @@ struct FinalArgs {
     int32_t n, pad;
     const double *H;           // couplings per job (4 doubles), or null: H_inline
     double *out;               // kObsQ doubles per job
+    const int32_t *out_index;  // output row of each job (or null: the job index)
     double H_inline[4];
+};
+
+struct InitJob {
+    uint64_t offset;           // element offset of the state
+    int32_t kind;              // 0 plaquette-even, 1 star-even (before the transform), 2 zero, 3 plus
+    int32_t pad;
+    double amp;
 };
 
 struct InitArgs {
     void *states;
-    uint64_t offset;
+    const InitJob *jobs;       // device array (gridDim.y jobs) or null: one_job
+    InitJob one_job;
     LatticeDev lat;
-    int32_t kind;              // 0 plaquette-even, 1 star-even (before the transform), 2 zero, 3 plus
-    int32_t pad;
-    double amp;
 };
 
 hipError_t launch_level(bool c128, int R, const LevelArgs &a, unsigned nblocks, size_t lds,
@@ -73,10 +80,13 @@ hipError_t launch_resident(bool c128, int R, const ResidentArgs &a, unsigned njo
 hipError_t launch_obs(bool c128, int R, const ObsArgs &a, unsigned workers, unsigned njobs,
                       size_t lds, hipStream_t s);
 hipError_t launch_obs_finalize(const FinalArgs &a, unsigned njobs, hipStream_t s);
-hipError_t launch_init(bool c128, const InitArgs &a, hipStream_t s);
+hipError_t launch_init(bool c128, const InitArgs &a, unsigned njobs, hipStream_t s);
 hipError_t launch_reduce_parts(const JobDev *jobs, const JobDev &inline_job, int njobs, int parts,
                                hipStream_t s);
 
 LevelOp level_op_host(int lev, int K, int S, int k0, int order);
+
+// Set the dynamic-LDS limit of every kernel (call before graph capture).
+hipError_t prepare_kernels();
 
 }  // namespace z2h

@@ -15,6 +15,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <atomic>
+
 #include "z2h_internal.h"
 #include "z2h_kernels.h"
 
@@ -613,7 +615,7 @@ __global__ void obs_finalize_kernel(FinalArgs a) {
     __syncthreads();
     if (t == 0) {
         const int n = a.n;
-        double *o = a.out + (size_t)job * kObsQ;
+        double *o = a.out + (size_t)(a.out_index ? a.out_index[job] : job) * kObsQ;
         const double *c = a.H ? a.H + 4 * job : a.H_inline;
         const double nz = sz[0], nxr = sx[0];
         const double sumB = sz[1] / nz, mz = sz[2] / (n * nz);
@@ -637,19 +639,20 @@ __global__ void obs_finalize_kernel(FinalArgs a) {
 
 template <typename Real>
 __global__ void init_kernel(InitArgs a) {
-    Cx<Real> *st = reinterpret_cast<Cx<Real> *>(a.states) + a.offset;
+    const InitJob J = a.jobs ? a.jobs[blockIdx.y] : a.one_job;
+    Cx<Real> *st = reinterpret_cast<Cx<Real> *>(a.states) + J.offset;
     const uint64_t N = 1ull << a.lat.n;
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < N;
          i += (uint64_t)gridDim.x * blockDim.x) {
         double v = 0.0;
-        if (a.kind == 0) {
-            v = syndrome_direct(a.lat.zmask, a.lat.nst, i) == 0 ? a.amp : 0.0;
-        } else if (a.kind == 1) {
-            v = syndrome_direct(a.lat.xmask, a.lat.nst, i) == 0 ? a.amp : 0.0;
-        } else if (a.kind == 2) {
+        if (J.kind == 0) {
+            v = syndrome_direct(a.lat.zmask, a.lat.nst, i) == 0 ? J.amp : 0.0;
+        } else if (J.kind == 1) {
+            v = syndrome_direct(a.lat.xmask, a.lat.nst, i) == 0 ? J.amp : 0.0;
+        } else if (J.kind == 2) {
             v = i == 0 ? 1.0 : 0.0;
         } else {
-            v = a.amp;
+            v = J.amp;
         }
         st[i] = Cx<Real>{(Real)v, (Real)0};
     }
@@ -668,11 +671,16 @@ __global__ void reduce_parts_kernel(const JobDev *jobs, JobDev inl, int parts) {
 
 // ---------------------------------------------------------------- launchers
 
+// Raise the dynamic-LDS limit of a kernel once to the largest block any plan
+// uses, so that no attribute call happens while a stream is being captured.
 template <typename Real, int R>
 static hipError_t set_lds(const void *fn, size_t lds) {
     (void)sizeof(Real);
-    if (lds > 65536) return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-    return hipSuccess;
+    static std::atomic<int> done{0};
+    if (lds <= 65536 || done.load(std::memory_order_acquire)) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
+    if (e == hipSuccess) done.store(1, std::memory_order_release);
+    return e;
 }
 
 template <typename Real, int R>
@@ -722,6 +730,27 @@ static hipError_t do_obs(const ObsArgs &a, dim3 grid, size_t lds, hipStream_t s)
         return hipErrorInvalidValue;                                       \
     } while (0)
 
+template <typename Real, int R>
+static hipError_t prep_one() {
+    hipError_t e = set_lds<Real, R>(reinterpret_cast<const void *>(&level_kernel<Real, R>), kMaxLdsBytes);
+    if (e == hipSuccess) e = set_lds<Real, R>(reinterpret_cast<const void *>(&resident_kernel<Real, R>), kMaxLdsBytes);
+    if (e == hipSuccess) e = set_lds<Real, R>(reinterpret_cast<const void *>(&obs_kernel<Real, R>), kMaxLdsBytes);
+    return e;
+}
+
+hipError_t prepare_kernels() {
+    hipError_t e = hipSuccess;
+    if (e == hipSuccess) e = prep_one<float, 2>();
+    if (e == hipSuccess) e = prep_one<float, 3>();
+    if (e == hipSuccess) e = prep_one<float, 4>();
+    if (e == hipSuccess) e = prep_one<float, 5>();
+    if (e == hipSuccess) e = prep_one<double, 2>();
+    if (e == hipSuccess) e = prep_one<double, 3>();
+    if (e == hipSuccess) e = prep_one<double, 4>();
+    if (e == hipSuccess) e = prep_one<double, 5>();
+    return e;
+}
+
 hipError_t launch_level(bool c128, int R, const LevelArgs &a, unsigned nblocks, size_t lds,
                         hipStream_t s) {
     Z2H_DISPATCH(do_level, a, dim3(nblocks), lds, s);
@@ -742,14 +771,15 @@ hipError_t launch_obs_finalize(const FinalArgs &a, unsigned njobs, hipStream_t s
     return hipGetLastError();
 }
 
-hipError_t launch_init(bool c128, const InitArgs &a, hipStream_t s) {
+hipError_t launch_init(bool c128, const InitArgs &a, unsigned njobs, hipStream_t s) {
     const uint64_t N = 1ull << a.lat.n;
     uint64_t blocks = (N + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
+    const uint64_t cap = njobs > 64 ? 64 : 4096;
+    if (blocks > cap) blocks = cap;
     if (c128)
-        hipLaunchKernelGGL(init_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(init_kernel<double>, dim3((unsigned)blocks, njobs), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(init_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(init_kernel<float>, dim3((unsigned)blocks, njobs), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -72,6 +72,7 @@ _i32, _i64, _sz, _dbl = ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t, ctypes.
 SIGNATURES = {
     "z2h_link_bit": (_i32, [_i32, _i32, _i32, _i32, _i32, ctypes.POINTER(_i32)]),
     "z2h_masks": (_i32, [_i32, _i32, _P, _P]),
+    "z2h_loop_masks": (_i32, [_i32, _i32, _P, ctypes.POINTER(_i32), _P, ctypes.POINTER(_i32)]),
     "z2h_plan_create": (_i32, [_i32, _i32, _i32, _i32, ctypes.POINTER(_P)]),
     "z2h_plan_destroy": (None, [_P]),
     "z2h_plan_sizes": (_i32, [_P, ctypes.POINTER(_sz), ctypes.POINTER(_sz), ctypes.POINTER(_sz),
@@ -90,6 +91,7 @@ SIGNATURES = {
                                 ctypes.POINTER(_sz), ctypes.POINTER(_sz), _P]),
     "z2h_batch_run": (_i32, [_P, _P, _P, _sz, _P, _P]),
     "z2h_batch_destroy": (None, [_P]),
+    "z2h_batch_timing": (_i32, [_P, _P, _P]),
     "z2h_timing_enable": (_i32, [_i32]),
     "z2h_timing_read": (_i32, [_P, _P]),
     "z2h_version": (ctypes.c_char_p, []),
@@ -179,6 +181,16 @@ def z2h_masks(Lx, Ly):
     pl = np.zeros(Lx * Ly, np.uint64)
     _check(lib().z2h_masks(Lx, Ly, st.ctypes.data_as(_P), pl.ctypes.data_as(_P)))
     return st, pl
+
+
+def z2h_loop_masks(Lx, Ly):
+    """(zloops, xloops) lists of the loop masks batches report."""
+    z = np.zeros(Z2H_MAX_LOOPS, np.uint64)
+    x = np.zeros(Z2H_MAX_LOOPS, np.uint64)
+    nz, nx = ctypes.c_int32(), ctypes.c_int32()
+    _check(lib().z2h_loop_masks(Lx, Ly, z.ctypes.data_as(_P), ctypes.byref(nz), x.ctypes.data_as(_P),
+                                ctypes.byref(nx)))
+    return [int(v) for v in z[:nz.value]], [int(v) for v in x[:nx.value]]
 
 
 class Plan:
@@ -309,6 +321,13 @@ def z2h_batch_destroy(batch):
     if batch.handle:
         lib().z2h_batch_destroy(batch.handle)
         batch.handle = None
+
+
+def z2h_batch_timing(batch):
+    c = np.zeros(4, np.int64)
+    m = np.zeros(4, np.float64)
+    _check(lib().z2h_batch_timing(batch.handle, c.ctypes.data_as(_P), m.ctypes.data_as(_P)))
+    return c, m
 
 
 def z2h_timing_enable(on):

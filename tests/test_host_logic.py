@@ -181,3 +181,33 @@ def test_level_sequence_counts():
             assert z2h.z2h_plan_info(plan)["groups"] == K
             info = z2h.z2h_plan_info(plan)
             assert info["passes_per_step"] == 2 * (K - 1)
+
+
+@pytest.mark.parametrize("Lx,Ly", [(2, 2), (3, 3), (3, 4), (4, 4)])
+def test_loop_masks(Lx, Ly):
+    """The reported loops: the strip and L loops are products of plaquettes
+    (contractible, commute with every star); W1, W2 and V1, V2 are the
+    noncontractible pairs (V1 anticommutes with W2, V2 with W1)."""
+    import oracle
+    zl, xl = z2h.z2h_loop_masks(Lx, Ly)
+    st, pl = z2h.z2h_masks(Lx, Ly)
+    strip = 0
+    for x in range(min(3, Lx)):
+        strip ^= int(pl[x])
+    assert zl[0] == strip
+    assert zl[1] == int(pl[0]) ^ int(pl[1]) ^ int(pl[Lx])
+    for m in zl:
+        for a in st:
+            assert bin(m & int(a)).count("1") % 2 == 0
+    for m in xl:
+        for b in pl:
+            assert bin(m & int(b)).count("1") % 2 == 0
+    assert bin(xl[0] & zl[3]).count("1") % 2 == 1
+    assert bin(xl[1] & zl[2]).count("1") % 2 == 1
+    # same loops as the oracle's, through the link-coordinate map
+    from helpers import mask_lib_to_oracle
+    ol = oracle.loops(Lx, Ly)
+    assert mask_lib_to_oracle(Lx, Ly, zl[2]) == ol["W1"]
+    assert mask_lib_to_oracle(Lx, Ly, zl[3]) == ol["W2"]
+    assert mask_lib_to_oracle(Lx, Ly, xl[0]) == ol["V1"]
+    assert mask_lib_to_oracle(Lx, Ly, xl[1]) == ol["V2"]
