@@ -11,6 +11,8 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <new>
@@ -20,6 +22,7 @@
 
 using namespace z2h;
 using namespace z2h::rt;
+
 
 namespace {
 
@@ -63,6 +66,7 @@ struct z2h_batch {
     void *g_states, *g_ws;
     double *g_obs;
     void *up_ws;                     // workspace the device job records point into
+    int chunk_jobs;                  // jobs evolved together (0: all)
     std::vector<TimedLaunch> timed;  // event pairs of the last timed run
     int device;
 };
@@ -149,13 +153,21 @@ static z2h_status enqueue(z2h_batch *b, void *states, void *ws, double *obs, hip
     }
     for (auto &g : b->groups) {
         if (g.P.K == 1) continue;
-        JobSet J;
-        memset(&J, 0, sizeof J);
-        J.d_jobs = g.d_jobs;
-        J.h_jobs = g.h_jobs.data();
-        J.njobs = (int)g.jobs.size();
-        z2h_status st = run_levels(g.P, states, J, s);
-        if (st) return st;
+        // Jobs run in chunks whose states fit the last-level cache together:
+        // every level of a chunk then streams from the 256 MB MALL instead of
+        // HBM.  Chunks keep the decreasing-step order, so each chunk's running
+        // jobs are still a prefix.
+        const int nj = (int)g.jobs.size();
+        const int chunk = b->chunk_jobs > 0 ? b->chunk_jobs : nj;
+        for (int c0 = 0; c0 < nj; c0 += chunk) {
+            JobSet J;
+            memset(&J, 0, sizeof J);
+            J.d_jobs = g.d_jobs + c0;
+            J.h_jobs = g.h_jobs.data() + c0;
+            J.njobs = std::min(chunk, nj - c0);
+            z2h_status st = run_levels(g.P, states, J, s);
+            if (st) return st;
+        }
     }
     if (forked) {
         HIP_TRY(hipEventRecord(b->join, b->side));
@@ -330,6 +342,17 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
             hipEventCreateWithFlags(&b->join, hipEventDisableTiming) != hipSuccess) {
             free_batch(b);
             return fail(Z2H_ERR_HIP, "stream/event creation failed");
+        }
+        // Chunking (jobs evolved together) is off by default: measured on
+        // MI355X, cache-sized chunks ran slower than one launch per level
+        // over all jobs, whose grids hide latency better.
+        b->chunk_jobs = 0;
+        {
+            if (const char *tv = getenv("Z2H_TUNE")) {
+                int v;
+                const char *q = strstr(tv, "chunk=");
+                if (q && sscanf(q, "chunk=%d", &v) == 1 && v >= 0) b->chunk_jobs = v;
+            }
         }
         *states_bytes = b->states_bytes;
         *ws_bytes = b->ws_bytes;

@@ -86,8 +86,18 @@ LatticeDev make_latdev(int Lx, int Ly) {
 // ------------------------------------------------------------------ planner
 
 
-// Register-layout sequence covering local transform bits [x0, x1).
-static void plan_layouts(GroupGeom &g, int R) {
+// Register-layout sequence covering local transform bits [x0, x1) with
+// windows of g.R bits from the top; g.full = number of layouts when every
+// window is complete and a straight-line kernel exists for it.
+static void plan_layouts(GroupGeom &g, bool resident) {
+    const int R = g.R;
+    const int width = g.x1 - g.x0;
+    const int need = width <= R ? 1 : 1 + (width - R + R - 1) / R;
+    g.full = 0;
+    if (need > kMaxLay || width < R) {
+        g.nlay = kMaxLay + 1;  // rejected by check_block; nothing written
+        return;
+    }
     int p = g.x1 - R, prev = g.x1;
     g.nlay = 0;
     while (true) {
@@ -100,12 +110,219 @@ static void plan_layouts(GroupGeom &g, int R) {
         prev = p;
         p -= R;
     }
+    if (width % R == 0 && (resident ? full_resident_ok(R, width / R) : full_level_ok(R, width / R)))
+        g.full = width / R;
 }
 
 static int pick_R(bool c128, int m) {
     int R = c128 ? 4 : 5;
     while (R > 2 && m - R < 6) --R;  // keep at least one wave per workgroup
     return R;
+}
+
+// Every group's workgroup must fit the kernels' launch bounds (64..512
+// threads) and the 160 KiB of LDS of a gfx950 workgroup.
+static z2h_status check_block(const Plan &P) {
+    for (int j = 0; j < P.K; ++j) {
+        const int tb = P.geom[j].m - P.geom[j].R;
+        if (tb < 6 || tb > 9)
+            return fail(Z2H_ERR_UNSUPPORTED, "group %d: 2^%d threads per workgroup outside [64, 512]", j, tb);
+        if (P.geom[j].nlay > kMaxLay)
+            return fail(Z2H_ERR_UNSUPPORTED, "group %d needs more than %d register layouts", j, kMaxLay);
+        if (lds_bytes(P, P.geom[j], P.geom[j].R) > (size_t)kMaxLdsBytes)
+            return fail(Z2H_ERR_UNSUPPORTED, "group %d needs %zu bytes of LDS", j,
+                        lds_bytes(P, P.geom[j], P.geom[j].R));
+        if (P.K == 1 && !P.geom[0].full)
+            return fail(Z2H_ERR_UNSUPPORTED, "no one-workgroup kernel for n = %d", P.n);
+    }
+    return Z2H_OK;
+}
+
+// Uniform-window planner (every group uses the same R; windows may be
+// partial and then run the general pass kernel).  Used for explicit tuning
+// and as the fallback when no full-window split exists.
+static z2h_status plan_uniform(Plan &P, int m_pref, int m_hi, int c_min, int force_R, int force_g0) {
+    const int n = P.n;
+    const bool c128 = P.c128;
+    memset(P.geom, 0, sizeof P.geom);
+    if (n <= m_hi) {
+        P.K = 1;
+        GroupGeom &g = P.geom[0];
+        g.m = n;
+        g.x1 = n;
+        g.R = force_R ? force_R : pick_R(c128, n);
+        plan_layouts(g, true);
+        return check_block(P);
+    }
+    int K = 0, m = 0;
+    for (int k = 2; k <= kMaxGroups && !K; ++k)
+        for (int mm = m_pref; mm <= m_hi; ++mm)
+            if (mm + (k - 1) * (mm - c_min) >= n) {
+                K = k;
+                m = mm;
+                break;
+            }
+    if (!K) return fail(Z2H_ERR_UNSUPPORTED, "no pass schedule for n = %d with tiles of 2^%d", n, m_hi);
+    P.K = K;
+    const int R = force_R ? force_R : pick_R(c128, m);
+    int gbits[kMaxGroups];
+    int rest = n;
+    for (int j = 0; j < K; ++j) {
+        const int cap = j == 0 ? m : m - c_min;
+        const int share = (rest + (K - j) - 1) / (K - j);
+        gbits[j] = std::min(cap, share);
+        if (j == 0 && force_g0) gbits[j] = std::min(cap, force_g0);
+        rest -= gbits[j];
+    }
+    for (int j = 0; j < K && rest > 0; ++j) {  // remainder to groups with spare capacity
+        const int cap = j == 0 ? m : m - c_min;
+        const int add = std::min(cap - gbits[j], rest);
+        gbits[j] += add;
+        rest -= add;
+    }
+    int b = 0;
+    for (int j = 0; j < K; ++j) {
+        GroupGeom &g = P.geom[j];
+        g.R = R;
+        if (gbits[j] < R) return fail(Z2H_ERR_UNSUPPORTED, "group of %d bits below R = %d", gbits[j], R);
+        if (j == 0) {
+            g.m = std::max(gbits[0], std::min(m_pref, n));
+            g.x1 = gbits[0];
+        } else {
+            const int c = std::min(b, std::max(c_min, m_pref - gbits[j]));
+            if (c + gbits[j] > m_hi) return fail(Z2H_ERR_UNSUPPORTED, "group %d does not fit a tile", j);
+            g.c = c;
+            g.b0 = b;
+            g.m = c + gbits[j];
+            g.x0 = c;
+            g.x1 = c + gbits[j];
+        }
+        g.tiles_log2 = n - g.m;
+        plan_layouts(g, false);
+        b += gbits[j];
+    }
+    return check_block(P);
+}
+
+// Full-window planner: split the n bits into K groups whose widths are
+// exact multiples NL * R of a register window with a compiled straight-line
+// kernel, choosing per group the window R and the tile (carried low bits c
+// for 128-byte or longer contiguous runs).  Cost: passes per step, then LDS
+// layout changes per step, then complex128 windows of 32 registers.
+struct GroupChoice {
+    int G, R, NL, m, c;
+};
+
+static bool fit_group(const Plan &P, int j, int b0, int G, int R, int NL, int m_pref, int m_hi, int c_min,
+                      GroupChoice &out) {
+    const int n = P.n;
+    out = {G, R, NL, 0, 0};
+    auto lds_ok = [&](int m) {
+        GroupGeom g{};
+        g.m = m;
+        g.R = R;
+        return lds_bytes(P, g, R) <= (size_t)kMaxLdsBytes;
+    };
+    if (j == 0) {
+        // largest tile up to the preferred size that suits the window
+        for (int m = std::min(std::min(m_pref, m_hi), n); m >= G; --m) {
+            if (m - R < 6 || m - R > 9 || !lds_ok(m)) continue;
+            out.m = m;
+            out.c = 0;
+            return true;
+        }
+        return false;
+    }
+    // most carried bits up to the preferred tile, at least c_min of them
+    const int cmax = std::min(b0, std::max(c_min, m_pref - G));
+    const int cmin = std::min(b0, c_min);
+    for (int c = cmax; c >= cmin; --c) {
+        const int m = c + G;
+        if (m - R < 6 || m - R > 9 || m > m_hi || !lds_ok(m)) continue;
+        out.m = m;
+        out.c = c;
+        return true;
+    }
+    return false;
+}
+
+static int plan_cost(const Plan &P, const GroupChoice *ch, int K) {
+    int exch = 0, penalty = 0;
+    for (int j = 0; j < K; ++j) {
+        if (j == 0 || j == K - 1) exch += 2 * (ch[j].NL - 1);
+        else exch += 2 * ch[j].NL;
+        if (P.c128 && ch[j].R == 5) return 1 << 29;  // 32 double-complex registers spill
+        if (!P.c128 && ch[j].R < 4) penalty += 5;
+    }
+    return 1000 * 2 * (K - 1) + 10 * exch + penalty;
+}
+
+static bool search_full(const Plan &P, int K, int j, int b0, int m_pref, int m_hi, int c_min, GroupChoice *cur,
+                        GroupChoice *best, int &best_cost) {
+    const int n = P.n;
+    if (j == K) {
+        if (b0 != n) return false;
+        const int cost = plan_cost(P, cur, K);
+        if (cost < best_cost) {
+            best_cost = cost;
+            for (int i = 0; i < K; ++i) best[i] = cur[i];
+        }
+        return true;
+    }
+    bool any = false;
+    for (int R = 5; R >= 2; --R)
+        for (int NL = 1; NL <= kMaxLay; ++NL) {
+            if (!full_level_ok(R, NL)) continue;
+            const int G = R * NL;
+            if (b0 + G > n) continue;
+            if (j == K - 1 && b0 + G != n) continue;
+            GroupChoice gc;
+            if (!fit_group(P, j, b0, G, R, NL, m_pref, m_hi, c_min, gc)) continue;
+            cur[j] = gc;
+            any |= search_full(P, K, j + 1, b0 + G, m_pref, m_hi, c_min, cur, best, best_cost);
+        }
+    return any;
+}
+
+static z2h_status plan_full(Plan &P, int m_pref, int m_hi, int c_min) {
+    const int n = P.n;
+    memset(P.geom, 0, sizeof P.geom);
+    if (n <= m_hi) {
+        // whole state in one workgroup
+        const int prefs[2][4] = {{5, 4, 3, 2}, {4, 3, 5, 2}};
+        for (int R : prefs[P.c128 ? 1 : 0]) {
+            if (n % R || !full_resident_ok(R, n / R) || n - R < 6 || n - R > 9) continue;
+            P.K = 1;
+            GroupGeom &g = P.geom[0];
+            g.m = n;
+            g.x1 = n;
+            g.R = R;
+            plan_layouts(g, true);
+            if (check_block(P) == Z2H_OK) return Z2H_OK;
+        }
+    }
+    for (int K = 2; K <= kMaxGroups; ++K) {
+        GroupChoice cur[kMaxGroups], best[kMaxGroups];
+        int best_cost = 1 << 30;
+        search_full(P, K, 0, 0, m_pref, m_hi, c_min, cur, best, best_cost);
+        if (best_cost >= 1 << 29) continue;
+        P.K = K;
+        int b = 0;
+        for (int j = 0; j < K; ++j) {
+            GroupGeom &g = P.geom[j];
+            g.R = best[j].R;
+            g.m = best[j].m;
+            g.c = best[j].c;
+            g.b0 = j == 0 ? 0 : b;
+            g.x0 = g.c;
+            g.x1 = g.c + best[j].G;
+            g.tiles_log2 = n - g.m;
+            plan_layouts(g, false);
+            b += best[j].G;
+        }
+        return check_block(P);
+    }
+    return fail(Z2H_ERR_UNSUPPORTED, "no full-window schedule for n = %d", n);
 }
 
 z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P) {
@@ -118,8 +335,8 @@ z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P) {
     P.c128 = c128;
     P.esize = c128 ? 16 : 8;
     P.lat = make_latdev(Lx, Ly);
-    const int n = P.n;
-    const int c_min = c128 ? 3 : 4;          // 128-byte contiguous runs
+    P.nt = 0;
+    const int c_min = c128 ? 3 : 4;           // 128-byte contiguous runs
     const int m_lo = c128 ? 12 : 13;          // preferred tile (64 KiB + padding)
     int m_hi = c128 ? 13 : 14;                // largest tile that fits in LDS
     if (max_tile_bits) {
@@ -128,73 +345,28 @@ z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P) {
         m_hi = max_tile_bits;
     }
     const int m_pref = std::min(m_lo, m_hi);
-    memset(P.geom, 0, sizeof P.geom);
-    if (n <= m_hi) {
-        P.K = 1;
-        GroupGeom &g = P.geom[0];
-        g.m = n;
-        g.c = 0;
-        g.b0 = 0;
-        g.x0 = 0;
-        g.x1 = n;
-        g.tiles_log2 = 0;
-        P.R = pick_R(c128, n);
-        plan_layouts(g, P.R);
+    // Tuning override "m=..,R=..,c=..,g0=..,nt=.." selects the uniform planner.
+    if (const char *tv = getenv("Z2H_TUNE")) {
+        int v, mp = m_pref, mh = m_hi, fR = 0, fg0 = 0, cm = c_min;
+        const char *q;
+        if ((q = strstr(tv, "m=")) && sscanf(q, "m=%d", &v) == 1 && v >= 8 && v <= 14) mp = mh = v;
+        if ((q = strstr(tv, "R=")) && sscanf(q, "R=%d", &v) == 1 && v >= 2 && v <= 5) fR = v;
+        if ((q = strstr(tv, "c=")) && sscanf(q, "c=%d", &v) == 1 && v >= 0 && v <= 8) cm = v;
+        if ((q = strstr(tv, "g0=")) && sscanf(q, "g0=%d", &v) == 1 && v >= 2) fg0 = v;
+        if ((q = strstr(tv, "nt=")) && sscanf(q, "nt=%d", &v) == 1) P.nt = v ? 1 : 0;
+        if (strstr(tv, "uniform")) return plan_uniform(P, mp, mh, cm, fR, fg0);
+    }
+    // Straight-line full-window kernels unless they would cost extra passes
+    // (HBM sweeps) per step compared with partial windows.
+    Plan U = P;
+    const z2h_status su = plan_uniform(U, m_pref, m_hi, c_min, 0, 0);
+    st = plan_full(P, m_pref, m_hi, c_min);
+    if (st == Z2H_OK && (su != Z2H_OK || P.K <= U.K)) return Z2H_OK;
+    if (su == Z2H_OK) {
+        P = U;
         return Z2H_OK;
     }
-    // Fewest groups first, then the smallest tile that reaches n bits.
-    int K = 0, m = 0;
-    for (int k = 2; k <= kMaxGroups && !K; ++k)
-        for (int mm = m_pref; mm <= m_hi; ++mm)
-            if (mm + (k - 1) * (mm - c_min) >= n) {
-                K = k;
-                m = mm;
-                break;
-            }
-    if (!K) return fail(Z2H_ERR_UNSUPPORTED, "no pass schedule for n = %d with tiles of 2^%d", n, m_hi);
-    P.K = K;
-    P.R = pick_R(c128, m);
-    // Balanced split of the n bits: group 0 takes up to m bits, the others up
-    // to m - c_min bits each.
-    int gbits[kMaxGroups];
-    int rest = n;
-    for (int j = 0; j < K; ++j) {
-        const int cap = j == 0 ? m : m - c_min;
-        const int share = (rest + (K - j) - 1) / (K - j);
-        gbits[j] = std::min(cap, share);
-        rest -= gbits[j];
-    }
-    if (rest > 0) {  // give the remainder to groups with spare capacity
-        for (int j = 0; j < K && rest > 0; ++j) {
-            const int cap = j == 0 ? m : m - c_min;
-            const int add = std::min(cap - gbits[j], rest);
-            gbits[j] += add;
-            rest -= add;
-        }
-    }
-    int b = 0;
-    for (int j = 0; j < K; ++j) {
-        GroupGeom &g = P.geom[j];
-        if (gbits[j] < P.R) return fail(Z2H_ERR_UNSUPPORTED, "group of %d bits below R = %d", gbits[j], P.R);
-        if (j == 0) {
-            g.m = std::max(gbits[0], std::min(m_pref, n));
-            g.c = 0;
-            g.b0 = 0;
-            g.x0 = 0;
-            g.x1 = gbits[0];
-        } else {
-            const int c = std::min(b, std::max(c_min, m_pref - gbits[j]));
-            g.c = c;
-            g.b0 = b;
-            g.m = c + gbits[j];
-            g.x0 = c;
-            g.x1 = c + gbits[j];
-        }
-        g.tiles_log2 = n - g.m;
-        plan_layouts(g, P.R);
-        b += gbits[j];
-    }
-    return Z2H_OK;
+    return st;
 }
 
 size_t lds_bytes(const Plan &P, const GroupGeom &g, int R) {
@@ -337,12 +509,13 @@ z2h_status launch_one_level(const Plan &P, void *states, const JobSet &J, int le
     a.group = group;
     a.rn_parts = rn_parts;
     a.force_plain = force_plain ? 1 : 0;
+    a.nt = P.nt;
     const uint64_t nblocks = (uint64_t)J.njobs << a.geom.tiles_log2;
     if (nblocks > 0x7fffffffull) return fail(Z2H_ERR_UNSUPPORTED, "grid of %llu blocks", (unsigned long long)nblocks);
-    const size_t lds = lds_bytes(P, a.geom, P.R);
+    const size_t lds = lds_bytes(P, a.geom, a.geom.R);
     hipEvent_t e0, e1;
     timed_begin(s, e0, e1);
-    hipError_t e = launch_level(P.c128, P.R, a, (unsigned)nblocks, lds, s);
+    hipError_t e = launch_level(P.c128, a.geom.R, a, (unsigned)nblocks, lds, s);
     if (e != hipSuccess) return fail(Z2H_ERR_HIP, "level kernel launch failed: %s", hipGetErrorString(e));
     timed_end(s, e0, e1, kind);
     return Z2H_OK;
@@ -377,7 +550,7 @@ z2h_status run_levels(const Plan &P, void *states, const JobSet &J, hipStream_t 
         a.job0 = 0;
         hipEvent_t e0, e1;
         timed_begin(s, e0, e1);
-        hipError_t e = launch_resident(P.c128, P.R, a, (unsigned)J.njobs, lds_bytes(P, a.geom, P.R), s);
+        hipError_t e = launch_resident(P.c128, a.geom.R, a, (unsigned)J.njobs, lds_bytes(P, a.geom, a.geom.R), s);
         if (e != hipSuccess) return fail(Z2H_ERR_HIP, "resident kernel launch failed: %s", hipGetErrorString(e));
         timed_end(s, e0, e1, 3);
         return Z2H_OK;
@@ -448,7 +621,7 @@ z2h_status run_observe(const Plan &P, const void *states, int njobs, const ObsBu
         a.part_x = gi == P.K - 1 ? B.partX : nullptr;
         if (gi == 0) wZ = w;
         if (gi == P.K - 1) wX = w;
-        hipError_t e = launch_obs(P.c128, P.R, a, w, njobs, obs_lds_bytes(P, a.geom, P.R), s);
+        hipError_t e = launch_obs(P.c128, a.geom.R, a, w, njobs, obs_lds_bytes(P, a.geom, a.geom.R), s);
         if (e != hipSuccess) return fail(Z2H_ERR_HIP, "observe kernel failed: %s", hipGetErrorString(e));
     }
     FinalArgs f;
@@ -590,7 +763,7 @@ z2h_status z2h_plan_info(const z2h_plan *plan, int32_t *n, int32_t *groups, int3
 z2h_status z2h_plan_describe(const z2h_plan *plan, char *buf, size_t len) {
     if (!plan || !buf || len == 0) return fail(Z2H_ERR_INVALID, "NULL argument");
     const Plan &P = plan->P;
-    std::string s = "{\"n\": " + std::to_string(P.n) + ", \"R\": " + std::to_string(P.R) +
+    std::string s = "{\"n\": " + std::to_string(P.n) + ", \"R\": " + std::to_string(P.geom[0].R) +
                     ", \"K\": " + std::to_string(P.K) + ", \"c128\": " + (P.c128 ? "1" : "0") + ", \"groups\": [";
     for (int j = 0; j < P.K; ++j) {
         const GroupGeom &g = P.geom[j];
@@ -604,7 +777,8 @@ z2h_status z2h_plan_describe(const z2h_plan *plan, char *buf, size_t len) {
         for (int l = 0; l < g.nlay; ++l) s += (l ? ", " : "") + std::to_string(g.blo[l]);
         s += "], \"bhi\": [";
         for (int l = 0; l < g.nlay; ++l) s += (l ? ", " : "") + std::to_string(g.bhi[l]);
-        s += "], \"lds_bytes\": " + std::to_string(lds_bytes(P, g, P.R)) + "}";
+        s += "], \"lds_bytes\": " + std::to_string(lds_bytes(P, g, g.R)) + ", \"R\": " + std::to_string(g.R) +
+             ", \"full\": " + std::to_string(g.full) + "}";
     }
     s += "]}";
     if (s.size() + 1 > len) return fail(Z2H_ERR_INVALID, "buffer of %zu bytes, %zu needed", len, s.size() + 1);

@@ -31,6 +31,8 @@ struct LatticeDev {
 // butterflies run over register bits [blo[j], bhi[j]).
 struct GroupGeom {
     int32_t m, c, b0, x0, x1;
+    int32_t R;                          // log2 amplitudes per thread
+    int32_t full;                       // NL when x1 - x0 = NL * R (straight-line kernel), else 0
     int32_t nlay;
     int32_t p[kMaxLay], blo[kMaxLay], bhi[kMaxLay];
     int32_t tiles_log2;                 // tiles per state = 2^(n - m)

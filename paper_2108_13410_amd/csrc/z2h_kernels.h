@@ -20,7 +20,7 @@ struct LevelArgs {
     int32_t level, K, group;
     int32_t rn_parts;          // partial norms to sum when a pass renormalizes
     int32_t force_plain;       // 1: plain transform of "group" regardless of the level
-    int32_t pad;
+    int32_t nt;                // 1: nontemporal (streaming) loads and stores of the state
     JobDev job_inline;         // used when jobs is null (single state)
 };
 
@@ -85,6 +85,10 @@ hipError_t launch_reduce_parts(const JobDev *jobs, const JobDev &inline_job, int
                                hipStream_t s);
 
 LevelOp level_op_host(int lev, int K, int S, int k0, int order);
+
+// Register-window shapes (R, NL) with a compiled straight-line kernel.
+bool full_level_ok(int R, int NL);
+bool full_resident_ok(int R, int NL);
 
 // Set the dynamic-LDS limit of every kernel (call before graph capture).
 hipError_t prepare_kernels();

@@ -16,6 +16,8 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <mutex>
+#include <set>
 
 #include "z2h_internal.h"
 #include "z2h_kernels.h"
@@ -141,25 +143,52 @@ __device__ __forceinline__ void lay_ctx(LayCtx<R> &L, const GroupGeom &g, const 
     }
 }
 
-template <typename Real, int R>
+template <typename Real> struct Vec2;
+template <> struct Vec2<float> { typedef float type __attribute__((ext_vector_type(2))); };
+template <> struct Vec2<double> { typedef double type __attribute__((ext_vector_type(2))); };
+
+// One complex element; NT selects the nontemporal (streaming) cache policy.
+template <typename Real, bool NT>
+__device__ __forceinline__ Cx<Real> ldc(const Cx<Real> *p) {
+    if constexpr (NT) {
+        typedef typename Vec2<Real>::type V;
+        const V v = __builtin_nontemporal_load(reinterpret_cast<const V *>(p));
+        return Cx<Real>{v.x, v.y};
+    } else {
+        return *p;
+    }
+}
+
+template <typename Real, bool NT>
+__device__ __forceinline__ void stc(Cx<Real> *p, Cx<Real> x) {
+    if constexpr (NT) {
+        typedef typename Vec2<Real>::type V;
+        V v = {x.x, x.y};
+        __builtin_nontemporal_store(v, reinterpret_cast<V *>(p));
+    } else {
+        *p = x;
+    }
+}
+
+template <typename Real, int R, bool NT = false>
 __device__ __forceinline__ void load_tile(Cx<Real> (&v)[1 << R], const Cx<Real> *st,
                                           const LayCtx<R> &L) {
     const Cx<Real> *b = st + L.i0;
 #pragma unroll
-    for (int q = 0; q < (1 << R); ++q) v[q] = b[(uint64_t)q << L.gs];
+    for (int q = 0; q < (1 << R); ++q) v[q] = ldc<Real, NT>(b + ((uint64_t)q << L.gs));
 }
 
 // The base index is passed through an empty asm statement so that the
 // compiler recomputes the 2^R store addresses instead of keeping the load
 // addresses alive through the whole pass (2 VGPRs each).
-template <typename Real, int R>
+template <typename Real, int R, bool NT = false>
 __device__ __forceinline__ void store_tile(const Cx<Real> (&v)[1 << R], Cx<Real> *st,
                                            const LayCtx<R> &L) {
     uint64_t i0 = L.i0;
     asm volatile("" : "+v"(i0));
     Cx<Real> *b = st + i0;
 #pragma unroll
-    for (int q = 0; q < (1 << R); ++q) b[(uint64_t)q << L.gs] = v[q];
+    for (int q = 0; q < (1 << R); ++q) stc<Real, NT>(b + ((uint64_t)q << L.gs), v[q]);
 }
 
 // Build the phase table T[k][w] = scale * exp(i (alpha (nst - 2k) + beta (n - 2w)))
@@ -323,7 +352,7 @@ __host__ __device__ inline LevelOp level_op(int lev, int K, int S, int k0, int o
 
 // ---------------------------------------------------------------- level kernel
 
-template <typename Real, int R>
+template <typename Real, int R, bool NT>
 __global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const GroupGeom &g = a.geom;
@@ -368,7 +397,7 @@ __global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
 
     LayCtx<R> L0;
     lay_ctx<R>(L0, g, a.lat, tile, g.p[0], t, false);
-    load_tile<Real, R>(v, st, L0);
+    load_tile<Real, R, NT>(v, st, L0);
 
     int cur = 0;
     if (preH) {
@@ -407,16 +436,157 @@ __global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
         }
     }
     if (cur != 0) exchange<Real, R>(v, lds, g.p[cur], g.p[0], t);
-    store_tile<Real, R>(v, st, L0);
+    store_tile<Real, R, NT>(v, st, L0);
+}
+
+// ---------------------------------------------------------------- full-window kernels
+//
+// When a group's transformed bits are an exact multiple NL * R of the
+// register window, every layout butterflies all R register bits: the
+// transform is straight-line code (no runtime-selected stages, so no register
+// copies at control-flow joins), layout j sits at local bit x1 - R (j + 1),
+// and each pass kind is its own straight-line path from load to store.
+
+template <typename Real, int R>
+__device__ __forceinline__ void bfly_all(Cx<Real> (&v)[1 << R]) {
+#pragma unroll
+    for (int j = 0; j < R; ++j) {
+#pragma unroll
+        for (int q = 0; q < (1 << R); ++q) {
+            if (!(q & (1 << j))) {
+                Cx<Real> a = v[q], b = v[q | (1 << j)];
+                v[q] = cadd(a, b);
+                v[q | (1 << j)] = csub(a, b);
+            }
+        }
+    }
+}
+
+// Layout change through LDS.  The register bits and the thread bits of a
+// local index are disjoint, so slot(base | q << p) = slot(base) + slot(q << p):
+// one per-thread base plus a block-uniform offset per element.
+template <typename Real, int R>
+__device__ __forceinline__ void xchg(Cx<Real> (&v)[1 << R], Cx<Real> *lds, int pf, int pt, uint32_t t) {
+    const uint32_t bf = slot<R>(lay_base<R>(pf, t)), bt = slot<R>(lay_base<R>(pt, t));
+#pragma unroll
+    for (int q = 0; q < (1 << R); ++q) lds[bf + slot<R>((uint32_t)q << pf)] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < (1 << R); ++q) v[q] = lds[bt + slot<R>((uint32_t)q << pt)];
+    __syncthreads();
+}
+
+// Transform over the group: layouts 0 .. NL-1 (ends in layout NL-1).
+template <typename Real, int R, int NL>
+__device__ __forceinline__ void fwd_full(Cx<Real> (&v)[1 << R], Cx<Real> *lds, int x1, uint32_t t) {
+    bfly_all<Real, R>(v);
+#pragma unroll
+    for (int j = 1; j < NL; ++j) {
+        xchg<Real, R>(v, lds, x1 - R * j, x1 - R * (j + 1), t);
+        bfly_all<Real, R>(v);
+    }
+}
+
+// Transform over the group starting in layout NL-1 (ends in layout 0).
+template <typename Real, int R, int NL>
+__device__ __forceinline__ void bwd_full(Cx<Real> (&v)[1 << R], Cx<Real> *lds, int x1, uint32_t t) {
+    bfly_all<Real, R>(v);
+#pragma unroll
+    for (int j = NL - 1; j >= 1; --j) {
+        xchg<Real, R>(v, lds, x1 - R * (j + 1), x1 - R * j, t);
+        bfly_all<Real, R>(v);
+    }
+}
+
+template <typename Real, int R, int NL, int KIND>
+__device__ __forceinline__ void pass_full(const LevelArgs &a, const JobDev &J, const LevelOp &op,
+                                          uint64_t tile, uint32_t t, Cx<Real> *lds, const Cx<Real> *tab,
+                                          double *red) {
+    const GroupGeom &g = a.geom;
+    const int x1 = g.x1;
+    const int p0 = x1 - R, pl = x1 - R * NL;
+    Cx<Real> *st = reinterpret_cast<Cx<Real> *>(a.states) + J.offset;
+    Cx<Real> v[1 << R];
+    LayCtx<R> L0;
+    lay_ctx<R>(L0, g, a.lat, tile, p0, t, KIND == kHalfIn);
+    load_tile<Real, R, true>(v, st, L0);
+    if constexpr (KIND == kHalfIn) {
+        if (op.norm) {
+            const double s = block_sum(sumsq<Real, R>(v), red);
+            if (t == 0 && J.norm_part) J.norm_part[tile] = s;
+        }
+        apply_phase<Real, R>(v, L0, op.basis, a.lat.n, tab);
+    }
+    fwd_full<Real, R, NL>(v, lds, x1, t);
+    if constexpr (KIND == kPhaseB || KIND == kHalfOut) {
+        LayCtx<R> Lm;
+        lay_ctx<R>(Lm, g, a.lat, tile, pl, t, true);
+        if constexpr (KIND == kPhaseB) {
+            if (op.norm) {
+                const double s = block_sum(sumsq<Real, R>(v), red);
+                if (t == 0 && J.norm_part) J.norm_part[tile] = s;
+            }
+        }
+        apply_phase<Real, R>(v, Lm, op.basis, a.lat.n, tab);
+    }
+    if constexpr (KIND == kPhaseB) {
+        bwd_full<Real, R, NL>(v, lds, x1, t);
+    } else {
+        if constexpr (NL > 1) xchg<Real, R>(v, lds, pl, p0, t);
+    }
+    store_tile<Real, R, true>(v, st, L0);
+}
+
+template <typename Real, int R, int NL>
+__global__ void __launch_bounds__(512) level_kernel_full(LevelArgs a) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const GroupGeom &g = a.geom;
+    const uint32_t t = threadIdx.x;
+    const uint64_t tiles = 1ull << g.tiles_log2;
+    const uint64_t bid = blockIdx.x;
+    const int jb = (int)(bid >> g.tiles_log2);
+    const uint64_t tile = bid & (tiles - 1);
+    const JobDev J = a.jobs ? a.jobs[jb] : a.job_inline;
+    const LevelOp op = a.force_plain ? LevelOp{a.group, kPlainH, 0, -1, -1, 0, 0, 0}
+                                     : level_op(a.level, a.K, J.steps, J.k_begin, J.order);
+    if (op.kind == kIdle || op.group != a.group) return;  // uniform per block
+
+    Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
+    const uint32_t lds_elems = (1u << g.m) + (1u << (g.m - R));
+    Cx<Real> *tab = lds + lds_elems;
+    const int W = a.lat.n + 1;
+    double2 *fac = align16<double2>(tab + (a.lat.nst + 1) * W);
+    double *red = reinterpret_cast<double *>(fac + (a.lat.nst + 1 + W));
+
+    if (op.kind != kPlainH) {
+        double alpha, beta;
+        phase_angles(J, op, alpha, beta);
+        double scale = op.basis ? ldexp(1.0, -a.lat.n) : 1.0;
+        if (op.renorm && J.norm_part) {
+            double s = 0.0;
+            for (int j = (int)t; j < a.rn_parts; j += blockDim.x) s += J.norm_part[j];
+            s = block_sum(s, red);
+            if (J.renorm) scale *= 1.0 / sqrt(s);
+            if (tile == 0 && t == 0 && J.norm_trace) J.norm_trace[op.ka - J.k_begin] = s;
+        }
+        build_table<Real>(tab, fac, a.lat.nst, a.lat.n, alpha, beta, scale);
+    }
+    switch (op.kind) {
+        case kPhaseB: pass_full<Real, R, NL, kPhaseB>(a, J, op, tile, t, lds, tab, red); break;
+        case kPlainH: pass_full<Real, R, NL, kPlainH>(a, J, op, tile, t, lds, tab, red); break;
+        case kHalfIn: pass_full<Real, R, NL, kHalfIn>(a, J, op, tile, t, lds, tab, red); break;
+        default: pass_full<Real, R, NL, kHalfOut>(a, J, op, tile, t, lds, tab, red); break;
+    }
 }
 
 // ---------------------------------------------------------------- resident kernel
 //
 // Whole ramp of a small lattice inside one workgroup: the state never leaves
 // registers between steps.  Same operation order, angles and renormalization
-// rule as the level sequence of the pass kernels.
+// rule as the level sequence of the pass kernels.  The whole state is one
+// group of NL * R = n transformed bits.
 
-template <typename Real, int R>
+template <typename Real, int R, int NL>
 __global__ void __launch_bounds__(512) resident_kernel(ResidentArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const GroupGeom &g = a.geom;
@@ -425,6 +595,7 @@ __global__ void __launch_bounds__(512) resident_kernel(ResidentArgs a) {
     const int S = J.steps, k0 = J.k_begin;
     if (S <= 0) return;
     const int n = a.lat.n, nst = a.lat.nst, W = n + 1;
+    const int x1 = g.x1, p0 = x1 - R, pl = x1 - R * NL;
 
     Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
     const uint32_t lds_elems = (1u << g.m) + (1u << (g.m - R));
@@ -435,15 +606,15 @@ __global__ void __launch_bounds__(512) resident_kernel(ResidentArgs a) {
     Cx<Real> v[1 << R];
     Cx<Real> *st = reinterpret_cast<Cx<Real> *>(a.states) + J.offset;
     LayCtx<R> L0, Lt;
-    lay_ctx<R>(L0, g, a.lat, 0, g.p[0], t, true);
-    lay_ctx<R>(Lt, g, a.lat, 0, g.p[g.nlay - 1], t, true);
+    lay_ctx<R>(L0, g, a.lat, 0, p0, t, true);
+    lay_ctx<R>(Lt, g, a.lat, 0, pl, t, true);
     load_tile<Real, R>(v, st, L0);
 
     double last_norm = 1.0;
-    bool have_norm = false;
     const double two_mn = ldexp(1.0, -n);
 
-    auto outer = [&](const LevelOp &op) {
+    // outer (Hadamard-basis) phase: transform, phase, transform back
+    auto outer = [&](const LevelOp &op, bool have_norm) {
         double alpha, beta;
         phase_angles(J, op, alpha, beta);
         double scale = two_mn;
@@ -452,41 +623,34 @@ __global__ void __launch_bounds__(512) resident_kernel(ResidentArgs a) {
             if (t == 0 && J.norm_trace) J.norm_trace[op.ka - k0] = last_norm;
         }
         build_table<Real>(tab, fac, nst, n, alpha, beta, scale);
-        int cur = 0;
-        for (int j = 0; j < g.nlay; ++j) {
-            if (j > 0) exchange<Real, R>(v, lds, g.p[j - 1], g.p[j], t);
-            butterflies<Real, R>(v, g.blo[j], g.bhi[j]);
-            cur = j;
-        }
+        fwd_full<Real, R, NL>(v, lds, x1, t);
         apply_phase<Real, R>(v, Lt, 1, n, tab);
-        for (int j = g.nlay - 1; j >= 0; --j) {
-            if (j != cur) {
-                exchange<Real, R>(v, lds, g.p[cur], g.p[j], t);
-                cur = j;
-            }
-            butterflies<Real, R>(v, g.blo[j], g.bhi[j]);
-        }
+        bwd_full<Real, R, NL>(v, lds, x1, t);
     };
+    // inner (computational-basis) phase, with the norm measured first
     auto inner = [&](const LevelOp &op) {
         double alpha, beta;
         phase_angles(J, op, alpha, beta);
-        if (op.norm) {
-            last_norm = block_sum(sumsq<Real, R>(v), red);
-            have_norm = true;
-        }
+        if (op.norm) last_norm = block_sum(sumsq<Real, R>(v), red);
         build_table<Real>(tab, fac, nst, n, alpha, beta, 1.0);
         apply_phase<Real, R>(v, L0, 0, n, tab);
     };
 
-    // Walk the same level sequence as the pass kernels with K = 2 groups;
-    // plain-transform visits of group 0 are no-ops here because the whole
-    // transform happens inside the outer visit.
-    const int nlev = J.order == 0 ? 2 * (S + 1) + 1 : 2 * S + 1;
-    for (int lev = 0; lev < nlev; ++lev) {
-        const LevelOp op = level_op(lev, 2, S, k0, J.order);
-        if (op.kind == kIdle || op.kind == kPlainH) continue;
-        if (op.group == 1) outer(op);
-        else inner(op);
+    // The level sequence with K = 2 groups, walked in its fixed pattern:
+    // order 0: X(0) [Z(j) X(j+1)] ..., order 1: Z(0) [X(j) Z(j+1)] ...
+    const int P = 2;
+    if (J.order == 0) {
+        outer(level_op(1, 2, S, k0, 0), false);
+        for (int j = 1; j <= S; ++j) {
+            inner(level_op(P * j, 2, S, k0, 0));
+            outer(level_op(P * j + 1, 2, S, k0, 0), true);
+        }
+    } else {
+        inner(level_op(0, 2, S, k0, 1));
+        for (int j = 0; j < S; ++j) {
+            outer(level_op(P * j + 1, 2, S, k0, 1), true);
+            inner(level_op(P * (j + 1), 2, S, k0, 1));
+        }
     }
     store_tile<Real, R>(v, st, L0);
 }
@@ -673,38 +837,95 @@ __global__ void reduce_parts_kernel(const JobDev *jobs, JobDev inl, int parts) {
 
 // Raise the dynamic-LDS limit of a kernel once to the largest block any plan
 // uses, so that no attribute call happens while a stream is being captured.
-template <typename Real, int R>
+static std::mutex g_lds_mu;
+static std::set<const void *> g_lds_done;
+
 static hipError_t set_lds(const void *fn, size_t lds) {
-    (void)sizeof(Real);
-    static std::atomic<int> done{0};
-    if (lds <= 65536 || done.load(std::memory_order_acquire)) return hipSuccess;
+    if (lds <= 65536) return hipSuccess;
+    std::lock_guard<std::mutex> lk(g_lds_mu);
+    if (g_lds_done.count(fn)) return hipSuccess;
     hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, kMaxLdsBytes);
-    if (e == hipSuccess) done.store(1, std::memory_order_release);
+    if (e == hipSuccess) g_lds_done.insert(fn);
     return e;
+}
+
+template <typename Real, int R, bool NT>
+static hipError_t do_level_nt(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    const void *fn = reinterpret_cast<const void *>(&level_kernel<Real, R, NT>);
+    hipError_t e = set_lds(fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((level_kernel<Real, R, NT>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
+    return hipGetLastError();
+}
+
+template <typename Real, int R, int NL>
+static hipError_t do_level_full(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    const void *fn = reinterpret_cast<const void *>(&level_kernel_full<Real, R, NL>);
+    hipError_t e = set_lds(fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((level_kernel_full<Real, R, NL>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
+    return hipGetLastError();
+}
+
+// (R, NL) shapes compiled as straight-line kernels.
+#define Z2H_FULL_LEVEL_SHAPES(X) \
+    X(5, 1) X(5, 2) X(5, 3) X(4, 1) X(4, 2) X(4, 3) X(3, 1) X(3, 2) X(3, 3) X(2, 2) X(2, 3) X(2, 4)
+#define Z2H_FULL_RESIDENT_SHAPES(X) X(2, 4) X(4, 2) X(4, 3) X(3, 4) X(5, 2)
+
+bool full_level_ok(int R, int NL) {
+#define Z2H_OK_SHAPE(r, nl) if (R == r && NL == nl) return true;
+    Z2H_FULL_LEVEL_SHAPES(Z2H_OK_SHAPE)
+    return false;
+}
+
+bool full_resident_ok(int R, int NL) {
+    Z2H_FULL_RESIDENT_SHAPES(Z2H_OK_SHAPE)
+#undef Z2H_OK_SHAPE
+    return false;
+}
+
+template <typename Real>
+static hipError_t level_full_dispatch(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    const int R = a.geom.R, NL = a.geom.full;
+#define Z2H_CALL_SHAPE(r, nl) \
+    if (R == r && NL == nl) return do_level_full<Real, r, nl>(a, grid, lds, s);
+    Z2H_FULL_LEVEL_SHAPES(Z2H_CALL_SHAPE)
+#undef Z2H_CALL_SHAPE
+    return hipErrorInvalidValue;
 }
 
 template <typename Real, int R>
 static hipError_t do_level(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
-    const void *fn = reinterpret_cast<const void *>(&level_kernel<Real, R>);
-    hipError_t e = set_lds<Real, R>(fn, lds);
+    if (a.geom.m - R < 6 || a.geom.m - R > 9) return hipErrorInvalidConfiguration;  // launch bounds
+    if (a.geom.full) return level_full_dispatch<Real>(a, grid, lds, s);
+    return a.nt ? do_level_nt<Real, R, true>(a, grid, lds, s) : do_level_nt<Real, R, false>(a, grid, lds, s);
+}
+
+template <typename Real, int R, int NL>
+static hipError_t do_resident_shape(const ResidentArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    const void *fn = reinterpret_cast<const void *>(&resident_kernel<Real, R, NL>);
+    hipError_t e = set_lds(fn, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((level_kernel<Real, R>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
+    hipLaunchKernelGGL((resident_kernel<Real, R, NL>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
     return hipGetLastError();
 }
 
 template <typename Real, int R>
 static hipError_t do_resident(const ResidentArgs &a, dim3 grid, size_t lds, hipStream_t s) {
-    const void *fn = reinterpret_cast<const void *>(&resident_kernel<Real, R>);
-    hipError_t e = set_lds<Real, R>(fn, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((resident_kernel<Real, R>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
-    return hipGetLastError();
+    if (a.geom.m - R < 6 || a.geom.m - R > 9) return hipErrorInvalidConfiguration;  // launch bounds
+    const int NL = a.geom.full;
+#define Z2H_CALL_SHAPE(r, nl) \
+    if (R == r && NL == nl) return do_resident_shape<Real, r, nl>(a, grid, lds, s);
+    Z2H_FULL_RESIDENT_SHAPES(Z2H_CALL_SHAPE)
+#undef Z2H_CALL_SHAPE
+    return hipErrorInvalidValue;
 }
 
 template <typename Real, int R>
 static hipError_t do_obs(const ObsArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    if (a.geom.m - R < 6 || a.geom.m - R > 9) return hipErrorInvalidConfiguration;  // launch bounds
     const void *fn = reinterpret_cast<const void *>(&obs_kernel<Real, R>);
-    hipError_t e = set_lds<Real, R>(fn, lds);
+    hipError_t e = set_lds(fn, lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((obs_kernel<Real, R>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
     return hipGetLastError();
@@ -730,24 +951,29 @@ static hipError_t do_obs(const ObsArgs &a, dim3 grid, size_t lds, hipStream_t s)
         return hipErrorInvalidValue;                                       \
     } while (0)
 
-template <typename Real, int R>
-static hipError_t prep_one() {
-    hipError_t e = set_lds<Real, R>(reinterpret_cast<const void *>(&level_kernel<Real, R>), kMaxLdsBytes);
-    if (e == hipSuccess) e = set_lds<Real, R>(reinterpret_cast<const void *>(&resident_kernel<Real, R>), kMaxLdsBytes);
-    if (e == hipSuccess) e = set_lds<Real, R>(reinterpret_cast<const void *>(&obs_kernel<Real, R>), kMaxLdsBytes);
+template <typename Real>
+static hipError_t prep_real() {
+    hipError_t e = hipSuccess;
+#define Z2H_PREP_GEN(r)                                                                                   \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel<Real, r, false>), kMaxLdsBytes); \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel<Real, r, true>), kMaxLdsBytes);  \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&obs_kernel<Real, r>), kMaxLdsBytes);
+    Z2H_PREP_GEN(2) Z2H_PREP_GEN(3) Z2H_PREP_GEN(4) Z2H_PREP_GEN(5)
+#undef Z2H_PREP_GEN
+#define Z2H_PREP_FULL(r, nl) \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl>), kMaxLdsBytes);
+    Z2H_FULL_LEVEL_SHAPES(Z2H_PREP_FULL)
+#undef Z2H_PREP_FULL
+#define Z2H_PREP_RES(r, nl) \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&resident_kernel<Real, r, nl>), kMaxLdsBytes);
+    Z2H_FULL_RESIDENT_SHAPES(Z2H_PREP_RES)
+#undef Z2H_PREP_RES
     return e;
 }
 
 hipError_t prepare_kernels() {
-    hipError_t e = hipSuccess;
-    if (e == hipSuccess) e = prep_one<float, 2>();
-    if (e == hipSuccess) e = prep_one<float, 3>();
-    if (e == hipSuccess) e = prep_one<float, 4>();
-    if (e == hipSuccess) e = prep_one<float, 5>();
-    if (e == hipSuccess) e = prep_one<double, 2>();
-    if (e == hipSuccess) e = prep_one<double, 3>();
-    if (e == hipSuccess) e = prep_one<double, 4>();
-    if (e == hipSuccess) e = prep_one<double, 5>();
+    hipError_t e = prep_real<float>();
+    if (e == hipSuccess) e = prep_real<double>();
     return e;
 }
 

@@ -21,10 +21,10 @@ struct Plan {
     bool c128;
     size_t esize;
     int K;                       // groups (1: whole state in one workgroup)
-    int R;                       // log2 register elements per thread
     GroupGeom geom[kMaxGroups];
     LatticeDev lat;
     int device;
+    int nt;                      // streaming loads/stores in the pass kernels
 };
 
 namespace rt {

@@ -121,11 +121,16 @@ PLANS = [(2, 2, 0, 0), (2, 2, 1, 0), (2, 3, 0, 0), (2, 3, 1, 0), (3, 3, 0, 0), (
 def test_pass_geometry(Lx, Ly, dt, mtb):
     plan = z2h.z2h_plan_create(Lx, Ly, dt, mtb)
     d = z2h.z2h_plan_describe(plan)
-    n, R, K = d["n"], d["R"], d["K"]
+    n, K = d["n"], d["K"]
     assert K == len(d["groups"])
     covered = []
     for gi, g in enumerate(d["groups"]):
+        R = g["R"]
         m, c, b0, x0, x1 = g["m"], g["c"], g["b0"], g["x0"], g["x1"]
+        if g["full"]:
+            # straight-line kernels: NL complete windows at x1 - R (j + 1)
+            assert (x1 - x0) == g["full"] * R
+            assert g["p"] == [x1 - R * (j + 1) for j in range(g["full"])]
         threads = 1 << (m - R)
         assert 64 <= threads <= 512
         assert g["lds_bytes"] <= LDS_LIMIT
@@ -211,3 +216,13 @@ def test_loop_masks(Lx, Ly):
     assert mask_lib_to_oracle(Lx, Ly, zl[3]) == ol["W2"]
     assert mask_lib_to_oracle(Lx, Ly, xl[0]) == ol["V1"]
     assert mask_lib_to_oracle(Lx, Ly, xl[1]) == ol["V2"]
+
+
+@pytest.mark.parametrize("tune", ["uniform,m=13,R=3,c=4", "uniform,m=14,R=2,c=4", "uniform,m=8,R=5,c=4", "uniform,m=12,R=2,c=3"])
+def test_out_of_bounds_tunings_rejected(tune, monkeypatch):
+    """Tile/register choices that would exceed the kernels' launch bounds
+    (64..512 threads), the layout table or LDS are refused at plan creation."""
+    monkeypatch.setenv("Z2H_TUNE", tune)
+    with pytest.raises(z2h.Z2HError) as e:
+        z2h.z2h_plan_create(3, 3, z2h.Z2H_C64)
+    assert e.value.code == z2h.Z2H_ERR_UNSUPPORTED
