@@ -157,7 +157,8 @@ void z2h_plan_destroy(z2h_plan *plan); /* NULL-safe */
 
 /* state_bytes = 2^n * sizeof(complex); ws_evolve_bytes = workspace needed by
  * z2h_evolve; ws_observe_bytes = workspace needed by z2h_observe (includes a
- * state-sized scratch copy); ws_adjoint_bytes = workspace for z2h_adjoint. */
+ * state-sized scratch copy); ws_adjoint_bytes = workspace for z2h_adjoint
+ * without its per-step part: add 64 bytes per Trotter step plus 1024. */
 z2h_status z2h_plan_sizes(const z2h_plan *plan, size_t *state_bytes, size_t *ws_evolve_bytes,
                           size_t *ws_observe_bytes, size_t *ws_adjoint_bytes);
 
@@ -203,10 +204,16 @@ z2h_status z2h_observe(const z2h_plan *plan, const void *d_state, void *d_ws, si
  * Gradient of L = <psi_M| H(lossH) |psi_M> / <psi_M|psi_M> with respect to
  * the per-step schedule values sZ[k] and sX[k] (see z2h_schedule), by
  * reverse evolution with the inverse passes (every pass is unitary, so no
- * intermediate state is stored).  d_psi_final: the state after the full
- * forward ramp of sched (k_begin = 0, k_end = steps, renorm 0); it is not
- * modified.  d_gradZ, d_gradX: device arrays of steps doubles.  d_ws: at
- * least ws_adjoint_bytes.  h_loss (host, may be NULL): L, after a sync.
+ * intermediate state is stored):
+ *   dL/dsZ[k] = 2 dt Im <lambda|dH_Z/ds|psi> at the z pass of step k,
+ *   dL/dsX[k] = dt Im <lambda|dH_X/ds|psi> summed over its two x halves,
+ * with lambda = H psi_M carried backwards beside psi.  d_psi_final: the state
+ * after the full forward ramp of sched from its initial state (k_begin = 0,
+ * k_end = steps, order 0, renorm 0); it is not modified.  d_gradZ, d_gradX:
+ * device arrays of steps doubles.  d_ws: see z2h_plan_sizes.  h_loss (host,
+ * may be NULL): L.  The call synchronizes the stream once (to read L and the
+ * norm).  Plans whose transform groups have no straight-line kernel return
+ * Z2H_ERR_UNSUPPORTED.
  */
 z2h_status z2h_adjoint(const z2h_plan *plan, const void *d_psi_final, void *d_ws,
                        size_t ws_bytes, const z2h_schedule *sched, const z2h_couplings *lossH,

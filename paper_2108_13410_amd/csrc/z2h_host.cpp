@@ -745,7 +745,7 @@ z2h_status z2h_plan_sizes(const z2h_plan *plan, size_t *state_bytes, size_t *ws_
     if (state_bytes) *state_bytes = P.esize << P.n;
     if (ws_evolve_bytes) *ws_evolve_bytes = ws_evolve_size(P);
     if (ws_observe_bytes) *ws_observe_bytes = ws_observe_size(P);
-    if (ws_adjoint_bytes) *ws_adjoint_bytes = 0;
+    if (ws_adjoint_bytes) *ws_adjoint_bytes = ws_adjoint_size(P);
     return Z2H_OK;
 }
 

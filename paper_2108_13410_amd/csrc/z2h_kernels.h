@@ -73,6 +73,42 @@ struct InitArgs {
     LatticeDev lat;
 };
 
+// Reverse-sweep pass of the adjoint: operates on psi (A) and the adjoint
+// state lambda (B) with the same transforms, undoing one forward level.
+struct AdjArgs {
+    void *A, *B;               // A: psi (or the source of mode 2); B: lambda (or the destination of mode 2)
+    GroupGeom geom;
+    LatticeDev lat;
+    JobDev job;                // schedule of the forward ramp (couplings, dt, device sZ/sX)
+    LevelOp op;                // forward level being undone
+    int32_t mode;              // 0: plain transform of A (and B if set); 1: inverse phase of A and B with
+                               // gradient reduction; 2: B = diag * A (real diagonal of the energy)
+    int32_t no_transform;      // 1: act in the current basis without transforming the group
+    double dJ, dh;             // diagonal (nst - 2k) dJ + (n - 2w) dh: gradient weight (mode 1) or energy (mode 2)
+    double dscale;             // extra real factor of the mode-2 diagonal (2^-n in the Hadamard basis)
+    double *part;              // per-block partial sums of Im sum conj(B) D A (mode 1)
+};
+
+struct AdjFinalArgs {
+    const double *part;        // per-block partials of one level
+    int32_t np;                // number of partials
+    int32_t pad;
+    double *out;               // the level's sum
+};
+
+struct AdjGradArgs {
+    const double *level_sum;
+    double *gZ, *gX;
+    int32_t S, K, P, n;
+    double dt, inv_norm;
+};
+
+hipError_t launch_adj(bool c128, const AdjArgs &a, unsigned nblocks, size_t lds, hipStream_t s);
+hipError_t launch_adj_final(const AdjFinalArgs &a, hipStream_t s);
+hipError_t launch_adj_grad(const AdjGradArgs &a, hipStream_t s);
+hipError_t launch_axpy(bool c128, void *y, const void *x, uint64_t n, hipStream_t s);
+bool adj_shape_ok(int R, int NL);
+
 hipError_t launch_level(bool c128, int R, const LevelArgs &a, unsigned nblocks, size_t lds,
                         hipStream_t s);
 hipError_t launch_resident(bool c128, int R, const ResidentArgs &a, unsigned njobs, size_t lds,

@@ -655,6 +655,135 @@ __global__ void __launch_bounds__(512) resident_kernel(ResidentArgs a) {
     store_tile<Real, R>(v, st, L0);
 }
 
+// ---------------------------------------------------------------- adjoint
+//
+// Reverse evolution for the gradient of <psi_M|H|psi_M> with respect to the
+// per-step schedule values.  Every forward level is undone on psi and on the
+// adjoint state lambda = H psi_M with the same transforms and the conjugate
+// phase (the level's real scale factor is kept, so the scale bookkeeping of
+// the unnormalized transforms matches the forward sweep).  At a diagonal
+// level the sum Im sum_i conj(lambda_i) D_i psi_i is reduced in FP64, with
+// D = dH/ds diagonal in that basis.
+
+template <typename Real, int R>
+__device__ __forceinline__ double adj_reduce(const Cx<Real> (&a)[1 << R], const Cx<Real> (&b)[1 << R],
+                                             const LayCtx<R> &L, int basis, int nst, int n, double dJ, double dh) {
+    uint32_t s = basis ? L.s0x : L.s0z;
+    double acc = 0.0;
+#pragma unroll
+    for (int idx = 0; idx < (1 << R); ++idx) {
+        const int q = idx ^ (idx >> 1);
+        if (idx) s ^= basis ? L.lx[__builtin_ctz(idx)] : L.lz[__builtin_ctz(idx)];
+        const double im = (double)b[q].x * (double)a[q].y - (double)b[q].y * (double)a[q].x;
+        const int k = popc(s), w = L.w0 + __builtin_popcount(q);
+        acc += (dJ * (double)(nst - 2 * k) + dh * (double)(n - 2 * w)) * im;
+    }
+    return acc;
+}
+
+// Real diagonal table T[k][w] = scale (dJ (nst - 2k) + dh (n - 2w)), FP64 cast.
+template <typename Real>
+__device__ void build_diag_table(Cx<Real> *tab, int nst, int n, double dJ, double dh, double scale) {
+    const int W = n + 1;
+    for (int j = threadIdx.x; j < (nst + 1) * W; j += blockDim.x) {
+        const int k = j / W, w = j - k * W;
+        tab[j] = Cx<Real>{(Real)(scale * (dJ * (double)(nst - 2 * k) + dh * (double)(n - 2 * w))), (Real)0};
+    }
+    __syncthreads();
+}
+
+template <typename Real, int R, int NL>
+__global__ void __launch_bounds__(512) adj_kernel(AdjArgs a) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    const GroupGeom &g = a.geom;
+    const uint32_t t = threadIdx.x;
+    const uint64_t tile = blockIdx.x;
+    const int n = a.lat.n, nst = a.lat.nst, W = n + 1;
+    Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
+    const uint32_t lds_elems = (1u << g.m) + (1u << (g.m - R));
+    Cx<Real> *tab = lds + lds_elems;
+    double2 *fac = align16<double2>(tab + (nst + 1) * W);
+    double *red = reinterpret_cast<double *>(fac + (nst + 1 + W));
+    const int x1 = g.x1, p0 = x1 - R, pl = x1 - R * NL;
+    Cx<Real> *A = reinterpret_cast<Cx<Real> *>(a.A);
+    Cx<Real> *B = reinterpret_cast<Cx<Real> *>(a.B);
+    LayCtx<R> L0, Lm;
+    lay_ctx<R>(L0, g, a.lat, tile, p0, t, true);
+    lay_ctx<R>(Lm, g, a.lat, tile, a.no_transform ? p0 : pl, t, true);
+    Cx<Real> va[1 << R], vb[1 << R];
+
+    if (a.mode == 0) {
+        load_tile<Real, R>(va, A, L0);
+        fwd_full<Real, R, NL>(va, lds, x1, t);
+        if (NL > 1) xchg<Real, R>(va, lds, pl, p0, t);
+        store_tile<Real, R>(va, A, L0);
+        if (B) {
+            load_tile<Real, R>(vb, B, L0);
+            fwd_full<Real, R, NL>(vb, lds, x1, t);
+            if (NL > 1) xchg<Real, R>(vb, lds, pl, p0, t);
+            store_tile<Real, R>(vb, B, L0);
+        }
+        return;
+    }
+    if (a.mode == 2) {
+        build_diag_table<Real>(tab, nst, n, a.dJ, a.dh, a.dscale);
+        load_tile<Real, R>(va, A, L0);
+        if (!a.no_transform) fwd_full<Real, R, NL>(va, lds, x1, t);
+        apply_phase<Real, R>(va, Lm, a.op.basis, n, tab);
+        if (!a.no_transform) bwd_full<Real, R, NL>(va, lds, x1, t);
+        store_tile<Real, R>(va, B, L0);
+        return;
+    }
+    // mode 1: undo a diagonal level on both states, reducing the gradient
+    {
+        double alpha, beta;
+        phase_angles(a.job, a.op, alpha, beta);
+        const double scale = a.op.basis ? ldexp(1.0, -n) : 1.0;
+        build_table<Real>(tab, fac, nst, n, -alpha, -beta, scale);
+    }
+    load_tile<Real, R>(va, A, L0);
+    load_tile<Real, R>(vb, B, L0);
+    if (!a.no_transform) {
+        fwd_full<Real, R, NL>(va, lds, x1, t);
+        fwd_full<Real, R, NL>(vb, lds, x1, t);
+    }
+    const double acc = block_sum(adj_reduce<Real, R>(va, vb, Lm, a.op.basis, nst, n, a.dJ, a.dh), red);
+    if (t == 0 && a.part) a.part[tile] = acc;
+    apply_phase<Real, R>(va, Lm, a.op.basis, n, tab);
+    apply_phase<Real, R>(vb, Lm, a.op.basis, n, tab);
+    if (!a.no_transform) bwd_full<Real, R, NL>(va, lds, x1, t);
+    store_tile<Real, R>(va, A, L0);
+    if (!a.no_transform) bwd_full<Real, R, NL>(vb, lds, x1, t);
+    store_tile<Real, R>(vb, B, L0);
+}
+
+// Sum of one level's per-block partials (fixed order).
+__global__ void adj_final_kernel(AdjFinalArgs a) {
+    __shared__ double red[16];
+    double s = 0.0;
+    for (int j = threadIdx.x; j < a.np; j += blockDim.x) s += a.part[j];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) *a.out = s;
+}
+
+// Gradient of each schedule value from the level sums (x-z-x order): the
+// z part of step k sits at inner visit k + 1, its two x halves at outer
+// visits k and k + 1.
+__global__ void adj_grad_kernel(AdjGradArgs a) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= a.S) return;
+    const int inner = a.P * (k + 1);
+    const int outer0 = (a.K - 1) + a.P * k, outer1 = (a.K - 1) + a.P * (k + 1);
+    a.gZ[k] = 2.0 * a.dt * a.level_sum[inner] * a.inv_norm;
+    a.gX[k] = a.dt * ldexp(1.0, -a.n) * (a.level_sum[outer0] + a.level_sum[outer1]) * a.inv_norm;
+}
+
+template <typename Real>
+__global__ void axpy_kernel(Cx<Real> *y, const Cx<Real> *x, uint64_t n) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        y[i] = cadd(y[i], x[i]);
+}
+
 // ---------------------------------------------------------------- observables
 
 // Per-thread accumulation of one basis' observables for the elements in
@@ -871,6 +1000,7 @@ static hipError_t do_level_full(const LevelArgs &a, dim3 grid, size_t lds, hipSt
 #define Z2H_FULL_LEVEL_SHAPES(X) \
     X(5, 1) X(5, 2) X(5, 3) X(4, 1) X(4, 2) X(4, 3) X(3, 1) X(3, 2) X(3, 3) X(2, 2) X(2, 3) X(2, 4)
 #define Z2H_FULL_RESIDENT_SHAPES(X) X(2, 4) X(4, 2) X(4, 3) X(3, 4) X(5, 2)
+#define Z2H_ADJ_SHAPES(X) Z2H_FULL_LEVEL_SHAPES(X) X(3, 4)
 
 bool full_level_ok(int R, int NL) {
 #define Z2H_OK_SHAPE(r, nl) if (R == r && NL == nl) return true;
@@ -972,7 +1102,13 @@ static hipError_t prep_real() {
 }
 
 hipError_t prepare_kernels() {
-    hipError_t e = prep_real<float>();
+#define Z2H_PREP_ADJ(r, nl)                                                                               \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&adj_kernel<float, r, nl>), kMaxLdsBytes); \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&adj_kernel<double, r, nl>), kMaxLdsBytes);
+    hipError_t e = hipSuccess;
+    Z2H_ADJ_SHAPES(Z2H_PREP_ADJ)
+#undef Z2H_PREP_ADJ
+    if (e == hipSuccess) e = prep_real<float>();
     if (e == hipSuccess) e = prep_real<double>();
     return e;
 }
@@ -1006,6 +1142,55 @@ hipError_t launch_init(bool c128, const InitArgs &a, unsigned njobs, hipStream_t
         hipLaunchKernelGGL(init_kernel<double>, dim3((unsigned)blocks, njobs), dim3(256), 0, s, a);
     else
         hipLaunchKernelGGL(init_kernel<float>, dim3((unsigned)blocks, njobs), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+bool adj_shape_ok(int R, int NL) {
+#define Z2H_OK_SHAPE(r, nl) if (R == r && NL == nl) return true;
+    Z2H_ADJ_SHAPES(Z2H_OK_SHAPE)
+#undef Z2H_OK_SHAPE
+    return false;
+}
+
+template <typename Real, int R, int NL>
+static hipError_t do_adj(const AdjArgs &a, unsigned nblocks, size_t lds, hipStream_t s) {
+    const void *fn = reinterpret_cast<const void *>(&adj_kernel<Real, R, NL>);
+    hipError_t e = set_lds(fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((adj_kernel<Real, R, NL>), dim3(nblocks), dim3(1u << (a.geom.m - R)), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj(bool c128, const AdjArgs &a, unsigned nblocks, size_t lds, hipStream_t s) {
+    const int R = a.geom.R, NL = a.geom.full;
+    if (a.geom.m - R < 6 || a.geom.m - R > 9) return hipErrorInvalidConfiguration;  // launch bounds
+#define Z2H_CALL_SHAPE(r, nl)                                                                  \
+    if (R == r && NL == nl)                                                                    \
+        return c128 ? do_adj<double, r, nl>(a, nblocks, lds, s) : do_adj<float, r, nl>(a, nblocks, lds, s);
+    Z2H_ADJ_SHAPES(Z2H_CALL_SHAPE)
+#undef Z2H_CALL_SHAPE
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_adj_final(const AdjFinalArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(adj_final_kernel, dim3(1), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adj_grad(const AdjGradArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(adj_grad_kernel, dim3((a.S + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(bool c128, void *y, const void *x, uint64_t n, hipStream_t s) {
+    uint64_t blocks = (n + 255) / 256;
+    if (blocks > 16384) blocks = 16384;
+    if (c128)
+        hipLaunchKernelGGL(axpy_kernel<double>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           reinterpret_cast<Cx<double> *>(y), reinterpret_cast<const Cx<double> *>(x), n);
+    else
+        hipLaunchKernelGGL(axpy_kernel<float>, dim3((unsigned)blocks), dim3(256), 0, s,
+                           reinterpret_cast<Cx<float> *>(y), reinterpret_cast<const Cx<float> *>(x), n);
     return hipGetLastError();
 }
 

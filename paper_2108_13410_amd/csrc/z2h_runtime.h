@@ -65,6 +65,7 @@ size_t obs_records(const Plan &P);
 size_t norm_parts(const Plan &P);
 size_t ws_evolve_size(const Plan &P);
 size_t ws_observe_size(const Plan &P);
+size_t ws_adjoint_size(const Plan &P);
 
 z2h_status validate_state_ptr(const void *p, const char *what);
 z2h_status validate_schedule(const Plan &P, const z2h_schedule *s);
