@@ -251,6 +251,38 @@ void z2h_batch_destroy(z2h_batch *batch); /* NULL-safe */
  * and their order are the same).  Synchronizes. */
 z2h_status z2h_batch_timing(z2h_batch *batch, int64_t counts[4], double ms[4]);
 
+/* ------------------------------------------------------------------ tuning */
+
+/*
+ * Autotuner: times candidate pass schedules (transform-group split, register
+ * windows, tile size, carried contiguous bits, streaming loads) for Trotter
+ * steps of `batch` states of the lattice on the current device, and keeps
+ * the fastest for plans (batch 1) and batches of similar size (classes 1,
+ * 2..63, >= 64) of this lattice and precision created afterwards in this
+ * process.  If cache_path is not NULL the choice is appended to it (text,
+ * one "n c128 batch-class schedule" line per entry; z2h_tune_load or the
+ * environment variable Z2H_TUNE_CACHE read it back).  Allocates and frees
+ * device memory for the trial states (batch * state_bytes) and synchronizes
+ * the device.  best (may be NULL): the winning schedule string;
+ * best_ms_per_step (may be NULL): its time per Trotter step.
+ */
+z2h_status z2h_autotune(int32_t Lx, int32_t Ly, z2h_dtype dtype, int32_t batch, const char *cache_path,
+                        char *best, size_t best_len, double *best_ms_per_step);
+
+/* Plan with an explicit schedule string (as returned by z2h_autotune):
+ * "split=G:R:m:c/..." lists, from the lowest qubits up, each transform
+ * group's width G, register window 2^R, tile bits m and carried low bits c;
+ * "uniform,m=..,c=..,R=..,g0=.." is the general planner with fixed tile
+ * parameters.  Either may end in ",nt=1" (streaming loads and stores). */
+z2h_status z2h_plan_create_config(int32_t Lx, int32_t Ly, z2h_dtype dtype, const char *schedule,
+                                  z2h_plan **out);
+
+/* The autotuner's candidate schedules for a lattice, one per line (host). */
+z2h_status z2h_tune_candidates(int32_t Lx, int32_t Ly, z2h_dtype dtype, char *buf, size_t len);
+
+/* Load schedules written by z2h_autotune. */
+z2h_status z2h_tune_load(const char *cache_path);
+
 /* ------------------------------------------------------------------ misc */
 
 /* Enable (1) or disable (0) per-kernel event timing of the pass kernels

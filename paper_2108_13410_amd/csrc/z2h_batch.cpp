@@ -258,7 +258,9 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
             auto key = std::make_pair(Lx[j], Ly[j]);
             if (!gid.count(key)) {
                 Group g{};
-                st = make_plan(Lx[j], Ly[j], c128, 0, g.P);
+                int count = 0;
+                for (int i = 0; i < njobs; ++i) count += (Lx[i] == Lx[j] && Ly[i] == Ly[j]);
+                st = make_plan(Lx[j], Ly[j], c128, 0, g.P, count);
                 if (st) { free_batch(b); return st; }
                 g.P.device = b->device;
                 gid[key] = (int)b->groups.size();

@@ -7,7 +7,10 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
+#include <tuple>
 #include <string>
 #include <vector>
 
@@ -257,12 +260,24 @@ static int plan_cost(const Plan &P, const GroupChoice *ch, int K) {
     return 1000 * 2 * (K - 1) + 10 * exch + penalty;
 }
 
+struct SplitCand {
+    int cost, K;
+    GroupChoice g[kMaxGroups];
+};
+
 static bool search_full(const Plan &P, int K, int j, int b0, int m_pref, int m_hi, int c_min, GroupChoice *cur,
-                        GroupChoice *best, int &best_cost) {
+                        GroupChoice *best, int &best_cost, std::vector<SplitCand> *all = nullptr) {
     const int n = P.n;
     if (j == K) {
         if (b0 != n) return false;
         const int cost = plan_cost(P, cur, K);
+        if (all && cost < (1 << 29)) {
+            SplitCand sc;
+            sc.cost = cost;
+            sc.K = K;
+            for (int i = 0; i < K; ++i) sc.g[i] = cur[i];
+            all->push_back(sc);
+        }
         if (cost < best_cost) {
             best_cost = cost;
             for (int i = 0; i < K; ++i) best[i] = cur[i];
@@ -279,9 +294,35 @@ static bool search_full(const Plan &P, int K, int j, int b0, int m_pref, int m_h
             GroupChoice gc;
             if (!fit_group(P, j, b0, G, R, NL, m_pref, m_hi, c_min, gc)) continue;
             cur[j] = gc;
-            any |= search_full(P, K, j + 1, b0 + G, m_pref, m_hi, c_min, cur, best, best_cost);
+            any |= search_full(P, K, j + 1, b0 + G, m_pref, m_hi, c_min, cur, best, best_cost, all);
         }
     return any;
+}
+
+// Geometry of a given split (group widths, windows, tiles, carried bits).
+static z2h_status apply_split(Plan &P, const GroupChoice *ch, int K) {
+    const int n = P.n;
+    memset(P.geom, 0, sizeof P.geom);
+    P.K = K;
+    int b = 0;
+    for (int j = 0; j < K; ++j) {
+        GroupGeom &g = P.geom[j];
+        if (ch[j].G <= 0 || ch[j].R < 2 || ch[j].R > 5 || ch[j].m < ch[j].G || ch[j].m > 14)
+            return fail(Z2H_ERR_INVALID, "bad split group %d", j);
+        if (j == 0 && ch[j].c != 0) return fail(Z2H_ERR_INVALID, "group 0 carries no bits");
+        if (j > 0 && (ch[j].c > b || ch[j].m != ch[j].c + ch[j].G)) return fail(Z2H_ERR_INVALID, "bad split group %d", j);
+        g.R = ch[j].R;
+        g.m = ch[j].m;
+        g.c = ch[j].c;
+        g.b0 = j == 0 ? 0 : b;
+        g.x0 = g.c;
+        g.x1 = g.c + ch[j].G;
+        g.tiles_log2 = n - g.m;
+        plan_layouts(g, false);
+        b += ch[j].G;
+    }
+    if (b != n) return fail(Z2H_ERR_INVALID, "split covers %d of %d bits", b, n);
+    return check_block(P);
 }
 
 static z2h_status plan_full(Plan &P, int m_pref, int m_hi, int c_min) {
@@ -306,28 +347,12 @@ static z2h_status plan_full(Plan &P, int m_pref, int m_hi, int c_min) {
         int best_cost = 1 << 30;
         search_full(P, K, 0, 0, m_pref, m_hi, c_min, cur, best, best_cost);
         if (best_cost >= 1 << 29) continue;
-        P.K = K;
-        int b = 0;
-        for (int j = 0; j < K; ++j) {
-            GroupGeom &g = P.geom[j];
-            g.R = best[j].R;
-            g.m = best[j].m;
-            g.c = best[j].c;
-            g.b0 = j == 0 ? 0 : b;
-            g.x0 = g.c;
-            g.x1 = g.c + best[j].G;
-            g.tiles_log2 = n - g.m;
-            plan_layouts(g, false);
-            b += best[j].G;
-        }
-        return check_block(P);
+        return apply_split(P, best, K);
     }
     return fail(Z2H_ERR_UNSUPPORTED, "no full-window schedule for n = %d", n);
 }
 
-z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P) {
-    z2h_status st = check_lattice(Lx, Ly);
-    if (st) return st;
+static void plan_base(int Lx, int Ly, bool c128, Plan &P) {
     P.Lx = Lx;
     P.Ly = Ly;
     P.n = 2 * Lx * Ly;
@@ -336,25 +361,110 @@ z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P) {
     P.esize = c128 ? 16 : 8;
     P.lat = make_latdev(Lx, Ly);
     P.nt = 0;
-    const int c_min = c128 ? 3 : 4;           // 128-byte contiguous runs
-    const int m_lo = c128 ? 12 : 13;          // preferred tile (64 KiB + padding)
-    int m_hi = c128 ? 13 : 14;                // largest tile that fits in LDS
-    if (max_tile_bits) {
-        if (max_tile_bits < 8 || max_tile_bits > m_hi)
-            return fail(Z2H_ERR_INVALID, "max_tile_bits %d outside [8, %d]", max_tile_bits, m_hi);
-        m_hi = max_tile_bits;
+}
+
+// A schedule configuration string: "split=G:R:m:c/G:R:m:c/..." (groups from
+// the lowest qubits up) or "uniform,m=..,R=..,c=..,g0=.."; either may add
+// ",nt=1" (streaming loads and stores in the general pass kernel).
+static z2h_status plan_from_config(Plan &P, const char *cfg, int m_pref, int m_hi, int c_min) {
+    int v;
+    const char *q;
+    if ((q = strstr(cfg, "nt=")) && sscanf(q, "nt=%d", &v) == 1) P.nt = v ? 1 : 0;
+    if ((q = strstr(cfg, "split="))) {
+        GroupChoice ch[kMaxGroups];
+        int K = 0;
+        q += 6;
+        while (*q && K < kMaxGroups) {
+            int G, R, m, c, used = 0;
+            if (sscanf(q, "%d:%d:%d:%d%n", &G, &R, &m, &c, &used) != 4) break;
+            ch[K++] = {G, R, G / std::max(R, 1), m, c};
+            q += used;
+            if (*q != '/') break;
+            ++q;
+        }
+        if (K == 0) return fail(Z2H_ERR_INVALID, "unreadable split in \"%s\"", cfg);
+        return apply_split(P, ch, K);
     }
-    const int m_pref = std::min(m_lo, m_hi);
-    // Tuning override "m=..,R=..,c=..,g0=..,nt=.." selects the uniform planner.
+    if (strstr(cfg, "uniform")) {
+        int mp = m_pref, mh = m_hi, fR = 0, fg0 = 0, cm = c_min;
+        if ((q = strstr(cfg, "m=")) && sscanf(q, "m=%d", &v) == 1 && v >= 8 && v <= 14) mp = mh = v;
+        if ((q = strstr(cfg, "R=")) && sscanf(q, "R=%d", &v) == 1 && v >= 2 && v <= 5) fR = v;
+        if ((q = strstr(cfg, "c=")) && sscanf(q, "c=%d", &v) == 1 && v >= 0 && v <= 8) cm = v;
+        if ((q = strstr(cfg, "g0=")) && sscanf(q, "g0=%d", &v) == 1 && v >= 2) fg0 = v;
+        return plan_uniform(P, mp, mh, cm, fR, fg0);
+    }
+    return fail(Z2H_ERR_INVALID, "unknown schedule configuration \"%s\"", cfg);
+}
+
+// Schedules chosen by the autotuner, keyed by (n, precision, batch class).
+static std::mutex g_tune_mu;
+static std::map<std::tuple<int, int, int>, std::string> g_tuned;
+static bool g_tune_env_loaded = false;
+
+static int batch_class(int batch) { return batch <= 1 ? 1 : (batch < 64 ? 8 : 64); }
+
+static z2h_status tune_load_file(const char *path) {
+    FILE *f = fopen(path, "r");
+    if (!f) return fail(Z2H_ERR_INVALID, "cannot open tuning cache %s", path);
+    char line[512];
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    while (fgets(line, sizeof line, f)) {
+        int n, c128, bc;
+        char cfg[400];
+        if (line[0] == '#') continue;
+        if (sscanf(line, "%d %d %d %399s", &n, &c128, &bc, cfg) == 4) g_tuned[std::make_tuple(n, c128, bc)] = cfg;
+    }
+    fclose(f);
+    return Z2H_OK;
+}
+
+static std::string tuned_config(int n, bool c128, int batch) {
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        if (!g_tune_env_loaded) {
+            g_tune_env_loaded = true;
+            const char *pth = getenv("Z2H_TUNE_CACHE");
+            if (pth) {
+                g_tune_mu.unlock();
+                (void)tune_load_file(pth);
+                g_tune_mu.lock();
+            }
+        }
+        auto it = g_tuned.find(std::make_tuple(n, c128 ? 1 : 0, batch_class(batch)));
+        if (it != g_tuned.end()) return it->second;
+    }
+    return std::string();
+}
+
+static void plan_limits(bool c128, int max_tile_bits, int &m_pref, int &m_hi, int &c_min) {
+    c_min = c128 ? 3 : 4;                  // 128-byte contiguous runs
+    const int m_lo = c128 ? 12 : 13;       // preferred tile (64 KiB + padding)
+    m_hi = c128 ? 13 : 14;                 // largest tile that fits in LDS
+    if (max_tile_bits) m_hi = max_tile_bits;
+    m_pref = std::min(m_lo, m_hi);
+}
+
+z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P, int batch_hint) {
+    z2h_status st = check_lattice(Lx, Ly);
+    if (st) return st;
+    plan_base(Lx, Ly, c128, P);
+    if (max_tile_bits && (max_tile_bits < 8 || max_tile_bits > (c128 ? 13 : 14)))
+        return fail(Z2H_ERR_INVALID, "max_tile_bits %d outside [8, %d]", max_tile_bits, c128 ? 13 : 14);
+    int m_pref, m_hi, c_min;
+    plan_limits(c128, max_tile_bits, m_pref, m_hi, c_min);
+    // explicit override, then a tuned schedule, then the planner's own choice
     if (const char *tv = getenv("Z2H_TUNE")) {
-        int v, mp = m_pref, mh = m_hi, fR = 0, fg0 = 0, cm = c_min;
-        const char *q;
-        if ((q = strstr(tv, "m=")) && sscanf(q, "m=%d", &v) == 1 && v >= 8 && v <= 14) mp = mh = v;
-        if ((q = strstr(tv, "R=")) && sscanf(q, "R=%d", &v) == 1 && v >= 2 && v <= 5) fR = v;
-        if ((q = strstr(tv, "c=")) && sscanf(q, "c=%d", &v) == 1 && v >= 0 && v <= 8) cm = v;
-        if ((q = strstr(tv, "g0=")) && sscanf(q, "g0=%d", &v) == 1 && v >= 2) fg0 = v;
-        if ((q = strstr(tv, "nt=")) && sscanf(q, "nt=%d", &v) == 1) P.nt = v ? 1 : 0;
-        if (strstr(tv, "uniform")) return plan_uniform(P, mp, mh, cm, fR, fg0);
+        if (strstr(tv, "uniform") || strstr(tv, "split=")) return plan_from_config(P, tv, m_pref, m_hi, c_min);
+    }
+    if (!max_tile_bits) {
+        const std::string cfg = tuned_config(P.n, c128, batch_hint);
+        if (!cfg.empty()) {
+            Plan T = P;
+            if (plan_from_config(T, cfg.c_str(), m_pref, m_hi, c_min) == Z2H_OK) {
+                P = T;
+                return Z2H_OK;
+            }
+        }
     }
     // Straight-line full-window kernels unless they would cost extra passes
     // (HBM sweeps) per step compared with partial windows.
@@ -368,6 +478,64 @@ z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P) {
     }
     return st;
 }
+
+// Candidate schedules for the autotuner: every full-window split with the
+// fewest groups (and one more), plus uniform-window variants.
+std::vector<std::string> tune_candidates(int Lx, int Ly, bool c128) {
+    Plan P;
+    plan_base(Lx, Ly, c128, P);
+    int m_pref, m_hi, c_min;
+    plan_limits(c128, 0, m_pref, m_hi, c_min);
+    std::vector<std::string> out;
+    std::vector<SplitCand> all;
+    int Kbest = 0;
+    for (int K = 2; K <= kMaxGroups; ++K) {
+        for (int mp = std::max(10, m_pref - 1); mp <= m_hi; ++mp)
+            for (int cm = c_min; cm <= c_min + 2; ++cm) {
+                GroupChoice cur[kMaxGroups], best[kMaxGroups];
+                int bc = 1 << 30;
+                search_full(P, K, 0, 0, mp, m_hi, cm, cur, best, bc, &all);
+            }
+        if (!all.empty() && !Kbest) Kbest = K;
+        if (Kbest && K > Kbest) break;
+    }
+    std::sort(all.begin(), all.end(), [](const SplitCand &a, const SplitCand &b) { return a.cost < b.cost; });
+    for (const auto &sc : all) {
+        std::string cfg = "split=";
+        for (int j = 0; j < sc.K; ++j) {
+            char buf[64];
+            snprintf(buf, sizeof buf, "%s%d:%d:%d:%d", j ? "/" : "", sc.g[j].G, sc.g[j].R, sc.g[j].m, sc.g[j].c);
+            cfg += buf;
+        }
+        if (std::find(out.begin(), out.end(), cfg) == out.end()) out.push_back(cfg);
+        if (out.size() >= 16) break;
+    }
+    for (int m = m_hi - 2; m <= m_hi; ++m)
+        for (int c = c_min; c <= c_min + 1; ++c) {
+            char buf[96];
+            snprintf(buf, sizeof buf, "uniform,m=%d,c=%d,nt=1", m, c);
+            out.push_back(buf);
+        }
+    return out;
+}
+
+z2h_status plan_with_config(int Lx, int Ly, bool c128, const char *cfg, Plan &P) {
+    z2h_status st = check_lattice(Lx, Ly);
+    if (st) return st;
+    plan_base(Lx, Ly, c128, P);
+    int m_pref, m_hi, c_min;
+    plan_limits(c128, 0, m_pref, m_hi, c_min);
+    return plan_from_config(P, cfg, m_pref, m_hi, c_min);
+}
+
+void tune_store(int n, bool c128, int batch, const std::string &cfg) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[std::make_tuple(n, c128 ? 1 : 0, batch_class(batch))] = cfg;
+}
+
+z2h_status tune_load(const char *path) { return tune_load_file(path); }
+
+int tune_batch_class(int batch) { return batch_class(batch); }
 
 size_t lds_bytes(const Plan &P, const GroupGeom &g, int R) {
     const size_t elems = ((size_t)1 << g.m) + ((size_t)1 << (g.m - R));
@@ -718,7 +886,7 @@ z2h_status z2h_plan_create(int32_t Lx, int32_t Ly, z2h_dtype dtype, int32_t max_
         if (dtype != Z2H_C64 && dtype != Z2H_C128) return fail(Z2H_ERR_INVALID, "bad dtype %d", dtype);
         z2h_plan *p = new (std::nothrow) z2h_plan;
         if (!p) return fail(Z2H_ERR_OOM, "out of host memory");
-        z2h_status st = make_plan(Lx, Ly, dtype == Z2H_C128, max_tile_bits, p->P);
+        z2h_status st = make_plan(Lx, Ly, dtype == Z2H_C128, max_tile_bits, p->P, 1);
         if (st) {
             delete p;
             return st;

@@ -57,7 +57,12 @@ int link_bit(int Lx, int Ly, int x, int y, int dir);
 void build_masks(int Lx, int Ly, uint64_t *st, uint64_t *pl);
 z2h_status check_lattice(int Lx, int Ly);
 LatticeDev make_latdev(int Lx, int Ly);
-z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P);
+z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P, int batch_hint);
+z2h_status plan_with_config(int Lx, int Ly, bool c128, const char *cfg, Plan &P);
+std::vector<std::string> tune_candidates(int Lx, int Ly, bool c128);
+void tune_store(int n, bool c128, int batch, const std::string &cfg);
+z2h_status tune_load(const char *path);
+int tune_batch_class(int batch);
 size_t lds_bytes(const Plan &P, const GroupGeom &g, int R);
 size_t obs_lds_bytes(const Plan &P, const GroupGeom &g, int R);
 int obs_workers(const GroupGeom &g);

@@ -92,6 +92,10 @@ SIGNATURES = {
     "z2h_batch_run": (_i32, [_P, _P, _P, _sz, _P, _P]),
     "z2h_batch_destroy": (None, [_P]),
     "z2h_batch_timing": (_i32, [_P, _P, _P]),
+    "z2h_autotune": (_i32, [_i32, _i32, _i32, _i32, ctypes.c_char_p, ctypes.c_char_p, _sz, ctypes.POINTER(_dbl)]),
+    "z2h_tune_load": (_i32, [ctypes.c_char_p]),
+    "z2h_plan_create_config": (_i32, [_i32, _i32, _i32, ctypes.c_char_p, ctypes.POINTER(_P)]),
+    "z2h_tune_candidates": (_i32, [_i32, _i32, _i32, ctypes.c_char_p, _sz]),
     "z2h_timing_enable": (_i32, [_i32]),
     "z2h_timing_read": (_i32, [_P, _P]),
     "z2h_version": (ctypes.c_char_p, []),
@@ -328,6 +332,31 @@ def z2h_batch_timing(batch):
     m = np.zeros(4, np.float64)
     _check(lib().z2h_batch_timing(batch.handle, c.ctypes.data_as(_P), m.ctypes.data_as(_P)))
     return c, m
+
+
+def z2h_autotune(Lx, Ly, dtype, batch, cache_path=None):
+    """Returns (schedule string, ms per Trotter step) of the fastest candidate."""
+    buf = ctypes.create_string_buffer(512)
+    ms = ctypes.c_double()
+    _check(lib().z2h_autotune(Lx, Ly, dtype, batch, None if cache_path is None else cache_path.encode(),
+                              buf, len(buf), ctypes.byref(ms)))
+    return buf.value.decode(), ms.value
+
+
+def z2h_plan_create_config(Lx, Ly, dtype, schedule):
+    h = ctypes.c_void_p()
+    _check(lib().z2h_plan_create_config(Lx, Ly, dtype, schedule.encode(), ctypes.byref(h)))
+    return Plan(h, Lx, Ly, dtype)
+
+
+def z2h_tune_candidates(Lx, Ly, dtype):
+    buf = ctypes.create_string_buffer(16384)
+    _check(lib().z2h_tune_candidates(Lx, Ly, dtype, buf, len(buf)))
+    return [l for l in buf.value.decode().split("\n") if l]
+
+
+def z2h_tune_load(cache_path):
+    _check(lib().z2h_tune_load(cache_path.encode()))
 
 
 def z2h_timing_enable(on):

@@ -119,7 +119,26 @@ PLANS = [(2, 2, 0, 0), (2, 2, 1, 0), (2, 3, 0, 0), (2, 3, 1, 0), (3, 3, 0, 0), (
 
 @pytest.mark.parametrize("Lx,Ly,dt,mtb", PLANS)
 def test_pass_geometry(Lx, Ly, dt, mtb):
-    plan = z2h.z2h_plan_create(Lx, Ly, dt, mtb)
+    check_geometry(z2h.z2h_plan_create(Lx, Ly, dt, mtb))
+
+
+@pytest.mark.parametrize("Lx,Ly,dt", [(3, 3, 0), (3, 3, 1), (3, 4, 0), (4, 4, 0), (4, 4, 1)])
+def test_autotuner_candidates_are_valid_plans(Lx, Ly, dt):
+    """Every schedule the autotuner may pick builds a plan whose passes cover
+    each amplitude once and stay inside their buffers."""
+    cands = z2h.z2h_tune_candidates(Lx, Ly, dt)
+    assert len(cands) >= 4
+    for c in cands:
+        check_geometry(z2h.z2h_plan_create_config(Lx, Ly, dt, c))
+
+
+def test_schedule_strings_rejected():
+    for bad in ("split=10:5:13:0", "split=10:5:13:1/8:4:13:5", "split=10:5:13:0/8:4:19:11", "split=10:5:16:0/8:4:13:5", "nonsense"):
+        with pytest.raises(z2h.Z2HError):
+            z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C64, bad)
+
+
+def check_geometry(plan):
     d = z2h.z2h_plan_describe(plan)
     n, K = d["n"], d["K"]
     assert K == len(d["groups"])
