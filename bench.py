@@ -13,7 +13,16 @@ Trotter step), the roofline of the dominant pass kernel from HIP events
 recorded inside the timed graph launches, the plain complex128 per-point
 throughput on the same GPU, and the FP64 oracle timed on the host cores.
 
+Also measured (legs of their own, outside the timed region): a plain
+streaming copy and an in-place elementwise kernel of 2 GiB (the chip's
+achievable HBM rate), and the 4x4 torus (32 link qubits, 32 GiB complex64
+and 64 GiB complex128 states) ramped to (0.25, 0.25) in 200 steps, with the
+event-timed GB/s of every pass kind.
+
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+       python bench.py --pmc-summary FETCH_CSV WRITE_CSV   (host only: turns two
+           rocprofv3 --pmc counter files of this benchmark into the traffic
+           record read by later runs)
 """
 from __future__ import annotations
 
@@ -85,6 +94,135 @@ def plain_c128(jobs, z2h, torch, npoints):
     return dt / len(picks), res
 
 
+def copy_ceiling(torch, nbytes=1 << 31, reps=5):
+    """Achievable HBM rate on this device: torch's device-to-device copy of
+    nbytes (nbytes read + nbytes written) and an in-place elementwise kernel
+    over the same buffer, timed with events on the current stream."""
+    a = torch.empty(nbytes // 4, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    a.neg_()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    torch.cuda.synchronize()
+    ev[0].record()
+    for _ in range(reps):
+        b.copy_(a)
+    ev[1].record()
+    ev[2].record()
+    for _ in range(reps):
+        a.neg_()
+    ev[3].record()
+    torch.cuda.synchronize()
+    copy_ms = ev[0].elapsed_time(ev[1]) / reps
+    inpl_ms = ev[2].elapsed_time(ev[3]) / reps
+    del a, b
+    torch.cuda.empty_cache()
+    return {"bytes_each_way": nbytes,
+            "copy_GBps": 2 * nbytes / (copy_ms * 1e-3) / 1e9,
+            "inplace_GBps": 2 * nbytes / (inpl_ms * 1e-3) / 1e9}
+
+
+def four_by_four(z2h, torch):
+    """The 4x4 torus (32 link qubits): ramp from the toric code to
+    (0.25, 0.25), T = 20, M = 200, in complex64 (renormalised every step)
+    and complex128; event-timed GB/s per pass kind, energies, norm drift."""
+    from paper_2108_13410_amd import workloads
+    job = workloads.point_4x4()
+    M, n = job["M"], 32
+    zl, xl = z2h.z2h_loop_masks(4, 4)
+    res = {}
+    for name, dtype in (("c64", z2h.Z2H_C64), ("c128", z2h.Z2H_C128)):
+        b = 8 if dtype == z2h.Z2H_C64 else 16
+        plan = z2h.z2h_plan_create(4, 4, dtype)
+        sz = z2h.z2h_plan_sizes(plan)
+        info = z2h.z2h_plan_info(plan)
+        psi = z2h.alloc_state(plan)
+        ws = z2h.alloc_bytes(max(sz["ws_evolve"], sz["ws_observe"]))
+        norms = torch.zeros(M, dtype=torch.float64, device="cuda")
+        sched = z2h.schedule(job["c0"], job["c1"], M, job["T"] / M,
+                             renorm=1 if dtype == z2h.Z2H_C64 else 0)
+        z2h.z2h_state_init(plan, psi, z2h.Z2H_INIT_PSI1)
+        torch.cuda.synchronize()
+        z2h.z2h_timing_read()
+        z2h.z2h_timing_enable(True)
+        t0 = time.perf_counter()
+        z2h.z2h_evolve(plan, psi, ws, sched, norms=norms)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        counts, ms = z2h.z2h_timing_read()
+        z2h.z2h_timing_enable(False)
+        ob = z2h.z2h_observe(plan, psi, ws, job["c1"], zl, xl)
+        nrm = norms.cpu().numpy()
+        per_pass = 2 * (1 << n) * b
+        kinds = {}
+        for k, kname in enumerate(("z", "x", "plain")):
+            if counts[k]:
+                avg = ms[k] / counts[k]
+                kinds[kname] = {"launches": int(counts[k]), "avg_ms": avg,
+                                "GBps": per_pass / (avg * 1e-3) / 1e9}
+        res[name] = {
+            "schedule": z2h.z2h_plan_describe(plan), "passes_per_step": info["passes_per_step"],
+            "seconds": el, "amp_updates_per_s": (1 << n) * M / el,
+            "bytes_per_pass": per_pass, "pass": kinds,
+            "energy": ob["energy"], "norm": ob["norm"], "mx": ob["mx"], "mz": ob["mz"],
+            "wilson_1x3": ob["zloop"][0],
+            "max_step_norm_drift": float(abs(nrm - 1).max()),
+        }
+        del psi, ws, norms
+        z2h.z2h_plan_destroy(plan)
+        torch.cuda.empty_cache()
+        print(f"4x4 {name}: {el:.2f} s", file=sys.stderr, flush=True)
+    res["c64_vs_c128"] = {"energy_per_link": abs(res["c64"]["energy"] - res["c128"]["energy"]) / n,
+                          "mx": abs(res["c64"]["mx"] - res["c128"]["mx"]),
+                          "mz": abs(res["c64"]["mz"] - res["c128"]["mz"])}
+    return res
+
+
+def pmc_summary(fetch_csv, write_csv):
+    """Reduce two rocprofv3 --pmc runs of this benchmark (FETCH_SIZE, then
+    WRITE_SIZE; KiB per dispatch) to bytes per scan pass launch.  Each counter
+    is scaled by what it reads for the calibration copy of known size (the
+    largest device-to-device copy dispatch: bytes_each_way read and written)."""
+    import csv
+    import numpy as np
+
+    def load(path, counter):
+        rows = [r for r in csv.DictReader(open(path)) if r["Counter_Name"] == counter]
+        per = {}
+        for r in rows:
+            per.setdefault((r["Kernel_Name"], int(r["Grid_Size"])), []).append(float(r["Counter_Value"]))
+        return per
+
+    out = {"kernel_source_sha256_16": kernel_hash()}
+    scale = {}
+    for key, path, counter in (("fetch", fetch_csv, "FETCH_SIZE"), ("write", write_csv, "WRITE_SIZE")):
+        per = load(path, counter)
+        copies = {k: v for k, v in per.items() if "copyBuffer" in k[0]}
+        ck = max(copies, key=lambda k: k[1])
+        copy_kib = float(np.median(copies[ck]))
+        expect = 1 << 31
+        scale[key] = expect / (copy_kib * 1024.0)
+        passes = {k: v for k, v in per.items() if "level_kernel" in k[0] and k[1] >= (1 << 23)}
+        vals = [x for v in passes.values() for x in v]
+        if not vals:
+            raise SystemExit(f"{path}: no scan pass dispatches (level_kernel, grid >= 2^23) found")
+        out[key] = {"copy_kernel": ck[0], "copy_grid": ck[1], "copy_kib_per_dispatch": copy_kib,
+                    "copy_bytes_expected": expect, "scale": scale[key],
+                    "pass_dispatches": len(vals), "pass_kib_per_dispatch": float(np.mean(vals)),
+                    "per_kernel": {f"{k[0][:80]} grid={k[1]}": float(np.mean(v)) for k, v in passes.items()}}
+    fb = out["fetch"]["pass_kib_per_dispatch"] * 1024 * scale["fetch"]
+    wb = out["write"]["pass_kib_per_dispatch"] * 1024 * scale["write"]
+    out["bytes_per_launch"] = fb + wb
+    out["fetch_bytes_per_launch"] = fb
+    out["write_bytes_per_launch"] = wb
+    out["algorithmic_bytes_per_launch"] = 2 * 1024 * (1 << 18) * 8
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+    print(json.dumps({k: out[k] for k in ("bytes_per_launch", "fetch_bytes_per_launch",
+                                          "write_bytes_per_launch", "algorithmic_bytes_per_launch")}))
+
+
 def cpu_baseline(seconds_hint):
     """The FP64 oracle (test infrastructure, untuned) on one scan point."""
     import numpy as np  # noqa: F401
@@ -114,7 +252,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
+    ap.add_argument("--no-4x4", action="store_true")
+    ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--tune-cache", default=None,
+                    help="schedule cache: loaded if it exists, else written by the autotuner")
+    ap.add_argument("--pmc-summary", nargs=2, default=None, metavar=("FETCH_CSV", "WRITE_CSV"))
     args = ap.parse_args()
+    if args.pmc_summary:
+        pmc_summary(*args.pmc_summary)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the batched scan shards by job with no communication, "
               "and multi-GPU runs are not part of this build; use --gpus 1", file=sys.stderr)
@@ -133,9 +279,12 @@ def main():
     # the project's autotuner picks the pass schedule for this batch size
     # (and for single complex128 states) before anything is created
     tuned = {}
-    if not args.no_tune:
-        tuned["scan_c64"] = z2h.z2h_autotune(3, 3, z2h.Z2H_C64, nj)
-        tuned["plain_c128"] = z2h.z2h_autotune(3, 3, z2h.Z2H_C128, 1)
+    if args.tune_cache and os.path.exists(args.tune_cache):
+        z2h.z2h_tune_load(args.tune_cache)
+        print(f"schedules loaded from {args.tune_cache}", file=sys.stderr, flush=True)
+    elif not args.no_tune:
+        tuned["scan_c64"] = z2h.z2h_autotune(3, 3, z2h.Z2H_C64, nj, args.tune_cache)
+        tuned["plain_c128"] = z2h.z2h_autotune(3, 3, z2h.Z2H_C128, 1, args.tune_cache)
         print(f"autotuned: {tuned}", file=sys.stderr, flush=True)
     batch = make_batch(jobs, z2h.Z2H_C64, z2h)
     states = torch.empty(batch.states_bytes, dtype=torch.uint8, device="cuda")
@@ -208,6 +357,10 @@ def main():
         "pass_ms": {"z": float(ms[0]), "x": float(ms[1]), "plain": float(ms[2]),
                     "counts": [int(c) for c in counts[:3]]},
     }
+    if not args.no_copy:
+        line["copy_ceiling"] = copy_ceiling(torch)
+        line["roofline"]["frac_of_copy"] = achieved / line["copy_ceiling"]["copy_GBps"]
+        print(f"copy ceiling: {line['copy_ceiling']}", file=sys.stderr, flush=True)
     if not args.no_plain:
         per_point, res = plain_c128(jobs, z2h, torch, args.plain_points)
         err_e = max(abs(res[j][1] - obs_np[j][1]) / n for j in res)
@@ -222,6 +375,8 @@ def main():
             "max_abs_err_wilson": err_w,
         }
         print(f"plain c128: {per_point*1e3:.2f} ms/point", file=sys.stderr, flush=True)
+    if not args.no_4x4:
+        line["torus_4x4"] = four_by_four(z2h, torch)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(15)
     line["paper_context"] = {"rtx3090_c128_19q": ">= 0.8e7-1.8e7 link-amplitude-updates/s (derived "

@@ -108,7 +108,7 @@ typedef struct {
  * and <Z_l>.  zloop[j] = <prod over zmask_j of Z>, xloop[j] = <prod over
  * xmask_j of X> (Wilson and 't Hooft loops).  dos[w] = weight of psi on the
  * eigenvalue Ztilde = 2w - n of Ztilde = -sum_l Z_l (Sec. V), w = 0..n.
- * The same 48 doubles are the device output layout (index order below).
+ * The same 56 doubles are the device output layout (index order below).
  */
 typedef struct {
     double norm, energy, sumA, sumB, mx, mz; /* 0..5 */
