@@ -275,18 +275,7 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
                 if (!std::isfinite(h[k])) { free_batch(b); return fail(Z2H_ERR_INVALID, "job %d: observed couplings not finite", j); }
             b->groups[gid[key]].jobs.push_back(j);
         }
-        // state offsets in job order
-        b->byte_off.resize(njobs);
-        size_t off = 0;
-        for (int j = 0; j < njobs; ++j) {
-            off = align256(off);
-            b->byte_off[j] = off;
-            state_offsets[j] = off;
-            off += b->esize << (2 * Lx[j] * Ly[j]);
-        }
-        b->states_bytes = align256(off);
-        // per group: order jobs by decreasing level count, build records
-        size_t tbytes = 0;
+        // per group: order jobs by decreasing level count
         for (auto &g : b->groups) {
             const int Pp = 2 * (g.P.K - 1);
             auto nlev = [&](int j) {
@@ -296,6 +285,23 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
             std::stable_sort(g.jobs.begin(), g.jobs.end(), [&](int a, int c) {
                 return g.P.K == 1 ? sched[a].steps > sched[c].steps : nlev(a) > nlev(c);
             });
+        }
+        // state offsets: the states of a group are contiguous, in the group's
+        // job order, at the stride of one state (a multiple of 256 bytes)
+        b->byte_off.resize(njobs);
+        size_t off = 0;
+        for (auto &g : b->groups) {
+            for (int j : g.jobs) {
+                off = align256(off);
+                b->byte_off[j] = off;
+                state_offsets[j] = off;
+                off += b->esize << (2 * Lx[j] * Ly[j]);
+            }
+        }
+        b->states_bytes = align256(off);
+        // records
+        size_t tbytes = 0;
+        for (auto &g : b->groups) {
             for (int j : g.jobs) {
                 const uint64_t eoff = b->byte_off[j] / b->esize;
                 g.h_jobs.push_back(make_job(&sched[j], eoff));

@@ -663,8 +663,30 @@ void timed_end(hipStream_t s, hipEvent_t e0, hipEvent_t e1, int kind) {
 }
 
 // Launch one level for the jobs of J (all on the lattice of plan P).
+// Where the states of J start: a uniform stride lets the pass kernels issue
+// their tile loads before reading the job record.
+static void job_layout(const JobSet &J, LevelArgs &a) {
+    a.jmode = 1;
+    a.jbase = 0;
+    a.jstride = 0;
+    if (!J.d_jobs) {
+        a.jmode = 0;
+        a.jbase = J.inl.offset;
+        return;
+    }
+    if (!J.h_jobs || J.njobs <= 0) return;
+    const uint64_t b0 = J.h_jobs[0].offset;
+    const uint64_t st = J.njobs > 1 ? J.h_jobs[1].offset - b0 : 0;
+    for (int j = 0; j < J.njobs; ++j)
+        if (J.h_jobs[j].offset != b0 + (uint64_t)j * st) return;
+    a.jmode = 0;
+    a.jbase = b0;
+    a.jstride = st;
+}
+
 z2h_status launch_one_level(const Plan &P, void *states, const JobSet &J, int lev, int group,
-                                   int rn_parts, bool force_plain, int kind, hipStream_t s) {
+                                   int rn_parts, bool force_plain, int kind, hipStream_t s,
+                                   int kind_hint) {
     LevelArgs a;
     memset(&a, 0, sizeof a);
     a.states = states;
@@ -678,6 +700,8 @@ z2h_status launch_one_level(const Plan &P, void *states, const JobSet &J, int le
     a.rn_parts = rn_parts;
     a.force_plain = force_plain ? 1 : 0;
     a.nt = P.nt;
+    a.kind_hint = force_plain ? (int)kPlainH : kind_hint;
+    job_layout(J, a);
     const uint64_t nblocks = (uint64_t)J.njobs << a.geom.tiles_log2;
     if (nblocks > 0x7fffffffull) return fail(Z2H_ERR_UNSUPPORTED, "grid of %llu blocks", (unsigned long long)nblocks);
     const size_t lds = lds_bytes(P, a.geom, a.geom.R);
@@ -742,19 +766,22 @@ z2h_status run_levels(const Plan &P, void *states, const JobSet &J, hipStream_t 
         if (active == 0) break;
         // the visited group is the same for every job; the kind may differ
         LevelOp op{};
-        bool any_norm = false;
+        bool any_norm = false, uniform = true;
         for (int j = 0; j < active; ++j) {
             LevelOp o = level_op_host(lev, P.K, J.h_jobs[j].steps, J.h_jobs[j].k_begin, J.h_jobs[j].order);
             if (o.kind != kIdle) {
                 if (op.kind == kIdle) op = o;
+                else if (o.kind != op.kind) uniform = false;
                 any_norm = any_norm || o.norm;
+            } else {
+                uniform = false;
             }
         }
         if (op.kind == kIdle) continue;
         JobSet Ja = J;
         Ja.njobs = active;
         z2h_status st = launch_one_level(P, states, Ja, lev, op.group, big_parts ? 1 : parts0, false,
-                                         pass_kind_of(op), s);
+                                         pass_kind_of(op), s, uniform ? (int)op.kind : -1);
         if (st) return st;
         if (big_parts && any_norm) {
             hipError_t e = launch_reduce_parts(J.d_jobs, J.inl, active, parts0, s);

@@ -21,6 +21,10 @@ struct LevelArgs {
     int32_t rn_parts;          // partial norms to sum when a pass renormalizes
     int32_t force_plain;       // 1: plain transform of "group" regardless of the level
     int32_t nt;                // 1: nontemporal (streaming) loads and stores of the state
+    int32_t kind_hint;         // pass kind shared by every job of the launch, or -1
+    int32_t jmode;             // 0: job jb's state starts at jbase + jb * jstride (elements)
+                               // 1: at its record's offset
+    uint64_t jbase, jstride;
     JobDev job_inline;         // used when jobs is null (single state)
 };
 

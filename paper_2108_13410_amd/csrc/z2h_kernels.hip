@@ -192,10 +192,10 @@ __device__ __forceinline__ void store_tile(const Cx<Real> (&v)[1 << R], Cx<Real>
 }
 
 // Build the phase table T[k][w] = scale * exp(i (alpha (nst - 2k) + beta (n - 2w)))
-// in LDS (FP64 angles and products, cast to Real).
-template <typename Real>
-__device__ void build_table(Cx<Real> *tab, double2 *fac, int nst, int n, double alpha,
-                            double beta, double scale) {
+// in LDS (FP64 angles and products, cast to Real).  Two stages so that a
+// pass can compute the factors while its tile loads are in flight and apply
+// the scale (which may depend on a norm reduction) afterwards.
+__device__ __forceinline__ void table_factors(double2 *fac, int nst, int n, double alpha, double beta) {
     const int t = threadIdx.x, nt = blockDim.x;
     for (int j = t; j < nst + 1 + n + 1; j += nt) {
         double ang = j <= nst ? alpha * (double)(nst - 2 * j) : beta * (double)(n - 2 * (j - nst - 1));
@@ -203,6 +203,12 @@ __device__ void build_table(Cx<Real> *tab, double2 *fac, int nst, int n, double 
         sincos(ang, &s, &c);
         fac[j] = make_double2(c, s);
     }
+}
+
+template <typename Real>
+__device__ __forceinline__ void table_products(Cx<Real> *tab, const double2 *fac, int nst, int n,
+                                               double scale) {
+    const int t = threadIdx.x, nt = blockDim.x;
     __syncthreads();
     const int W = n + 1;
     for (int j = t; j < (nst + 1) * W; j += nt) {
@@ -213,6 +219,13 @@ __device__ void build_table(Cx<Real> *tab, double2 *fac, int nst, int n, double 
         tab[j] = Cx<Real>{(Real)re, (Real)im};
     }
     __syncthreads();
+}
+
+template <typename Real>
+__device__ void build_table(Cx<Real> *tab, double2 *fac, int nst, int n, double alpha,
+                            double beta, double scale) {
+    table_factors(fac, nst, n, alpha, beta);
+    table_products<Real>(tab, fac, nst, n, scale);
 }
 
 // Multiply every register element by T[k][w]: elements are visited in
@@ -231,15 +244,20 @@ __device__ __forceinline__ void apply_phase(Cx<Real> (&v)[1 << R], const LayCtx<
     }
 }
 
+// Sum of |v_q|^2 over a thread's register elements: pairwise in the storage
+// precision (complex64 steps accumulate in FP32), returned as FP64 for the
+// block and grid reductions.
 template <typename Real, int R>
 __device__ __forceinline__ double sumsq(const Cx<Real> (&v)[1 << R]) {
-    double acc = 0.0;
+    Real a[1 << R];
 #pragma unroll
-    for (int q = 0; q < (1 << R); ++q) {
-        const Real a = v[q].x * v[q].x + v[q].y * v[q].y;
-        acc += (double)a;
+    for (int q = 0; q < (1 << R); ++q) a[q] = v[q].x * v[q].x + v[q].y * v[q].y;
+#pragma unroll
+    for (int h = (1 << R) >> 1; h > 0; h >>= 1) {
+#pragma unroll
+        for (int q = 0; q < h; ++q) a[q] += a[q + h];
     }
-    return acc;
+    return (double)a[0];
 }
 
 __device__ __forceinline__ double wave_sum(double x) {
@@ -498,26 +516,64 @@ __device__ __forceinline__ void bwd_full(Cx<Real> (&v)[1 << R], Cx<Real> *lds, i
     }
 }
 
+// Finish the norm of the previous z pass (thread t already holds partial t)
+// and fold 1/sqrt(norm) into the phase table when the job renormalizes.
+template <typename Real>
+__device__ __forceinline__ void renorm_table(const LevelArgs &a, const JobDev &J, const LevelOp &op,
+                                             uint64_t tile, uint32_t t, double part, Cx<Real> *tab,
+                                             double *red) {
+    for (int j = (int)t + (int)blockDim.x; j < a.rn_parts; j += blockDim.x) part += J.norm_part[j];
+    const double s = block_sum(part, red);
+    if (tile == 0 && t == 0 && J.norm_trace) J.norm_trace[op.ka - J.k_begin] = s;
+    if (J.renorm) {
+        const Real f = (Real)(1.0 / sqrt(s));
+        const int entries = (a.lat.nst + 1) * (a.lat.n + 1);
+        for (int j = (int)t; j < entries; j += blockDim.x) {
+            tab[j].x *= f;
+            tab[j].y *= f;
+        }
+        __syncthreads();
+    }
+}
+
+// Rest of one tile of one pass, after its loads were issued (v in layout 0).
+// The phase table is built while the loads are in flight: FP64 factors and
+// unscaled products first; the renormalization factor (from the previous z
+// pass's block partials, whose load was issued after the tile's) is applied
+// to the table after the first transform, when those loads have landed.
 template <typename Real, int R, int NL, int KIND>
 __device__ __forceinline__ void pass_full(const LevelArgs &a, const JobDev &J, const LevelOp &op,
-                                          uint64_t tile, uint32_t t, Cx<Real> *lds, const Cx<Real> *tab,
-                                          double *red) {
+                                          uint64_t tile, uint32_t t, Cx<Real> (&v)[1 << R],
+                                          Cx<Real> *st, const LayCtx<R> &L0, Cx<Real> *lds,
+                                          Cx<Real> *tab, double2 *fac, double *red) {
     const GroupGeom &g = a.geom;
     const int x1 = g.x1;
     const int p0 = x1 - R, pl = x1 - R * NL;
-    Cx<Real> *st = reinterpret_cast<Cx<Real> *>(a.states) + J.offset;
-    Cx<Real> v[1 << R];
-    LayCtx<R> L0;
-    lay_ctx<R>(L0, g, a.lat, tile, p0, t, KIND == kHalfIn);
-    load_tile<Real, R, true>(v, st, L0);
+    constexpr bool kPhase = KIND != kPlainH;
+    const bool want_norm = kPhase && op.renorm && J.norm_part;
+    const int nst = a.lat.nst, n = a.lat.n;
+    double part = 0.0;
+    if constexpr (kPhase) {
+        if (want_norm && (int)t < a.rn_parts) part = J.norm_part[t];
+        double alpha, beta;
+        phase_angles(J, op, alpha, beta);
+        table_factors(fac, nst, n, alpha, beta);
+        table_products<Real>(tab, fac, nst, n, op.basis ? ldexp(1.0, -n) : 1.0);
+    }
     if constexpr (KIND == kHalfIn) {
+        if (want_norm) renorm_table<Real>(a, J, op, tile, t, part, tab, red);
+        LayCtx<R> Ls;
+        lay_ctx<R>(Ls, g, a.lat, tile, p0, t, true);
         if (op.norm) {
             const double s = block_sum(sumsq<Real, R>(v), red);
             if (t == 0 && J.norm_part) J.norm_part[tile] = s;
         }
-        apply_phase<Real, R>(v, L0, op.basis, a.lat.n, tab);
+        apply_phase<Real, R>(v, Ls, op.basis, n, tab);
     }
     fwd_full<Real, R, NL>(v, lds, x1, t);
+    if constexpr (kPhase && KIND != kHalfIn) {
+        if (want_norm) renorm_table<Real>(a, J, op, tile, t, part, tab, red);
+    }
     if constexpr (KIND == kPhaseB || KIND == kHalfOut) {
         LayCtx<R> Lm;
         lay_ctx<R>(Lm, g, a.lat, tile, pl, t, true);
@@ -527,7 +583,7 @@ __device__ __forceinline__ void pass_full(const LevelArgs &a, const JobDev &J, c
                 if (t == 0 && J.norm_part) J.norm_part[tile] = s;
             }
         }
-        apply_phase<Real, R>(v, Lm, op.basis, a.lat.n, tab);
+        apply_phase<Real, R>(v, Lm, op.basis, n, tab);
     }
     if constexpr (KIND == kPhaseB) {
         bwd_full<Real, R, NL>(v, lds, x1, t);
@@ -537,7 +593,14 @@ __device__ __forceinline__ void pass_full(const LevelArgs &a, const JobDev &J, c
     store_tile<Real, R, true>(v, st, L0);
 }
 
-template <typename Real, int R, int NL>
+// KS: the pass kind every job of the launch has at this level (kPhaseB or
+// kPlainH), or kAnyKind when the kinds differ or are rarer (half passes of
+// the z-x-z order) and each block selects its job's kind.  When jobs are laid out at a uniform stride
+// (a.jstride, elements; a.jmode 0) the tile loads are issued before the job
+// record is read.
+constexpr int kAnyKind = -1;
+
+template <typename Real, int R, int NL, int KS>
 __global__ void __launch_bounds__(512) level_kernel_full(LevelArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const GroupGeom &g = a.geom;
@@ -546,10 +609,22 @@ __global__ void __launch_bounds__(512) level_kernel_full(LevelArgs a) {
     const uint64_t bid = blockIdx.x;
     const int jb = (int)(bid >> g.tiles_log2);
     const uint64_t tile = bid & (tiles - 1);
+    Cx<Real> *base = reinterpret_cast<Cx<Real> *>(a.states);
+
+    Cx<Real> v[1 << R];
+    LayCtx<R> L0;
+    lay_ctx<R>(L0, g, a.lat, tile, g.x1 - R, t, false);
+    Cx<Real> *st = base + a.jbase + (uint64_t)jb * a.jstride;
+    if (a.jmode == 0) load_tile<Real, R, true>(v, st, L0);
+
     const JobDev J = a.jobs ? a.jobs[jb] : a.job_inline;
     const LevelOp op = a.force_plain ? LevelOp{a.group, kPlainH, 0, -1, -1, 0, 0, 0}
                                      : level_op(a.level, a.K, J.steps, J.k_begin, J.order);
     if (op.kind == kIdle || op.group != a.group) return;  // uniform per block
+    if (a.jmode != 0) {
+        st = base + J.offset;
+        load_tile<Real, R, true>(v, st, L0);
+    }
 
     Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
     const uint32_t lds_elems = (1u << g.m) + (1u << (g.m - R));
@@ -558,24 +633,15 @@ __global__ void __launch_bounds__(512) level_kernel_full(LevelArgs a) {
     double2 *fac = align16<double2>(tab + (a.lat.nst + 1) * W);
     double *red = reinterpret_cast<double *>(fac + (a.lat.nst + 1 + W));
 
-    if (op.kind != kPlainH) {
-        double alpha, beta;
-        phase_angles(J, op, alpha, beta);
-        double scale = op.basis ? ldexp(1.0, -a.lat.n) : 1.0;
-        if (op.renorm && J.norm_part) {
-            double s = 0.0;
-            for (int j = (int)t; j < a.rn_parts; j += blockDim.x) s += J.norm_part[j];
-            s = block_sum(s, red);
-            if (J.renorm) scale *= 1.0 / sqrt(s);
-            if (tile == 0 && t == 0 && J.norm_trace) J.norm_trace[op.ka - J.k_begin] = s;
+    if constexpr (KS != kAnyKind) {
+        pass_full<Real, R, NL, KS>(a, J, op, tile, t, v, st, L0, lds, tab, fac, red);
+    } else {
+        switch (op.kind) {
+            case kPhaseB: pass_full<Real, R, NL, kPhaseB>(a, J, op, tile, t, v, st, L0, lds, tab, fac, red); break;
+            case kPlainH: pass_full<Real, R, NL, kPlainH>(a, J, op, tile, t, v, st, L0, lds, tab, fac, red); break;
+            case kHalfIn: pass_full<Real, R, NL, kHalfIn>(a, J, op, tile, t, v, st, L0, lds, tab, fac, red); break;
+            default: pass_full<Real, R, NL, kHalfOut>(a, J, op, tile, t, v, st, L0, lds, tab, fac, red); break;
         }
-        build_table<Real>(tab, fac, a.lat.nst, a.lat.n, alpha, beta, scale);
-    }
-    switch (op.kind) {
-        case kPhaseB: pass_full<Real, R, NL, kPhaseB>(a, J, op, tile, t, lds, tab, red); break;
-        case kPlainH: pass_full<Real, R, NL, kPlainH>(a, J, op, tile, t, lds, tab, red); break;
-        case kHalfIn: pass_full<Real, R, NL, kHalfIn>(a, J, op, tile, t, lds, tab, red); break;
-        default: pass_full<Real, R, NL, kHalfOut>(a, J, op, tile, t, lds, tab, red); break;
     }
 }
 
@@ -987,13 +1053,20 @@ static hipError_t do_level_nt(const LevelArgs &a, dim3 grid, size_t lds, hipStre
     return hipGetLastError();
 }
 
-template <typename Real, int R, int NL>
-static hipError_t do_level_full(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
-    const void *fn = reinterpret_cast<const void *>(&level_kernel_full<Real, R, NL>);
+template <typename Real, int R, int NL, int KS>
+static hipError_t do_level_full_ks(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    const void *fn = reinterpret_cast<const void *>(&level_kernel_full<Real, R, NL, KS>);
     hipError_t e = set_lds(fn, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((level_kernel_full<Real, R, NL>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
+    hipLaunchKernelGGL((level_kernel_full<Real, R, NL, KS>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
     return hipGetLastError();
+}
+
+template <typename Real, int R, int NL>
+static hipError_t do_level_full(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    if (a.kind_hint == kPhaseB) return do_level_full_ks<Real, R, NL, kPhaseB>(a, grid, lds, s);
+    if (a.kind_hint == kPlainH) return do_level_full_ks<Real, R, NL, kPlainH>(a, grid, lds, s);
+    return do_level_full_ks<Real, R, NL, kAnyKind>(a, grid, lds, s);
 }
 
 // (R, NL) shapes compiled as straight-line kernels.
@@ -1091,7 +1164,9 @@ static hipError_t prep_real() {
     Z2H_PREP_GEN(2) Z2H_PREP_GEN(3) Z2H_PREP_GEN(4) Z2H_PREP_GEN(5)
 #undef Z2H_PREP_GEN
 #define Z2H_PREP_FULL(r, nl) \
-    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl>), kMaxLdsBytes);
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kAnyKind>), kMaxLdsBytes); \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kPhaseB>), kMaxLdsBytes); \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kPlainH>), kMaxLdsBytes);
     Z2H_FULL_LEVEL_SHAPES(Z2H_PREP_FULL)
 #undef Z2H_PREP_FULL
 #define Z2H_PREP_RES(r, nl) \

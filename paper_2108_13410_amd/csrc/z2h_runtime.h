@@ -102,7 +102,8 @@ struct JobSet {
 };
 
 z2h_status launch_one_level(const Plan &P, void *states, const JobSet &J, int lev, int group,
-                            int rn_parts, bool force_plain, int kind, hipStream_t s);
+                            int rn_parts, bool force_plain, int kind, hipStream_t s,
+                            int kind_hint = -1);
 z2h_status full_transform(const Plan &P, void *states, const JobSet &J, hipStream_t s);
 z2h_status run_levels(const Plan &P, void *states, const JobSet &J, hipStream_t s);
 
