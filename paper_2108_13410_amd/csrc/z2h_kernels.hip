@@ -42,9 +42,13 @@ __device__ __forceinline__ int popc(uint32_t v) { return __builtin_popcount(v); 
 
 // Next 16-byte boundary at or after p (LDS sub-buffers; the host sizes the
 // dynamic LDS block with the same rounding).
+// The padding is added to the original pointer (not rebuilt from an
+// integer) so the compiler still knows the result points into LDS and emits
+// ds_* instructions rather than flat ones for it.
 template <typename T, typename U>
 __device__ __forceinline__ T *align16(U *p) {
-    return reinterpret_cast<T *>((reinterpret_cast<uintptr_t>(p) + 15) & ~(uintptr_t)15);
+    const uintptr_t pad = (16u - (uint32_t)(reinterpret_cast<uintptr_t>(p) & 15u)) & 15u;
+    return reinterpret_cast<T *>(reinterpret_cast<unsigned char *>(p) + pad);
 }
 
 // Local index of register element q of thread t in layout p.
@@ -240,7 +244,7 @@ __device__ __forceinline__ void apply_phase(Cx<Real> (&v)[1 << R], const LayCtx<
     for (int idx = 0; idx < (1 << R); ++idx) {
         const int q = idx ^ (idx >> 1);
         if (idx) s ^= basis ? L.lx[__builtin_ctz(idx)] : L.lz[__builtin_ctz(idx)];
-        v[q] = cmul(v[q], tw[popc(s) * W + __builtin_popcount(q)]);
+        v[q] = cmul(v[q], tw[__umul24((uint32_t)popc(s), (uint32_t)W) + __builtin_popcount(q)]);
     }
 }
 
@@ -279,11 +283,35 @@ __device__ double block_sum(double x, double *red) {
     return s;
 }
 
+// Norm partials and traces live in global memory; accessing them through
+// global-address-space pointers keeps them off the LDS counter (generic
+// "flat" accesses count on both, and would make LDS waits wait for them).
+typedef __attribute__((address_space(1))) double *GlobalDoubles;
+__device__ __forceinline__ double gld(const double *p, int64_t i) { return ((GlobalDoubles)p)[i]; }
+__device__ __forceinline__ void gst(double *p, int64_t i, double v) { ((GlobalDoubles)p)[i] = v; }
+
+// Job records are read-only during a launch: read them through the constant
+// address space so that the (block-uniform) record is fetched with scalar
+// loads, whose completion does not wait on the block's outstanding tile loads.
+typedef const __attribute__((address_space(4))) uint32_t *ConstWords;
+static_assert(sizeof(JobDev) % 4 == 0, "job record is copied in 32-bit words");
+
+__device__ __forceinline__ JobDev job_record(const JobDev *jobs, int jb, const JobDev &inl) {
+    if (!jobs) return inl;
+    JobDev J;
+    uint32_t *d = reinterpret_cast<uint32_t *>(&J);
+    const ConstWords src = (ConstWords)(jobs + jb);
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(JobDev) / 4); ++i) d[i] = src[i];
+    return J;
+}
+
 // ---------------------------------------------------------------- schedule
 
 __device__ __forceinline__ double sched_s(const JobDev &J, int k, int zkind) {
+    typedef const __attribute__((address_space(4))) double *ConstDoubles;
     const double *arr = zkind ? J.sZ : J.sX;
-    if (arr) return arr[k];
+    if (arr) return ((ConstDoubles)arr)[k];  // read-only; scalar load
     return J.sampling ? (double)(k + 1) / (double)J.M : ((double)k + 0.5) / (double)J.M;
 }
 
@@ -379,7 +407,7 @@ __global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
     const uint64_t bid = blockIdx.x;
     const int jb = (int)(bid >> g.tiles_log2);
     const uint64_t tile = bid & (tiles - 1);
-    const JobDev J = a.jobs ? a.jobs[jb] : a.job_inline;
+    const JobDev J = job_record(a.jobs, jb, a.job_inline);
     const LevelOp op = a.force_plain ? LevelOp{a.group, kPlainH, 0, -1, -1, 0, 0, 0}
                                      : level_op(a.level, a.K, J.steps, J.k_begin, J.order);
     if (op.kind == kIdle || op.group != a.group) return;  // uniform per block
@@ -402,10 +430,10 @@ __global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
         double scale = op.basis ? ldexp(1.0, -a.lat.n) : 1.0;
         if (op.renorm && J.norm_part) {
             double s = 0.0;
-            for (int j = (int)t; j < a.rn_parts; j += blockDim.x) s += J.norm_part[j];
+            for (int j = (int)t; j < a.rn_parts; j += blockDim.x) s += gld(J.norm_part, j);
             s = block_sum(s, red);
             if (J.renorm) scale *= 1.0 / sqrt(s);
-            if (tile == 0 && t == 0 && J.norm_trace) J.norm_trace[op.ka - J.k_begin] = s;
+            if (tile == 0 && t == 0 && J.norm_trace) gst(J.norm_trace, op.ka - J.k_begin, s);
         }
         build_table<Real>(tab, fac, a.lat.nst, a.lat.n, alpha, beta, scale);
     }
@@ -430,7 +458,7 @@ __global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
         lay_ctx<R>(Lm, g, a.lat, tile, g.p[cur], t, has_phase);
         if (op.norm) {
             double s = block_sum(sumsq<Real, R>(v), red);
-            if (t == 0 && J.norm_part) J.norm_part[tile] = s;
+            if (t == 0 && J.norm_part) gst(J.norm_part, tile, s);
         }
         if (has_phase) apply_phase<Real, R>(v, Lm, op.basis, a.lat.n, tab);
     }
@@ -522,9 +550,9 @@ template <typename Real>
 __device__ __forceinline__ void renorm_table(const LevelArgs &a, const JobDev &J, const LevelOp &op,
                                              uint64_t tile, uint32_t t, double part, Cx<Real> *tab,
                                              double *red) {
-    for (int j = (int)t + (int)blockDim.x; j < a.rn_parts; j += blockDim.x) part += J.norm_part[j];
+    for (int j = (int)t + (int)blockDim.x; j < a.rn_parts; j += blockDim.x) part += gld(J.norm_part, j);
     const double s = block_sum(part, red);
-    if (tile == 0 && t == 0 && J.norm_trace) J.norm_trace[op.ka - J.k_begin] = s;
+    if (tile == 0 && t == 0 && J.norm_trace) gst(J.norm_trace, op.ka - J.k_begin, s);
     if (J.renorm) {
         const Real f = (Real)(1.0 / sqrt(s));
         const int entries = (a.lat.nst + 1) * (a.lat.n + 1);
@@ -554,7 +582,7 @@ __device__ __forceinline__ void pass_full(const LevelArgs &a, const JobDev &J, c
     const int nst = a.lat.nst, n = a.lat.n;
     double part = 0.0;
     if constexpr (kPhase) {
-        if (want_norm && (int)t < a.rn_parts) part = J.norm_part[t];
+        if (want_norm && (int)t < a.rn_parts) part = gld(J.norm_part, t);
         double alpha, beta;
         phase_angles(J, op, alpha, beta);
         table_factors(fac, nst, n, alpha, beta);
@@ -566,7 +594,7 @@ __device__ __forceinline__ void pass_full(const LevelArgs &a, const JobDev &J, c
         lay_ctx<R>(Ls, g, a.lat, tile, p0, t, true);
         if (op.norm) {
             const double s = block_sum(sumsq<Real, R>(v), red);
-            if (t == 0 && J.norm_part) J.norm_part[tile] = s;
+            if (t == 0 && J.norm_part) gst(J.norm_part, tile, s);
         }
         apply_phase<Real, R>(v, Ls, op.basis, n, tab);
     }
@@ -580,7 +608,7 @@ __device__ __forceinline__ void pass_full(const LevelArgs &a, const JobDev &J, c
         if constexpr (KIND == kPhaseB) {
             if (op.norm) {
                 const double s = block_sum(sumsq<Real, R>(v), red);
-                if (t == 0 && J.norm_part) J.norm_part[tile] = s;
+                if (t == 0 && J.norm_part) gst(J.norm_part, tile, s);
             }
         }
         apply_phase<Real, R>(v, Lm, op.basis, n, tab);
@@ -617,7 +645,7 @@ __global__ void __launch_bounds__(512) level_kernel_full(LevelArgs a) {
     Cx<Real> *st = base + a.jbase + (uint64_t)jb * a.jstride;
     if (a.jmode == 0) load_tile<Real, R, true>(v, st, L0);
 
-    const JobDev J = a.jobs ? a.jobs[jb] : a.job_inline;
+    const JobDev J = job_record(a.jobs, jb, a.job_inline);
     const LevelOp op = a.force_plain ? LevelOp{a.group, kPlainH, 0, -1, -1, 0, 0, 0}
                                      : level_op(a.level, a.K, J.steps, J.k_begin, J.order);
     if (op.kind == kIdle || op.group != a.group) return;  // uniform per block
@@ -657,7 +685,7 @@ __global__ void __launch_bounds__(512) resident_kernel(ResidentArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const GroupGeom &g = a.geom;
     const uint32_t t = threadIdx.x;
-    const JobDev J = a.jobs ? a.jobs[a.job0 + blockIdx.x] : a.job_inline;
+    const JobDev J = job_record(a.jobs, a.job0 + blockIdx.x, a.job_inline);
     const int S = J.steps, k0 = J.k_begin;
     if (S <= 0) return;
     const int n = a.lat.n, nst = a.lat.nst, W = n + 1;
@@ -686,7 +714,7 @@ __global__ void __launch_bounds__(512) resident_kernel(ResidentArgs a) {
         double scale = two_mn;
         if (op.renorm && have_norm) {
             if (J.renorm) scale *= 1.0 / sqrt(last_norm);
-            if (t == 0 && J.norm_trace) J.norm_trace[op.ka - k0] = last_norm;
+            if (t == 0 && J.norm_trace) gst(J.norm_trace, op.ka - k0, last_norm);
         }
         build_table<Real>(tab, fac, nst, n, alpha, beta, scale);
         fwd_full<Real, R, NL>(v, lds, x1, t);
@@ -1023,9 +1051,9 @@ __global__ void reduce_parts_kernel(const JobDev *jobs, JobDev inl, int parts) {
     const JobDev J = jobs ? jobs[blockIdx.x] : inl;
     if (!J.norm_part) return;
     double s = 0.0;
-    for (int j = threadIdx.x; j < parts; j += blockDim.x) s += J.norm_part[j];
+    for (int j = threadIdx.x; j < parts; j += blockDim.x) s += gld(J.norm_part, j);
     s = block_sum(s, red);
-    if (threadIdx.x == 0) J.norm_part[0] = s;
+    if (threadIdx.x == 0) gst(J.norm_part, 0, s);
 }
 
 // ---------------------------------------------------------------- launchers
