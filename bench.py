@@ -123,7 +123,20 @@ def copy_ceiling(torch, nbytes=1 << 31, reps=5):
             "inplace_GBps": 2 * nbytes / (inpl_ms * 1e-3) / 1e9}
 
 
-def four_by_four(z2h, torch):
+def cache_has(path, n, c128):
+    """Whether a schedule cache written by the autotuner has an entry for n
+    qubits in this precision (lines: n c128 batch-class schedule)."""
+    if not path or not os.path.exists(path):
+        return False
+    with open(path) as f:
+        for ln in f:
+            p = ln.split()
+            if len(p) >= 4 and p[0] == str(n) and p[1] == ("1" if c128 else "0"):
+                return True
+    return False
+
+
+def four_by_four(z2h, torch, tune=True, tune_cache=None):
     """The 4x4 torus (32 link qubits): ramp from the toric code to
     (0.25, 0.25), T = 20, M = 200, in complex64 (renormalised every step)
     and complex128; event-timed GB/s per pass kind, energies, norm drift."""
@@ -134,6 +147,13 @@ def four_by_four(z2h, torch):
     res = {}
     for name, dtype in (("c64", z2h.Z2H_C64), ("c128", z2h.Z2H_C128)):
         b = 8 if dtype == z2h.Z2H_C64 else 16
+        tuned = None
+        if tune:
+            if cache_has(tune_cache, 32, dtype == z2h.Z2H_C128):
+                z2h.z2h_tune_load(tune_cache)
+            else:
+                tuned = z2h.z2h_autotune(4, 4, dtype, 1, tune_cache)
+                print(f"4x4 {name} autotuned: {tuned}", file=sys.stderr, flush=True)
         plan = z2h.z2h_plan_create(4, 4, dtype)
         sz = z2h.z2h_plan_sizes(plan)
         info = z2h.z2h_plan_info(plan)
@@ -163,6 +183,7 @@ def four_by_four(z2h, torch):
                                 "GBps": per_pass / (avg * 1e-3) / 1e9}
         res[name] = {
             "schedule": z2h.z2h_plan_describe(plan), "passes_per_step": info["passes_per_step"],
+            "autotuned": None if tuned is None else {"config": tuned[0], "ms_per_trotter_step": tuned[1]},
             "seconds": el, "amp_updates_per_s": (1 << n) * M / el,
             "bytes_per_pass": per_pass, "pass": kinds,
             "energy": ob["energy"], "norm": ob["norm"], "mx": ob["mx"], "mz": ob["mz"],
@@ -279,7 +300,7 @@ def main():
     # the project's autotuner picks the pass schedule for this batch size
     # (and for single complex128 states) before anything is created
     tuned = {}
-    if args.tune_cache and os.path.exists(args.tune_cache):
+    if cache_has(args.tune_cache, 18, False) and cache_has(args.tune_cache, 18, True):
         z2h.z2h_tune_load(args.tune_cache)
         print(f"schedules loaded from {args.tune_cache}", file=sys.stderr, flush=True)
     elif not args.no_tune:
@@ -376,7 +397,7 @@ def main():
         }
         print(f"plain c128: {per_point*1e3:.2f} ms/point", file=sys.stderr, flush=True)
     if not args.no_4x4:
-        line["torus_4x4"] = four_by_four(z2h, torch)
+        line["torus_4x4"] = four_by_four(z2h, torch, not args.no_tune, args.tune_cache)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(15)
     line["paper_context"] = {"rtx3090_c128_19q": ">= 0.8e7-1.8e7 link-amplitude-updates/s (derived "

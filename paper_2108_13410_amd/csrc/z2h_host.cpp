@@ -33,13 +33,6 @@ z2h_status fail(z2h_status code, const char *fmt, ...) {
     return code;
 }
 
-#define HIP_TRY(expr)                                                                  \
-    do {                                                                               \
-        hipError_t e_ = (expr);                                                        \
-        if (e_ != hipSuccess)                                                          \
-            return fail(Z2H_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));   \
-    } while (0)
-
 // ------------------------------------------------------------------ lattice
 
 // Library numbering (see the header): h(x,y) = y*Lx + x, v(x,y) = Lx*Ly + y*Lx + x.
@@ -479,8 +472,36 @@ z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P, int 
     return st;
 }
 
-// Candidate schedules for the autotuner: every full-window split with the
-// fewest groups (and one more), plus uniform-window variants.
+// Tile options of one group of a split: every (m, c) whose block size is
+// within the launch bounds and whose tile fits LDS, with contiguous runs of
+// at least 64 bytes for groups that carry low bits.
+static std::vector<std::pair<int, int>> group_tiles(const Plan &P, int j, int b0, int G, int R, int m_hi) {
+    std::vector<std::pair<int, int>> out;
+    auto lds_ok = [&](int m) {
+        GroupGeom g{};
+        g.m = m;
+        g.R = R;
+        return lds_bytes(P, g, R) <= (size_t)kMaxLdsBytes;
+    };
+    const int c_lo = P.c128 ? 2 : 3;
+    if (j == 0) {
+        for (int m = G; m <= std::min(m_hi, P.n); ++m)
+            if (m - R >= 6 && m - R <= 9 && lds_ok(m)) out.push_back({m, 0});
+        return out;
+    }
+    for (int c = c_lo; c <= b0; ++c) {
+        const int m = c + G;
+        if (m > m_hi) break;
+        if (m - R >= 6 && m - R <= 9 && lds_ok(m)) out.push_back({m, c});
+    }
+    return out;
+}
+
+// Candidate schedules for the autotuner.  Structures (group widths and
+// register windows) come from the full-window planner with the fewest groups
+// (and one more); for each structure every combination of per-group tile
+// options is a candidate, best-ranked structures first.  Uniform-window
+// schedules follow.
 std::vector<std::string> tune_candidates(int Lx, int Ly, bool c128) {
     Plan P;
     plan_base(Lx, Ly, c128, P);
@@ -499,16 +520,36 @@ std::vector<std::string> tune_candidates(int Lx, int Ly, bool c128) {
         if (!all.empty() && !Kbest) Kbest = K;
         if (Kbest && K > Kbest) break;
     }
-    std::sort(all.begin(), all.end(), [](const SplitCand &a, const SplitCand &b) { return a.cost < b.cost; });
+    std::stable_sort(all.begin(), all.end(), [](const SplitCand &a, const SplitCand &b) { return a.cost < b.cost; });
+    std::vector<std::string> seen_struct;
+    const size_t kMaxCands = 64;
     for (const auto &sc : all) {
-        std::string cfg = "split=";
+        std::string key;
+        for (int j = 0; j < sc.K; ++j) key += std::to_string(sc.g[j].G) + ":" + std::to_string(sc.g[j].R) + "/";
+        if (std::find(seen_struct.begin(), seen_struct.end(), key) != seen_struct.end()) continue;
+        seen_struct.push_back(key);
+        std::vector<std::vector<std::pair<int, int>>> opts(sc.K);
+        int b0 = 0;
+        size_t combos = 1;
         for (int j = 0; j < sc.K; ++j) {
-            char buf[64];
-            snprintf(buf, sizeof buf, "%s%d:%d:%d:%d", j ? "/" : "", sc.g[j].G, sc.g[j].R, sc.g[j].m, sc.g[j].c);
-            cfg += buf;
+            opts[j] = group_tiles(P, j, b0, sc.g[j].G, sc.g[j].R, m_hi);
+            b0 += sc.g[j].G;
+            combos *= opts[j].size();
         }
-        if (std::find(out.begin(), out.end(), cfg) == out.end()) out.push_back(cfg);
-        if (out.size() >= 16) break;
+        if (combos == 0) continue;
+        for (size_t idx = 0; idx < combos && out.size() < kMaxCands; ++idx) {
+            std::string cfg = "split=";
+            size_t r = idx;
+            for (int j = 0; j < sc.K; ++j) {
+                const auto &o = opts[j][r % opts[j].size()];
+                r /= opts[j].size();
+                char buf[64];
+                snprintf(buf, sizeof buf, "%s%d:%d:%d:%d", j ? "/" : "", sc.g[j].G, sc.g[j].R, o.first, o.second);
+                cfg += buf;
+            }
+            if (std::find(out.begin(), out.end(), cfg) == out.end()) out.push_back(cfg);
+        }
+        if (out.size() >= kMaxCands) break;
     }
     for (int m = m_hi - 2; m <= m_hi; ++m)
         for (int c = c_min; c <= c_min + 1; ++c) {

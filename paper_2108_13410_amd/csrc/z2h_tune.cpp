@@ -150,15 +150,21 @@ z2h_status z2h_autotune(int32_t Lx, int32_t Ly, z2h_dtype dtype, int32_t batch, 
         for (const auto &cfg : cands) {
             Plan P;
             if (plan_with_config(Lx, Ly, c128, cfg.c_str(), P) != Z2H_OK) continue;
-            float a2 = 0, a6 = 0, w = 0;
-            // warm-up, then the difference of a 6-step and a 2-step ramp
-            // removes the first and last transform passes
+            float alo = 0, ahi = 0, w = 0;
+            // warm-up, then the difference of a long and a short ramp removes
+            // the first and last transform passes; large states (a warm-up
+            // above 50 ms) are timed once over fewer steps
             if ((st = time_steps(P, B, batch, 2, s, w))) return st;
+            // a 2-step ramp is about 3 steps of passes: skip candidates whose
+            // warm-up is far behind the best so far
+            if (best_t < 1e300 && w > 1.5 * 3.0 * best_t) continue;
+            const bool big = w > 50.0f;
+            const int lo = big ? 1 : 2, hi = big ? 3 : 6, reps = big ? 1 : 2;
             double t = 1e300;
-            for (int r = 0; r < 2; ++r) {
-                if ((st = time_steps(P, B, batch, 2, s, a2))) return st;
-                if ((st = time_steps(P, B, batch, 6, s, a6))) return st;
-                t = std::min(t, (double)(a6 - a2) / 4.0);
+            for (int r = 0; r < reps; ++r) {
+                if ((st = time_steps(P, B, batch, lo, s, alo))) return st;
+                if ((st = time_steps(P, B, batch, hi, s, ahi))) return st;
+                t = std::min(t, (double)(ahi - alo) / (double)(hi - lo));
             }
             if (t < best_t) {
                 best_t = t;
