@@ -39,6 +39,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, GB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_scan_3x3_c64.json")
+# schedules chosen by the autotuner on an MI355X (lines: n c128 batch-class schedule)
+SHIPPED_TABLE = os.path.join(ROOT, "paper_2108_13410_amd", "tuned_mi355x.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2108_13410_amd", "csrc", "z2h_kernels.hip")
 
 
@@ -152,7 +154,7 @@ def four_by_four(z2h, torch, tune=True, tune_cache=None):
             if cache_has(tune_cache, 32, dtype == z2h.Z2H_C128):
                 z2h.z2h_tune_load(tune_cache)
             else:
-                tuned = z2h.z2h_autotune(4, 4, dtype, 1, tune_cache)
+                tuned = z2h.z2h_autotune(4, 4, dtype, 1, None if tune_cache == SHIPPED_TABLE else tune_cache)
                 print(f"4x4 {name} autotuned: {tuned}", file=sys.stderr, flush=True)
         plan = z2h.z2h_plan_create(4, 4, dtype)
         sz = z2h.z2h_plan_sizes(plan)
@@ -276,9 +278,13 @@ def main():
     ap.add_argument("--no-4x4", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--tune-cache", default=None,
-                    help="schedule cache: loaded if it exists, else written by the autotuner")
+                    help="schedule cache: loaded if it has the needed entries, else written by the autotuner "
+                         "(default: the table shipped with the package, never written)")
+    ap.add_argument("--retune", action="store_true", help="run the autotuner instead of loading a table")
     ap.add_argument("--pmc-summary", nargs=2, default=None, metavar=("FETCH_CSV", "WRITE_CSV"))
     args = ap.parse_args()
+    if args.tune_cache is None and not args.retune and os.path.exists(SHIPPED_TABLE):
+        args.tune_cache = SHIPPED_TABLE
     if args.pmc_summary:
         pmc_summary(*args.pmc_summary)
         return
@@ -300,12 +306,15 @@ def main():
     # the project's autotuner picks the pass schedule for this batch size
     # (and for single complex128 states) before anything is created
     tuned = {}
+    tuned_from = "autotuned in this run" if not args.no_tune else "planner default"
     if cache_has(args.tune_cache, 18, False) and cache_has(args.tune_cache, 18, True):
         z2h.z2h_tune_load(args.tune_cache)
+        tuned_from = os.path.relpath(args.tune_cache, ROOT)
         print(f"schedules loaded from {args.tune_cache}", file=sys.stderr, flush=True)
     elif not args.no_tune:
-        tuned["scan_c64"] = z2h.z2h_autotune(3, 3, z2h.Z2H_C64, nj, args.tune_cache)
-        tuned["plain_c128"] = z2h.z2h_autotune(3, 3, z2h.Z2H_C128, 1, args.tune_cache)
+        out = None if args.tune_cache == SHIPPED_TABLE else args.tune_cache
+        tuned["scan_c64"] = z2h.z2h_autotune(3, 3, z2h.Z2H_C64, nj, out)
+        tuned["plain_c128"] = z2h.z2h_autotune(3, 3, z2h.Z2H_C128, 1, out)
         print(f"autotuned: {tuned}", file=sys.stderr, flush=True)
     batch = make_batch(jobs, z2h.Z2H_C64, z2h)
     states = torch.empty(batch.states_bytes, dtype=torch.uint8, device="cuda")
@@ -371,6 +380,7 @@ def main():
                    "parallelism": "1 GPU", "launch": "timed: direct launches with per-kernel events"},
         "graph_ms_per_step": graph_ms,
         "schedule": {k: {"config": v[0], "ms_per_trotter_step": v[1]} for k, v in tuned.items()},
+        "schedule_source": tuned_from,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "level_kernel_full (tile pass, both groups)", "launches_timed": launches,

@@ -881,7 +881,12 @@ size_t obs_records(const Plan &P) {
     return (size_t)obs_workers(P.geom[0]) + (size_t)obs_workers(P.geom[P.K - 1]);
 }
 
-size_t norm_parts(const Plan &P) { return (size_t)1 << P.geom[0].tiles_log2; }
+// Doubles of norm partials per job: one per tile of the z pass, plus the
+// first-stage slots when there are more partials than a pass reads.
+size_t norm_parts(const Plan &P) {
+    const size_t tiles = (size_t)1 << P.geom[0].tiles_log2;
+    return tiles + (tiles > (size_t)kReduceChunk ? (tiles + kReduceChunk - 1) / kReduceChunk : 0);
+}
 
 size_t ws_evolve_size(const Plan &P) {
     Carver c{nullptr, 0};

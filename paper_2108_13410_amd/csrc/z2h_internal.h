@@ -11,6 +11,7 @@ constexpr int kMaxLay = 4;       // register layouts per transform
 constexpr int kMaxGroups = 4;    // qubit groups of the transform
 constexpr int kObsQ = 56;        // doubles per observable record
 constexpr int kMaxLoops = 8;
+constexpr int kReduceChunk = 1024;  // block partials per first-stage reduction block
 
 // Lattice data the kernels need: stabilizer masks of both kinds, the
 // stabilizers containing each link ("syndrome" columns) and loop masks.

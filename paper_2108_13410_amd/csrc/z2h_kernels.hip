@@ -1046,12 +1046,28 @@ __global__ void init_kernel(InitArgs a) {
 }
 
 // In-place sum of each job's partial norms into entry 0 (fixed order).
-__global__ void reduce_parts_kernel(const JobDev *jobs, JobDev inl, int parts) {
+// Norm of a z pass with more block partials than a pass kernel should read:
+// stage 1 sums chunks of kReduceChunk partials (block x of job y) into the
+// slots after the partials, stage 2 sums the slots into partial 0.  Fixed
+// summation order, so results do not depend on scheduling.
+__global__ void reduce_parts_stage1(const JobDev *jobs, JobDev inl, int parts) {
     __shared__ double red[16];
-    const JobDev J = jobs ? jobs[blockIdx.x] : inl;
+    const JobDev J = job_record(jobs, blockIdx.y, inl);
+    if (!J.norm_part) return;
+    const int lo = blockIdx.x * kReduceChunk;
+    const int hi = min(parts, lo + kReduceChunk);
+    double s = 0.0;
+    for (int j = lo + (int)threadIdx.x; j < hi; j += blockDim.x) s += gld(J.norm_part, j);
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) gst(J.norm_part, parts + blockIdx.x, s);
+}
+
+__global__ void reduce_parts_stage2(const JobDev *jobs, JobDev inl, int parts, int chunks) {
+    __shared__ double red[16];
+    const JobDev J = job_record(jobs, blockIdx.x, inl);
     if (!J.norm_part) return;
     double s = 0.0;
-    for (int j = threadIdx.x; j < parts; j += blockDim.x) s += gld(J.norm_part, j);
+    for (int j = (int)threadIdx.x; j < chunks; j += blockDim.x) s += gld(J.norm_part, parts + j);
     s = block_sum(s, red);
     if (threadIdx.x == 0) gst(J.norm_part, 0, s);
 }
@@ -1303,7 +1319,12 @@ LevelOp level_op_host(int lev, int K, int S, int k0, int order) {
 
 hipError_t launch_reduce_parts(const JobDev *jobs, const JobDev &inl, int njobs, int parts,
                                hipStream_t s) {
-    hipLaunchKernelGGL(reduce_parts_kernel, dim3(njobs), dim3(256), 0, s, jobs, inl, parts);
+    const int chunks = (parts + kReduceChunk - 1) / kReduceChunk;
+    if (chunks > kReduceChunk) return hipErrorInvalidValue;  // slots sized for one second stage
+    hipLaunchKernelGGL(reduce_parts_stage1, dim3(chunks, njobs), dim3(256), 0, s, jobs, inl, parts);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(reduce_parts_stage2, dim3(njobs), dim3(256), 0, s, jobs, inl, parts, chunks);
     return hipGetLastError();
 }
 

@@ -35,7 +35,7 @@ struct TuneBufs {
 // Milliseconds of S Trotter steps of `batch` states with plan P.
 z2h_status time_steps(const Plan &P, TuneBufs &B, int batch, int S, hipStream_t s, float &ms) {
     std::vector<JobDev> h(batch);
-    const size_t parts_per_job = (size_t)1 << (P.n - 8);
+    const size_t parts_per_job = ((size_t)1 << (P.n - 8)) + ((size_t)1 << (P.n - 18 > 0 ? P.n - 18 : 0));
     z2h_schedule sc;
     memset(&sc, 0, sizeof sc);
     sc.start = {1.0, 1.0, 0.0, 0.0};
@@ -123,7 +123,7 @@ z2h_status z2h_autotune(int32_t Lx, int32_t Ly, z2h_dtype dtype, int32_t batch, 
         TuneBufs B;
         const size_t sb = (size_t)batch * (esize << n);
         if (hipMalloc(&B.states, sb) != hipSuccess) return fail(Z2H_ERR_OOM, "trial states of %zu bytes", sb);
-        if (hipMalloc(&B.parts, sizeof(double) * (size_t)batch << (n - 8)) != hipSuccess)
+        if (hipMalloc(&B.parts, sizeof(double) * (size_t)batch * (((size_t)1 << (n - 8)) + ((size_t)1 << (n - 18 > 0 ? n - 18 : 0)))) != hipSuccess)
             return fail(Z2H_ERR_OOM, "trial partials");
         if (hipMalloc(&B.jobs, sizeof(JobDev) * batch) != hipSuccess) return fail(Z2H_ERR_OOM, "trial jobs");
         if (hipMalloc(&B.inits, sizeof(InitJob) * batch) != hipSuccess) return fail(Z2H_ERR_OOM, "trial inits");
