@@ -219,6 +219,45 @@ z2h_status z2h_adjoint(const z2h_plan *plan, const void *d_psi_final, void *d_ws
                        size_t ws_bytes, const z2h_schedule *sched, const z2h_couplings *lossH,
                        double *d_gradZ, double *d_gradX, double *h_loss, void *stream);
 
+/* ------------------------------------------------------------------ paths */
+
+/*
+ * A piecewise-linear path through coupling space (Sec. III, Fig. evo: the
+ * red path P(p,0) -> R(p,r) -> R'(0,r), the blue path P(p,0) -> P'(0,p);
+ * Sec. V: the path (0,0.5) -> (0.5,0.5) -> O along the dual line).  Leg i
+ * ramps linearly from vert[i] to vert[i+1] in steps[i] Trotter steps of
+ * duration dt (sampling, order, renorm as in z2h_schedule; the paper's
+ * protocol is sampling 1 with dg = 1e-5 per step, dt = 0.02).  Consecutive
+ * legs join with unmerged x halves, so a path is the exact product of its
+ * legs' Trotter steps.  trace_every > 0 observes the state every trace_every
+ * steps of each leg and at each leg's end; 0 observes at leg ends only.
+ */
+typedef struct {
+    int32_t nvert;              /* >= 2 */
+    int32_t reserved;           /* 0 */
+    const z2h_couplings *vert;  /* host, nvert entries */
+    const int64_t *steps;       /* host, nvert - 1 entries, >= 0 */
+    double dt;
+    int32_t sampling, order, renorm, trace_every;
+} z2h_path;
+
+/*
+ * Evolve d_state along the path and record observables (z2h_obs layout,
+ * Z2H_OBS_DOUBLES doubles per sample, device) into d_trace: sample 0 is the
+ * initial state observed at vert[0]; then, for each leg with steps > 0, one
+ * sample after every trace_every steps and one at the leg's end, each
+ * observed with the couplings of the point reached, vert[i] + (k/M)
+ * (vert[i+1] - vert[i]) after k of the leg's M steps.  Loop masks as in
+ * z2h_observe.  n_samples (host, may be NULL) receives the number of
+ * samples; with d_trace NULL nothing is enqueued (size query).  trace_cap:
+ * samples d_trace can hold (Z2H_ERR_WORKSPACE if fewer are needed).
+ * d_ws: at least the larger of ws_evolve_bytes and ws_observe_bytes.
+ */
+z2h_status z2h_path_evolve(const z2h_plan *plan, void *d_state, void *d_ws, size_t ws_bytes,
+                           const z2h_path *path, const uint64_t *zmasks, int32_t nz,
+                           const uint64_t *xmasks, int32_t nx, double *d_trace, int64_t trace_cap,
+                           int64_t *n_samples, void *stream);
+
 /* ------------------------------------------------------------------ batches */
 
 /*

@@ -56,6 +56,13 @@ class z2h_schedule(ctypes.Structure):
                 ("sZ", ctypes.POINTER(ctypes.c_double)), ("sX", ctypes.POINTER(ctypes.c_double))]
 
 
+class z2h_path(ctypes.Structure):
+    _fields_ = [("nvert", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("vert", ctypes.POINTER(z2h_couplings)), ("steps", ctypes.POINTER(ctypes.c_int64)),
+                ("dt", ctypes.c_double), ("sampling", ctypes.c_int32), ("order", ctypes.c_int32),
+                ("renorm", ctypes.c_int32), ("trace_every", ctypes.c_int32)]
+
+
 class z2h_obs(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_double), ("energy", ctypes.c_double),
                 ("sumA", ctypes.c_double), ("sumB", ctypes.c_double),
@@ -96,6 +103,8 @@ SIGNATURES = {
     "z2h_tune_load": (_i32, [ctypes.c_char_p]),
     "z2h_plan_create_config": (_i32, [_i32, _i32, _i32, ctypes.c_char_p, ctypes.POINTER(_P)]),
     "z2h_tune_candidates": (_i32, [_i32, _i32, _i32, ctypes.c_char_p, _sz]),
+    "z2h_path_evolve": (_i32, [_P, _P, _P, _sz, ctypes.POINTER(z2h_path), _P, _i32, _P, _i32, _P,
+                                ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _P]),
     "z2h_timing_enable": (_i32, [_i32]),
     "z2h_timing_read": (_i32, [_P, _P]),
     "z2h_version": (ctypes.c_char_p, []),
@@ -109,6 +118,10 @@ def lib():
     """Load libz2h.so (raises if it is missing: there is no CPU fallback)."""
     global _lib
     if _lib is None:
+        # torch carries its own HIP runtime under the same soname as the
+        # system's; load it first so that the library and torch share one
+        # runtime instance (the other order leaves torch without devices)
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise RuntimeError(f"{LIB_PATH} is missing: build it with __graft_entry__.build() "
                                "or python -m paper_2108_13410_amd.build")
@@ -284,6 +297,34 @@ def z2h_adjoint(plan, psi_final, ws, sched, lossH, gradZ, gradX, stream=None):
                              ctypes.byref(sched), ctypes.byref(Hc), _ptr(gradZ), _ptr(gradX),
                              ctypes.byref(loss), _stream(stream)))
     return loss.value
+
+
+def make_path(vertices, steps, dt, sampling=1, order=0, renorm=0, every=0):
+    """z2h_path for a list of coupling 4-tuples and per-leg step counts; the
+    returned object keeps its arrays alive."""
+    nv = len(vertices)
+    if len(steps) != nv - 1:
+        raise ValueError("need one step count per leg")
+    verts = (z2h_couplings * nv)(*[v if isinstance(v, z2h_couplings) else couplings(*v) for v in vertices])
+    st = (ctypes.c_int64 * (nv - 1))(*[int(m) for m in steps])
+    p = z2h_path(nv, 0, verts, st, float(dt), int(sampling), int(order), int(renorm), int(every))
+    p._keep = (verts, st)
+    return p
+
+
+def z2h_path_evolve(plan, state, ws, path, zmasks=None, xmasks=None, stream=None):
+    """Evolve along a path; returns the device trace (samples x Z2H_OBS_DOUBLES)."""
+    import torch
+    zp, nz, za = _masks_arg(zmasks)
+    xp, nx, xa = _masks_arg(xmasks)
+    ns = ctypes.c_int64()
+    L = lib()
+    _check(L.z2h_path_evolve(plan.handle, None, None, 0, ctypes.byref(path), zp, nz, xp, nx, None, 0,
+                             ctypes.byref(ns), None))
+    trace = torch.empty((ns.value, Z2H_OBS_DOUBLES), dtype=torch.float64, device=state.device)
+    _check(L.z2h_path_evolve(plan.handle, _ptr(state), _ptr(ws), ws.numel() * ws.element_size(),
+                             ctypes.byref(path), zp, nz, xp, nx, _ptr(trace), ns.value, None, _stream(stream)))
+    return trace
 
 
 class Batch:

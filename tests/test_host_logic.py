@@ -245,3 +245,29 @@ def test_out_of_bounds_tunings_rejected(tune, monkeypatch):
     with pytest.raises(z2h.Z2HError) as e:
         z2h.z2h_plan_create(3, 3, z2h.Z2H_C64)
     assert e.value.code == z2h.Z2H_ERR_UNSUPPORTED
+
+
+def test_path_sample_count_and_validation():
+    """Size query of z2h_path_evolve (no device work) and path validation."""
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C64)
+    L = z2h.lib()
+    ns = ctypes.c_int64()
+    p = z2h.make_path([(1, 1, 0, 0), (1, 1, .2, 0), (1, 1, .2, .1), (1, 1, .2, .1)], [25, 0, 10], 0.02, every=10)
+    assert L.z2h_path_evolve(plan.handle, None, None, 0, ctypes.byref(p), None, 0, None, 0, None, 0,
+                             ctypes.byref(ns), None) == z2h.Z2H_OK
+    assert ns.value == 1 + 3 + 0 + 1
+    p0 = z2h.make_path([(1, 1, 0, 0), (1, 1, .2, 0)], [25], 0.02, every=0)
+    assert L.z2h_path_evolve(plan.handle, None, None, 0, ctypes.byref(p0), None, 0, None, 0, None, 0,
+                             ctypes.byref(ns), None) == z2h.Z2H_OK
+    assert ns.value == 2
+    bad = [z2h.make_path([(1, 1, 0, 0), (1, 1, .2, 0)], [-1], 0.02),
+           z2h.make_path([(1, 1, 0, 0), (1, 1, float("nan"), 0)], [5], 0.02),
+           z2h.make_path([(1, 1, 0, 0), (1, 1, .2, 0)], [5], 0.02, sampling=2),
+           z2h.make_path([(1, 1, 0, 0), (1, 1, .2, 0)], [5], 0.02, every=-3)]
+    for q in bad:
+        assert L.z2h_path_evolve(plan.handle, None, None, 0, ctypes.byref(q), None, 0, None, 0, None, 0,
+                                 ctypes.byref(ns), None) == z2h.Z2H_ERR_INVALID
+    # a trace too small for the samples is a workspace error, raised before any device work
+    assert L.z2h_path_evolve(plan.handle, ctypes.c_void_p(4096), ctypes.c_void_p(8192), 1 << 30,
+                             ctypes.byref(p), None, 0, None, 0, ctypes.c_void_p(4096), 2,
+                             ctypes.byref(ns), None) == z2h.Z2H_ERR_WORKSPACE
