@@ -246,6 +246,41 @@ def pmc_summary(fetch_csv, write_csv):
                                           "write_bytes_per_launch", "algorithmic_bytes_per_launch")}))
 
 
+def paper_protocol(z2h, torch):
+    """The paper's protocol on the 3x3 torus (complex128, J = 1/2, dg = 1e-5
+    and dt = 0.02 per step): the dual-line path and the three red paths,
+    with energies traced every 100 steps; extrema of d2E/dg2 from local
+    quadratic fits, beside the values the paper prints (Figs. dual_evo,
+    sec_order)."""
+    import numpy as np
+    from paper_2108_13410_amd import protocols as pr
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C128)
+    sz = z2h.z2h_plan_sizes(plan)
+    psi = z2h.alloc_state(plan)
+    ws = z2h.alloc_bytes(max(sz["ws_evolve"], sz["ws_observe"]))
+    runs = [("dual line", pr.dual_path(0.5), 0.1798)] + \
+           [(f"red r={r}", pr.red_path(0.5, r), paper) for r, paper in ((0.05, 0.1920), (0.15, 0.1916), (0.25, 0.2489))]
+    out, steps_total, secs = [], 0, 0.0
+    for name, (init, verts, steps), paper in runs:
+        z2h.z2h_state_init(plan, psi, {"psi1": z2h.Z2H_INIT_PSI1, "psi1p": z2h.Z2H_INIT_PSI1P}[init])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tr = z2h.z2h_path_evolve(plan, psi, ws, z2h.make_path(verts, steps, pr.DT, sampling=1, every=100))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        n = steps[-1] // 100
+        E = tr[-n - 1:, 1].cpu().numpy()[::-1]
+        g = np.linspace(0.0, 0.5, n + 1)
+        x, d2 = pr.second_derivative(g, E, 10)
+        gx, _ = pr.extremum_in(x, d2, 0.05, 0.45, "min")
+        out.append({"path": name, "steps": int(sum(steps)), "seconds": el, "d2E_extremum_g": gx, "paper": paper})
+        steps_total += sum(steps)
+        secs += el
+    return {"runs": out, "trotter_steps_per_s": steps_total / secs,
+            "amp_updates_per_s": steps_total * (1 << 18) / secs, "precision": "complex128",
+            "traces": "observables every 100 steps (every 1e-3 in g)"}
+
+
 def cpu_baseline(seconds_hint):
     """The FP64 oracle (test infrastructure, untuned) on one scan point."""
     import numpy as np  # noqa: F401
@@ -277,6 +312,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-4x4", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
+    ap.add_argument("--no-protocol", action="store_true")
     ap.add_argument("--tune-cache", default=None,
                     help="schedule cache: loaded if it has the needed entries, else written by the autotuner "
                          "(default: the table shipped with the package, never written)")
@@ -408,6 +444,9 @@ def main():
         print(f"plain c128: {per_point*1e3:.2f} ms/point", file=sys.stderr, flush=True)
     if not args.no_4x4:
         line["torus_4x4"] = four_by_four(z2h, torch, not args.no_tune, args.tune_cache)
+    if not args.no_protocol:
+        line["paper_protocol"] = paper_protocol(z2h, torch)
+        print(f"paper protocol: {line['paper_protocol']['trotter_steps_per_s']:.0f} steps/s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(15)
     line["paper_context"] = {"rtx3090_c128_19q": ">= 0.8e7-1.8e7 link-amplitude-updates/s (derived "
