@@ -116,9 +116,51 @@ static int pick_R(bool c128, int m) {
     return R;
 }
 
+// LDS block length of a full-window group (the kernels place local index e
+// at slot(t) + u * blk, t the transformed bits, u the others).  Within a
+// layout every element's address is the thread's base plus a constant, so
+// bank conflicts depend on the bases only: choose the shortest block, from
+// the padded span up, for which each group of lanes that fills the banks
+// once (256 bytes) hits distinct banks in every layout of the first wave, or
+// failing that the one with the fewest collisions.
+static void choose_lds_blk(const Plan &P, GroupGeom &g) {
+    g.lds_blk = 0;
+    if (!g.full) return;
+    const int R = g.R, G = R * g.full, x0 = g.x0, x1 = g.x1;
+    const int lb = P.c128 ? 4 : 5;
+    const uint32_t nb = 1u << lb, span = (1u << G) + (1u << (G - R));
+    const uint32_t lanes = std::min<uint32_t>(64, 1u << (g.m - R));
+    int best_bad = 1 << 30;
+    uint32_t best = span;
+    for (uint32_t sft = 0; sft < nb; ++sft) {
+        const uint32_t blk = span + sft;
+        int bad = 0;
+        for (int j = 0; j < g.full; ++j) {
+            const int p = x1 - R * (j + 1);
+            for (uint32_t w0 = 0; w0 < lanes; w0 += nb) {
+                uint32_t hit[32] = {0};
+                for (uint32_t l = w0; l < std::min(lanes, w0 + nb); ++l) {
+                    const uint32_t e = ((l >> p) << (p + R)) | (l & ((1u << p) - 1u));
+                    const uint32_t tb = (e >> x0) & ((1u << G) - 1u);
+                    const uint32_t u = (e & ((1u << x0) - 1u)) | ((e >> x1) << x0);
+                    const uint32_t a = tb + (tb >> R) + u * blk;
+                    bad += hit[a & (nb - 1u)]++ ? 1 : 0;
+                }
+            }
+        }
+        if (bad < best_bad) {
+            best_bad = bad;
+            best = blk;
+            if (!bad) break;
+        }
+    }
+    g.lds_blk = (int32_t)best;
+}
+
 // Every group's workgroup must fit the kernels' launch bounds (64..512
 // threads) and the 160 KiB of LDS of a gfx950 workgroup.
-static z2h_status check_block(const Plan &P) {
+static z2h_status check_block(Plan &P) {
+    for (int j = 0; j < P.K; ++j) choose_lds_blk(P, P.geom[j]);
     for (int j = 0; j < P.K; ++j) {
         const int tb = P.geom[j].m - P.geom[j].R;
         if (tb < 6 || tb > 9)
@@ -207,16 +249,19 @@ static z2h_status plan_uniform(Plan &P, int m_pref, int m_hi, int c_min, int for
 // layout changes per step, then complex128 windows of 32 registers.
 struct GroupChoice {
     int G, R, NL, m, c;
+    int np;  // tiles per block: 1, or 2 (two-tile blocks of a strided group)
 };
 
 static bool fit_group(const Plan &P, int j, int b0, int G, int R, int NL, int m_pref, int m_hi, int c_min,
                       GroupChoice &out) {
     const int n = P.n;
-    out = {G, R, NL, 0, 0};
+    out = {G, R, NL, 0, 0, 1};
     auto lds_ok = [&](int m) {
         GroupGeom g{};
         g.m = m;
         g.R = R;
+        g.full = NL;
+        g.c = j == 0 ? 0 : m - G;
         return lds_bytes(P, g, R) <= (size_t)kMaxLdsBytes;
     };
     if (j == 0) {
@@ -312,6 +357,18 @@ static z2h_status apply_split(Plan &P, const GroupChoice *ch, int K) {
         g.x1 = g.c + ch[j].G;
         g.tiles_log2 = n - g.m;
         plan_layouts(g, false);
+        if (ch[j].np != 1 && ch[j].np != 2) return fail(Z2H_ERR_INVALID, "group %d: %d tiles per block", j, ch[j].np);
+        if (ch[j].np == 2) {
+            // the block's two tiles differ in the lowest tile bit, which must
+            // sit right above the carried bits for the pair to be contiguous
+            if (j == 0 || g.b0 - g.c < 1 || g.tiles_log2 < 1)
+                return fail(Z2H_ERR_INVALID, "group %d: two-tile blocks need a strided group with tile bits below it", j);
+            if (!g.full || !pair_level_ok(P.c128, g.R, g.full))
+                return fail(Z2H_ERR_UNSUPPORTED, "group %d: no two-tile kernel for window %d x %d", j, g.R, g.full);
+            g.pair = 2;
+        } else {
+            g.pair = 1;
+        }
         b += ch[j].G;
     }
     if (b != n) return fail(Z2H_ERR_INVALID, "split covers %d of %d bits", b, n);
@@ -368,10 +425,11 @@ static z2h_status plan_from_config(Plan &P, const char *cfg, int m_pref, int m_h
         int K = 0;
         q += 6;
         while (*q && K < kMaxGroups) {
-            int G, R, m, c, used = 0;
+            int G, R, m, c, np = 1, used = 0, used2 = 0;
             if (sscanf(q, "%d:%d:%d:%d%n", &G, &R, &m, &c, &used) != 4) break;
-            ch[K++] = {G, R, G / std::max(R, 1), m, c};
             q += used;
+            if (*q == ':' && sscanf(q, ":%d%n", &np, &used2) == 1) q += used2;
+            ch[K++] = {G, R, G / std::max(R, 1), m, c, np};
             if (*q != '/') break;
             ++q;
         }
@@ -475,24 +533,34 @@ z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P, int 
 // Tile options of one group of a split: every (m, c) whose block size is
 // within the launch bounds and whose tile fits LDS, with contiguous runs of
 // at least 64 bytes for groups that carry low bits.
-static std::vector<std::pair<int, int>> group_tiles(const Plan &P, int j, int b0, int G, int R, int m_hi) {
-    std::vector<std::pair<int, int>> out;
+struct TileOpt {
+    int m, c, np;
+};
+
+static std::vector<TileOpt> group_tiles(const Plan &P, int j, int b0, int G, int R, int m_hi) {
+    std::vector<TileOpt> out;
     auto lds_ok = [&](int m) {
         GroupGeom g{};
         g.m = m;
         g.R = R;
+        g.full = G % R == 0 ? G / R : 0;
+        g.c = j == 0 ? 0 : m - G;
         return lds_bytes(P, g, R) <= (size_t)kMaxLdsBytes;
     };
     const int c_lo = P.c128 ? 2 : 3;
     if (j == 0) {
         for (int m = G; m <= std::min(m_hi, P.n); ++m)
-            if (m - R >= 6 && m - R <= 9 && lds_ok(m)) out.push_back({m, 0});
+            if (m - R >= 6 && m - R <= 9 && lds_ok(m)) out.push_back({m, 0, 1});
         return out;
     }
+    const bool pair = (G % R == 0) && pair_level_ok(P.c128, R, G / R);
     for (int c = c_lo; c <= b0; ++c) {
         const int m = c + G;
         if (m > m_hi) break;
-        if (m - R >= 6 && m - R <= 9 && lds_ok(m)) out.push_back({m, c});
+        if (m - R >= 6 && m - R <= 9 && lds_ok(m)) {
+            out.push_back({m, c, 1});
+            if (pair && c >= 4 && b0 - c >= 1 && P.n - m >= 1) out.push_back({m, c, 2});
+        }
     }
     return out;
 }
@@ -528,7 +596,7 @@ std::vector<std::string> tune_candidates(int Lx, int Ly, bool c128) {
         for (int j = 0; j < sc.K; ++j) key += std::to_string(sc.g[j].G) + ":" + std::to_string(sc.g[j].R) + "/";
         if (std::find(seen_struct.begin(), seen_struct.end(), key) != seen_struct.end()) continue;
         seen_struct.push_back(key);
-        std::vector<std::vector<std::pair<int, int>>> opts(sc.K);
+        std::vector<std::vector<TileOpt>> opts(sc.K);
         int b0 = 0;
         size_t combos = 1;
         for (int j = 0; j < sc.K; ++j) {
@@ -544,7 +612,8 @@ std::vector<std::string> tune_candidates(int Lx, int Ly, bool c128) {
                 const auto &o = opts[j][r % opts[j].size()];
                 r /= opts[j].size();
                 char buf[64];
-                snprintf(buf, sizeof buf, "%s%d:%d:%d:%d", j ? "/" : "", sc.g[j].G, sc.g[j].R, o.first, o.second);
+                snprintf(buf, sizeof buf, "%s%d:%d:%d:%d%s", j ? "/" : "", sc.g[j].G, sc.g[j].R, o.m, o.c,
+                         o.np == 2 ? ":2" : "");
                 cfg += buf;
             }
             if (std::find(out.begin(), out.end(), cfg) == out.end()) out.push_back(cfg);
@@ -579,7 +648,15 @@ z2h_status tune_load(const char *path) { return tune_load_file(path); }
 int tune_batch_class(int batch) { return batch_class(batch); }
 
 size_t lds_bytes(const Plan &P, const GroupGeom &g, int R) {
-    const size_t elems = ((size_t)1 << g.m) + ((size_t)1 << (g.m - R));
+    size_t elems = ((size_t)1 << g.m) + ((size_t)1 << (g.m - R));
+    if (g.full) {
+        // full-window kernels: a block per value of the untransformed bits;
+        // before the planner has chosen the block, count the longest one
+        const int G = R * g.full;
+        const size_t blk = g.lds_blk ? (size_t)g.lds_blk
+                                     : ((size_t)1 << G) + ((size_t)1 << (G - R)) + (P.c128 ? 15 : 31);
+        elems = std::max(elems, ((size_t)1 << (g.m - G)) * blk);
+    }
     size_t b = elems * P.esize;
     b += (size_t)(P.nst + 1) * (P.n + 1) * P.esize;  // phase table
     b = (b + 15) & ~(size_t)15;
@@ -1019,7 +1096,8 @@ z2h_status z2h_plan_describe(const z2h_plan *plan, char *buf, size_t len) {
         s += "], \"bhi\": [";
         for (int l = 0; l < g.nlay; ++l) s += (l ? ", " : "") + std::to_string(g.bhi[l]);
         s += "], \"lds_bytes\": " + std::to_string(lds_bytes(P, g, g.R)) + ", \"R\": " + std::to_string(g.R) +
-             ", \"full\": " + std::to_string(g.full) + "}";
+             ", \"full\": " + std::to_string(g.full) + ", \"pair\": " + std::to_string(g.pair == 2 ? 2 : 1) +
+             ", \"lds_blk\": " + std::to_string(g.lds_blk) + "}";
     }
     s += "]}";
     if (s.size() + 1 > len) return fail(Z2H_ERR_INVALID, "buffer of %zu bytes, %zu needed", len, s.size() + 1);

@@ -37,6 +37,8 @@ struct GroupGeom {
     int32_t nlay;
     int32_t p[kMaxLay], blo[kMaxLay], bhi[kMaxLay];
     int32_t tiles_log2;                 // tiles per state = 2^(n - m)
+    int32_t pair;                       // 2: each block handles tiles 2u, 2u + 1 (else 1 or 0)
+    int32_t lds_blk;                    // full-window LDS block per value of the untransformed bits
 };
 
 // Per-job data for the level-synchronous pass kernel.

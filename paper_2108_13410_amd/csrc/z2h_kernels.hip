@@ -195,6 +195,19 @@ __device__ __forceinline__ void store_tile(const Cx<Real> (&v)[1 << R], Cx<Real>
     for (int q = 0; q < (1 << R); ++q) stc<Real, NT>(b + ((uint64_t)q << L.gs), v[q]);
 }
 
+// Streaming loads of NT tiles, element by element across the tiles: with
+// two tiles of a strided group the two 128-byte halves of each 256-byte row
+// are requested back to back.
+template <typename Real, int R, int NT>
+__device__ __forceinline__ void load_tiles(Cx<Real> (&v)[NT][1 << R], const Cx<Real> *st,
+                                           const LayCtx<R> (&L)[NT]) {
+#pragma unroll
+    for (int q = 0; q < (1 << R); ++q) {
+#pragma unroll
+        for (int s = 0; s < NT; ++s) v[s][q] = ldc<Real, true>(st + L[s].i0 + ((uint64_t)q << L[s].gs));
+    }
+}
+
 // Build the phase table T[k][w] = scale * exp(i (alpha (nst - 2k) + beta (n - 2w)))
 // in LDS (FP64 angles and products, cast to Real).  Two stages so that a
 // pass can compute the factors while its tile loads are in flight and apply
@@ -234,7 +247,7 @@ __device__ void build_table(Cx<Real> *tab, double2 *fac, int nst, int n, double 
 
 // Multiply every register element by T[k][w]: elements are visited in
 // Gray-code order so each step updates the syndrome by one uniform column.
-template <typename Real, int R>
+template <typename Real, int R, int PHASE_CHUNK = 0>
 __device__ __forceinline__ void apply_phase(Cx<Real> (&v)[1 << R], const LayCtx<R> &L, int basis,
                                             int n, const Cx<Real> *tab) {
     uint32_t s = basis ? L.s0x : L.s0z;
@@ -245,6 +258,9 @@ __device__ __forceinline__ void apply_phase(Cx<Real> (&v)[1 << R], const LayCtx<
         const int q = idx ^ (idx >> 1);
         if (idx) s ^= basis ? L.lx[__builtin_ctz(idx)] : L.lz[__builtin_ctz(idx)];
         v[q] = cmul(v[q], tw[__umul24((uint32_t)popc(s), (uint32_t)W) + __builtin_popcount(q)]);
+        // keep the table reads of at most eight elements in flight (register
+        // pressure when a block holds two tiles)
+        if (PHASE_CHUNK && (idx & (PHASE_CHUNK - 1)) == PHASE_CHUNK - 1) __builtin_amdgcn_sched_barrier(0);
     }
 }
 
@@ -564,16 +580,88 @@ __device__ __forceinline__ void renorm_table(const LevelArgs &a, const JobDev &J
     }
 }
 
-// Rest of one tile of one pass, after its loads were issued (v in layout 0).
-// The phase table is built while the loads are in flight: FP64 factors and
-// unscaled products first; the renormalization factor (from the previous z
-// pass's block partials, whose load was issued after the tile's) is applied
-// to the table after the first transform, when those loads have landed.
-template <typename Real, int R, int NL, int KIND>
-__device__ __forceinline__ void pass_full(const LevelArgs &a, const JobDev &J, const LevelOp &op,
-                                          uint64_t tile, uint32_t t, Cx<Real> (&v)[1 << R],
-                                          Cx<Real> *st, const LayCtx<R> &L0, Cx<Real> *lds,
-                                          Cx<Real> *tab, double2 *fac, double *red) {
+// Rest of one pass over NT consecutive tiles of a block, after their loads
+// were issued (v[s] in layout 0 for tile tile0 + s).  The phase table is
+// built while the loads are in flight: FP64 factors and unscaled products
+// first; the renormalization factor (from the previous z pass's block
+// partials, whose load was issued after the tiles') is applied to the table
+// after the first transform, when those loads have landed.  Layout changes
+// go through LDS one tile at a time (the LDS block holds one tile).
+// LDS placement of a tile for the layout changes of a full-window pass.
+// Local index e splits into its G transformed bits t = e[x0, x1) and the
+// untransformed bits u (carried low bits, then any bits above x1); element e
+// goes to slot(t) + u * g.lds_blk.  Register window j covers bits
+// [R (NL-1-j), R (NL-j)) of t, so an element's offset within a layout is a
+// compile-time constant and each thread keeps one base per layout.  The block
+// length (at least the padded 2^G + 2^(G-R)) is chosen by the planner so that
+// the lanes of a wave spread over the LDS banks in every layout.
+template <int R, int NL>
+struct LdsMap {
+    uint32_t base[NL];
+};
+
+template <int R, int NL, typename Real>
+__device__ __forceinline__ void lds_map(LdsMap<R, NL> &M, const GroupGeom &g, uint32_t t) {
+    constexpr int G = R * NL;
+    const int x0 = g.x0, x1 = g.x1;
+    const uint32_t blk = (uint32_t)g.lds_blk;
+#pragma unroll
+    for (int j = 0; j < NL; ++j) {
+        const uint32_t e = lay_base<R>(x1 - R * (j + 1), t);
+        const uint32_t tb = (e >> x0) & ((1u << G) - 1u);
+        const uint32_t u = (e & ((1u << x0) - 1u)) | ((e >> x1) << x0);
+        M.base[j] = slot<R>(tb) + u * blk;
+    }
+}
+
+// Layout change from window position PF to PT (positions in rot coordinates).
+template <typename Real, int R, int PF, int PT>
+__device__ __forceinline__ void xchg_rot(Cx<Real> (&v)[1 << R], Cx<Real> *lds, uint32_t bf, uint32_t bt) {
+#pragma unroll
+    for (int q = 0; q < (1 << R); ++q) lds[bf + slot<R>((uint32_t)q << PF)] = v[q];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < (1 << R); ++q) v[q] = lds[bt + slot<R>((uint32_t)q << PT)];
+    __syncthreads();
+}
+
+template <typename Real, int R, int NL, int J>
+__device__ __forceinline__ void fwd_rot_from(Cx<Real> (&v)[1 << R], Cx<Real> *lds, const LdsMap<R, NL> &M) {
+    if constexpr (J < NL) {
+        xchg_rot<Real, R, R * (NL - J), R * (NL - 1 - J)>(v, lds, M.base[J - 1], M.base[J]);
+        bfly_all<Real, R>(v);
+        fwd_rot_from<Real, R, NL, J + 1>(v, lds, M);
+    }
+}
+
+// Transform over the group: layouts 0 .. NL-1 (ends in layout NL-1).
+template <typename Real, int R, int NL>
+__device__ __forceinline__ void fwd_rot(Cx<Real> (&v)[1 << R], Cx<Real> *lds, const LdsMap<R, NL> &M) {
+    bfly_all<Real, R>(v);
+    fwd_rot_from<Real, R, NL, 1>(v, lds, M);
+}
+
+template <typename Real, int R, int NL, int J>
+__device__ __forceinline__ void bwd_rot_from(Cx<Real> (&v)[1 << R], Cx<Real> *lds, const LdsMap<R, NL> &M) {
+    if constexpr (J >= 1) {
+        xchg_rot<Real, R, R * (NL - 1 - J), R * (NL - J)>(v, lds, M.base[J], M.base[J - 1]);
+        bfly_all<Real, R>(v);
+        bwd_rot_from<Real, R, NL, J - 1>(v, lds, M);
+    }
+}
+
+// Transform over the group starting in layout NL-1 (ends in layout 0).
+template <typename Real, int R, int NL>
+__device__ __forceinline__ void bwd_rot(Cx<Real> (&v)[1 << R], Cx<Real> *lds, const LdsMap<R, NL> &M) {
+    bfly_all<Real, R>(v);
+    bwd_rot_from<Real, R, NL, NL - 1>(v, lds, M);
+}
+
+template <typename Real, int R, int NL, int KIND, int NT>
+__device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, const LevelOp &op,
+                                           uint64_t tile0, uint32_t t, Cx<Real> (&v)[NT][1 << R],
+                                           Cx<Real> *st, const LayCtx<R> (&L0)[NT], Cx<Real> *lds,
+                                           Cx<Real> *tab, double2 *fac, double *red) {
     const GroupGeom &g = a.geom;
     const int x1 = g.x1;
     const int p0 = x1 - R, pl = x1 - R * NL;
@@ -589,36 +677,48 @@ __device__ __forceinline__ void pass_full(const LevelArgs &a, const JobDev &J, c
         table_products<Real>(tab, fac, nst, n, op.basis ? ldexp(1.0, -n) : 1.0);
     }
     if constexpr (KIND == kHalfIn) {
-        if (want_norm) renorm_table<Real>(a, J, op, tile, t, part, tab, red);
-        LayCtx<R> Ls;
-        lay_ctx<R>(Ls, g, a.lat, tile, p0, t, true);
-        if (op.norm) {
-            const double s = block_sum(sumsq<Real, R>(v), red);
-            if (t == 0 && J.norm_part) gst(J.norm_part, tile, s);
+        if (want_norm) renorm_table<Real>(a, J, op, tile0, t, part, tab, red);
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            LayCtx<R> Ls;
+            lay_ctx<R>(Ls, g, a.lat, tile0 + s, p0, t, true);
+            if (op.norm) {
+                const double q = block_sum(sumsq<Real, R>(v[s]), red);
+                if (t == 0 && J.norm_part) gst(J.norm_part, tile0 + s, q);
+            }
+            apply_phase<Real, R, NT == 2 ? 8 : 0>(v[s], Ls, op.basis, n, tab);
         }
-        apply_phase<Real, R>(v, Ls, op.basis, n, tab);
     }
-    fwd_full<Real, R, NL>(v, lds, x1, t);
+    LdsMap<R, NL> M;
+    lds_map<R, NL, Real>(M, g, t);
+#pragma unroll
+    for (int s = 0; s < NT; ++s) fwd_rot<Real, R, NL>(v[s], lds, M);
     if constexpr (kPhase && KIND != kHalfIn) {
-        if (want_norm) renorm_table<Real>(a, J, op, tile, t, part, tab, red);
+        if (want_norm) renorm_table<Real>(a, J, op, tile0, t, part, tab, red);
     }
     if constexpr (KIND == kPhaseB || KIND == kHalfOut) {
-        LayCtx<R> Lm;
-        lay_ctx<R>(Lm, g, a.lat, tile, pl, t, true);
-        if constexpr (KIND == kPhaseB) {
-            if (op.norm) {
-                const double s = block_sum(sumsq<Real, R>(v), red);
-                if (t == 0 && J.norm_part) gst(J.norm_part, tile, s);
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+            LayCtx<R> Lm;
+            lay_ctx<R>(Lm, g, a.lat, tile0 + s, pl, t, true);
+            if constexpr (KIND == kPhaseB) {
+                if (op.norm) {
+                    const double q = block_sum(sumsq<Real, R>(v[s]), red);
+                    if (t == 0 && J.norm_part) gst(J.norm_part, tile0 + s, q);
+                }
             }
+            apply_phase<Real, R, NT == 2 ? 8 : 0>(v[s], Lm, op.basis, n, tab);
         }
-        apply_phase<Real, R>(v, Lm, op.basis, n, tab);
     }
-    if constexpr (KIND == kPhaseB) {
-        bwd_full<Real, R, NL>(v, lds, x1, t);
-    } else {
-        if constexpr (NL > 1) xchg<Real, R>(v, lds, pl, p0, t);
+#pragma unroll
+    for (int s = 0; s < NT; ++s) {
+        if constexpr (KIND == kPhaseB) {
+            bwd_rot<Real, R, NL>(v[s], lds, M);
+        } else {
+            if constexpr (NL > 1) xchg_rot<Real, R, 0, R * (NL - 1)>(v[s], lds, M.base[NL - 1], M.base[0]);
+        }
+        store_tile<Real, R, true>(v[s], st, L0[s]);
     }
-    store_tile<Real, R, true>(v, st, L0);
 }
 
 // KS: the pass kind every job of the launch has at this level (kPhaseB or
@@ -628,22 +728,27 @@ __device__ __forceinline__ void pass_full(const LevelArgs &a, const JobDev &J, c
 // record is read.
 constexpr int kAnyKind = -1;
 
-template <typename Real, int R, int NL, int KS>
+// NT: consecutive tiles per block (1, or 2 for strided groups whose tiles
+// carry 128-byte rows: the two tiles of a block differ only in the lowest
+// tile bit, so each block reads and writes 256 contiguous bytes per row).
+template <typename Real, int R, int NL, int KS, int NT>
 __global__ void __launch_bounds__(512) level_kernel_full(LevelArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const GroupGeom &g = a.geom;
     const uint32_t t = threadIdx.x;
-    const uint64_t tiles = 1ull << g.tiles_log2;
+    constexpr int kNTlog = NT == 2 ? 1 : 0;
+    const int blog = g.tiles_log2 - kNTlog;  // blocks per state = 2^blog
     const uint64_t bid = blockIdx.x;
-    const int jb = (int)(bid >> g.tiles_log2);
-    const uint64_t tile = bid & (tiles - 1);
+    const int jb = (int)(bid >> blog);
+    const uint64_t tile0 = (bid & ((1ull << blog) - 1)) << kNTlog;
     Cx<Real> *base = reinterpret_cast<Cx<Real> *>(a.states);
 
-    Cx<Real> v[1 << R];
-    LayCtx<R> L0;
-    lay_ctx<R>(L0, g, a.lat, tile, g.x1 - R, t, false);
+    Cx<Real> v[NT][1 << R];
+    LayCtx<R> L0[NT];
+#pragma unroll
+    for (int s = 0; s < NT; ++s) lay_ctx<R>(L0[s], g, a.lat, tile0 + s, g.x1 - R, t, false);
     Cx<Real> *st = base + a.jbase + (uint64_t)jb * a.jstride;
-    if (a.jmode == 0) load_tile<Real, R, true>(v, st, L0);
+    if (a.jmode == 0) load_tiles<Real, R, NT>(v, st, L0);
 
     const JobDev J = job_record(a.jobs, jb, a.job_inline);
     const LevelOp op = a.force_plain ? LevelOp{a.group, kPlainH, 0, -1, -1, 0, 0, 0}
@@ -651,24 +756,24 @@ __global__ void __launch_bounds__(512) level_kernel_full(LevelArgs a) {
     if (op.kind == kIdle || op.group != a.group) return;  // uniform per block
     if (a.jmode != 0) {
         st = base + J.offset;
-        load_tile<Real, R, true>(v, st, L0);
+        load_tiles<Real, R, NT>(v, st, L0);
     }
 
     Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
-    const uint32_t lds_elems = (1u << g.m) + (1u << (g.m - R));
+    const uint32_t lds_elems = (1u << (g.m - R * NL)) * (uint32_t)g.lds_blk;
     Cx<Real> *tab = lds + lds_elems;
     const int W = a.lat.n + 1;
     double2 *fac = align16<double2>(tab + (a.lat.nst + 1) * W);
     double *red = reinterpret_cast<double *>(fac + (a.lat.nst + 1 + W));
 
     if constexpr (KS != kAnyKind) {
-        pass_full<Real, R, NL, KS>(a, J, op, tile, t, v, st, L0, lds, tab, fac, red);
+        pass_multi<Real, R, NL, KS, NT>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red);
     } else {
         switch (op.kind) {
-            case kPhaseB: pass_full<Real, R, NL, kPhaseB>(a, J, op, tile, t, v, st, L0, lds, tab, fac, red); break;
-            case kPlainH: pass_full<Real, R, NL, kPlainH>(a, J, op, tile, t, v, st, L0, lds, tab, fac, red); break;
-            case kHalfIn: pass_full<Real, R, NL, kHalfIn>(a, J, op, tile, t, v, st, L0, lds, tab, fac, red); break;
-            default: pass_full<Real, R, NL, kHalfOut>(a, J, op, tile, t, v, st, L0, lds, tab, fac, red); break;
+            case kPhaseB: pass_multi<Real, R, NL, kPhaseB, NT>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
+            case kPlainH: pass_multi<Real, R, NL, kPlainH, NT>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
+            case kHalfIn: pass_multi<Real, R, NL, kHalfIn, NT>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
+            default: pass_multi<Real, R, NL, kHalfOut, NT>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
         }
     }
 }
@@ -1097,20 +1202,46 @@ static hipError_t do_level_nt(const LevelArgs &a, dim3 grid, size_t lds, hipStre
     return hipGetLastError();
 }
 
-template <typename Real, int R, int NL, int KS>
+template <typename Real, int R, int NL, int KS, int NT>
 static hipError_t do_level_full_ks(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
-    const void *fn = reinterpret_cast<const void *>(&level_kernel_full<Real, R, NL, KS>);
+    const void *fn = reinterpret_cast<const void *>(&level_kernel_full<Real, R, NL, KS, NT>);
     hipError_t e = set_lds(fn, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((level_kernel_full<Real, R, NL, KS>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
+    hipLaunchKernelGGL((level_kernel_full<Real, R, NL, KS, NT>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
     return hipGetLastError();
 }
 
+template <typename Real, int R, int NL, int NT>
+static hipError_t do_level_full_nt(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    if (a.kind_hint == kPhaseB) return do_level_full_ks<Real, R, NL, kPhaseB, NT>(a, grid, lds, s);
+    if (a.kind_hint == kPlainH) return do_level_full_ks<Real, R, NL, kPlainH, NT>(a, grid, lds, s);
+    return do_level_full_ks<Real, R, NL, kAnyKind, NT>(a, grid, lds, s);
+}
+
+// Shapes with a two-tile variant (complex64 only: two register windows of
+// 2^R complex doubles would not fit the register budget).
+#define Z2H_PAIR_SHAPES(X) X(5, 2) X(4, 2) X(4, 3) X(3, 2) X(3, 3)
+
 template <typename Real, int R, int NL>
 static hipError_t do_level_full(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
-    if (a.kind_hint == kPhaseB) return do_level_full_ks<Real, R, NL, kPhaseB>(a, grid, lds, s);
-    if (a.kind_hint == kPlainH) return do_level_full_ks<Real, R, NL, kPlainH>(a, grid, lds, s);
-    return do_level_full_ks<Real, R, NL, kAnyKind>(a, grid, lds, s);
+    if (a.geom.pair == 2) {
+        if constexpr (sizeof(Real) == 4) {
+#define Z2H_PAIR_CALL(r, nl) \
+            if (R == r && NL == nl) return do_level_full_nt<Real, r, nl, 2>(a, dim3(grid.x / 2), lds, s);
+            Z2H_PAIR_SHAPES(Z2H_PAIR_CALL)
+#undef Z2H_PAIR_CALL
+        }
+        return hipErrorInvalidValue;
+    }
+    return do_level_full_nt<Real, R, NL, 1>(a, grid, lds, s);
+}
+
+bool pair_level_ok(bool c128, int R, int NL) {
+    if (c128) return false;
+#define Z2H_OK_PAIR(r, nl) if (R == r && NL == nl) return true;
+    Z2H_PAIR_SHAPES(Z2H_OK_PAIR)
+#undef Z2H_OK_PAIR
+    return false;
 }
 
 // (R, NL) shapes compiled as straight-line kernels.
@@ -1208,11 +1339,19 @@ static hipError_t prep_real() {
     Z2H_PREP_GEN(2) Z2H_PREP_GEN(3) Z2H_PREP_GEN(4) Z2H_PREP_GEN(5)
 #undef Z2H_PREP_GEN
 #define Z2H_PREP_FULL(r, nl) \
-    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kAnyKind>), kMaxLdsBytes); \
-    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kPhaseB>), kMaxLdsBytes); \
-    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kPlainH>), kMaxLdsBytes);
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kAnyKind, 1>), kMaxLdsBytes); \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kPhaseB, 1>), kMaxLdsBytes); \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kPlainH, 1>), kMaxLdsBytes);
     Z2H_FULL_LEVEL_SHAPES(Z2H_PREP_FULL)
 #undef Z2H_PREP_FULL
+    if constexpr (sizeof(Real) == 4) {
+#define Z2H_PREP_PAIR(r, nl) \
+        if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kAnyKind, 2>), kMaxLdsBytes); \
+        if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kPhaseB, 2>), kMaxLdsBytes); \
+        if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kPlainH, 2>), kMaxLdsBytes);
+        Z2H_PAIR_SHAPES(Z2H_PREP_PAIR)
+#undef Z2H_PREP_PAIR
+    }
 #define Z2H_PREP_RES(r, nl) \
     if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&resident_kernel<Real, r, nl>), kMaxLdsBytes);
     Z2H_FULL_RESIDENT_SHAPES(Z2H_PREP_RES)

@@ -133,9 +133,54 @@ def test_autotuner_candidates_are_valid_plans(Lx, Ly, dt):
 
 
 def test_schedule_strings_rejected():
-    for bad in ("split=10:5:13:0", "split=10:5:13:1/8:4:13:5", "split=10:5:13:0/8:4:19:11", "split=10:5:16:0/8:4:13:5", "nonsense"):
+    for bad in ("split=10:5:13:0", "split=10:5:13:1/8:4:13:5", "split=10:5:13:0/8:4:19:11", "split=10:5:16:0/8:4:13:5",
+                "split=10:5:11:0:2/8:4:13:5", "split=10:5:11:0/8:4:13:5:3", "nonsense"):
         with pytest.raises(z2h.Z2HError):
             z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C64, bad)
+    # two-tile blocks exist for complex64 only
+    with pytest.raises(z2h.Z2HError):
+        z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C128, "split=12:4:12:0/6:3:10:4:2")
+    ok = z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C64, "split=10:5:11:0/8:4:12:4:2")
+    assert z2h.z2h_plan_describe(ok)["groups"][1]["pair"] == 2
+    check_geometry(ok)
+
+
+def check_full_lds(g, n, esize):
+    """Re-enact the full-window kernels' LDS placement: one slot per local
+    index inside the allocated block, and the bank pattern of every layout
+    change (each group of 2^lb consecutive lanes of a wave, 2^lb = 256 bytes /
+    element size, for both the writes and the reads)."""
+    R, NL, m, c, x0, x1 = g["R"], g["full"], g["m"], g["c"], g["x0"], g["x1"]
+    G = R * NL
+    blk = g["lds_blk"]
+    assert blk >= (1 << G) + (1 << (G - R))
+    lb = 5 if esize == 8 else 4
+
+    def place(e):
+        tb = (e >> x0) & ((1 << G) - 1)
+        u = (e & ((1 << x0) - 1)) | ((e >> x1) << x0)
+        return tb + (tb >> R) + u * blk
+
+    e = np.arange(1 << m)
+    a = place(e)
+    assert np.unique(a).size == e.size
+    assert a.max() < (1 << (m - G)) * blk
+    assert (1 << (m - G)) * blk * esize + (n // 2 + 1) * (n + 1) * esize <= LDS_LIMIT
+    threads = 1 << (m - R)
+    t = np.arange(threads)
+    for j in range(NL):
+        p = x1 - R * (j + 1)
+        base = place(lay_base(p, t, R))
+        for q in range(1 << R):
+            addr = base + (q << (G - R * (j + 1))) + ((q << (G - R * (j + 1))) >> R)
+            # the compile-time offset form equals the direct placement
+            assert np.array_equal(addr, place(lay_base(p, t, R) | (q << p)))
+            for w0 in range(0, min(threads, 64), 1 << lb):
+                grp = addr[w0:w0 + (1 << lb)] % (1 << lb)
+                worst = np.bincount(grp).max()
+                # conflict-free, except that contiguous groups with narrow
+                # windows keep the transform padding's at most 2-way overlap
+                assert worst <= (1 if c > 0 else 2), (g, j, q, w0, worst)
 
 
 def check_geometry(plan):
@@ -185,6 +230,15 @@ def check_geometry(plan):
                     i_split = glob(g, tile, lay_base(p, t, R)) + (q << gs)
                     assert np.array_equal(i_direct, i_split)
                     assert i_direct.max() < (1 << n)
+        if g["full"] and K > 1:
+            check_full_lds(g, n, 16 if d["c128"] else 8)
+        if g.get("pair", 1) == 2:
+            # two-tile blocks: tiles 2u and 2u + 1 differ only in global bit c,
+            # so a block's rows are 2^(c+1) contiguous amplitudes
+            assert gi > 0 and g["tiles_log2"] >= 1 and b0 - c >= 1 and g["full"]
+            e = np.arange(1 << m)
+            for u in (0, (1 << (g["tiles_log2"] - 1)) - 1):
+                assert np.array_equal(glob(g, 2 * u + 1, e) - glob(g, 2 * u, e), np.full(e.size, 1 << c))
         if n <= 18:
             # all tiles together cover the state exactly once
             e = np.arange(1 << m)
