@@ -1458,8 +1458,7 @@ LevelOp level_op_host(int lev, int K, int S, int k0, int order) {
 
 hipError_t launch_reduce_parts(const JobDev *jobs, const JobDev &inl, int njobs, int parts,
                                hipStream_t s) {
-    const int chunks = (parts + kReduceChunk - 1) / kReduceChunk;
-    if (chunks > kReduceChunk) return hipErrorInvalidValue;  // slots sized for one second stage
+    const int chunks = (parts + kReduceChunk - 1) / kReduceChunk;  // slots after the partials (norm_parts)
     hipLaunchKernelGGL(reduce_parts_stage1, dim3(chunks, njobs), dim3(256), 0, s, jobs, inl, parts);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
