@@ -281,6 +281,55 @@ def paper_protocol(z2h, torch):
             "traces": "observables every 100 steps (every 1e-3 in g)"}
 
 
+def adjoint_leg(z2h, torch):
+    """Gradient of the final energy (3x3, complex128, M = 200, T = 20, loss at
+    (1, 1, 0.3, 0.3)) with respect to the 400 per-step schedule values, by
+    the adjoint sweep through torch.autograd; timed beside the forward ramp."""
+    from paper_2108_13410_amd import workloads
+    from paper_2108_13410_amd.autograd import EvolveEnergy
+    M, T = 200, 20.0
+    c0, c1 = workloads.TORIC, workloads.point(0.3, 0.3)
+    sZ0, sX0 = workloads.adjoint_angles(M)
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C128)
+    times = []
+    for _ in range(3):
+        sZ = torch.tensor(sZ0, dtype=torch.float64, requires_grad=True)
+        sX = torch.tensor(sX0, dtype=torch.float64, requires_grad=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        L = EvolveEnergy.apply(sZ, sX, plan, c0, c1, T / M, c1)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        L.backward()
+        torch.cuda.synchronize()
+        times.append((t1 - t0, time.perf_counter() - t1))
+    fwd, bwd = min(t[0] for t in times), min(t[1] for t in times)
+    return {"lattice": "3x3", "steps": M, "precision": "complex128", "parameters": 2 * M,
+            "loss": float(L.detach()), "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3,
+            "backward_over_forward": bwd / fwd, "grad_norm": float(torch.cat([sZ.grad, sX.grad]).norm())}
+
+
+def mixed_leg(z2h, torch):
+    """The mixed batch (32 each of 2x2, 2x3 and 3x3 tori, (hx, hz) ~ U[0, 0.6]^2,
+    M ~ U{200..1000}, T = 20, seeded) in complex64 as one batch run."""
+    from paper_2108_13410_amd import workloads
+    jobs = workloads.mixed()
+    batch = make_batch(jobs, z2h.Z2H_C64, z2h)
+    states = torch.empty(batch.states_bytes, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(batch.ws_bytes, dtype=torch.uint8, device="cuda")
+    obs = torch.zeros(len(jobs) * z2h.Z2H_OBS_DOUBLES, dtype=torch.float64, device="cuda")
+    z2h.z2h_batch_run(batch, states, ws, obs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(3):
+        z2h.z2h_batch_run(batch, states, ws, obs)
+    torch.cuda.synchronize()
+    el = (time.perf_counter() - t0) / 3
+    amp = sum((1 << (2 * j["Lx"] * j["Ly"])) * j["M"] for j in jobs)
+    return {"jobs": len(jobs), "lattices": "32 x 2x2, 32 x 2x3, 32 x 3x3", "ms_per_run": el * 1e3,
+            "amp_updates_per_s": amp / el, "launch": "HIP graph (resident small lattices on a side stream)"}
+
+
 def cpu_baseline(seconds_hint):
     """The FP64 oracle (test infrastructure, untuned) on one scan point."""
     import numpy as np  # noqa: F401
@@ -313,6 +362,7 @@ def main():
     ap.add_argument("--no-4x4", action="store_true")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-protocol", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint and mixed-batch legs")
     ap.add_argument("--tune-cache", default=None,
                     help="schedule cache: loaded if it has the needed entries, else written by the autotuner "
                          "(default: the table shipped with the package, never written)")
@@ -444,6 +494,11 @@ def main():
         print(f"plain c128: {per_point*1e3:.2f} ms/point", file=sys.stderr, flush=True)
     if not args.no_4x4:
         line["torus_4x4"] = four_by_four(z2h, torch, not args.no_tune, args.tune_cache)
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_leg(z2h, torch)
+        line["mixed_batch"] = mixed_leg(z2h, torch)
+        print(f"adjoint: {line['adjoint']['backward_ms']:.1f} ms, mixed batch: {line['mixed_batch']['ms_per_run']:.1f} ms",
+              file=sys.stderr, flush=True)
     if not args.no_protocol:
         line["paper_protocol"] = paper_protocol(z2h, torch)
         print(f"paper protocol: {line['paper_protocol']['trotter_steps_per_s']:.0f} steps/s", file=sys.stderr, flush=True)
