@@ -283,6 +283,37 @@ z2h_status z2h_batch_run(z2h_batch *batch, void *d_states, void *d_ws, size_t ws
                          double *d_obs, void *stream);
 void z2h_batch_destroy(z2h_batch *batch); /* NULL-safe */
 
+/*
+ * Traced batch runs (Sec. V diagnostics over a whole scan): every job's ramp
+ * is split into segments of `every` Trotter steps (steps [s*every,
+ * (s+1)*every) clipped to the job's M steps, joined with unmerged x halves,
+ * so each sample is the state of the uninterrupted ramp) and all jobs are
+ * observed after each segment with the couplings of the point reached,
+ * c_start + (k/M) (c_end - c_start) after k steps.  A job that has finished
+ * is observed again in later samples.  Lattices whose jobs mix the two step
+ * orders are rejected.
+ *
+ * z2h_batch_trace_sizes: samples per job (ceil(max M / every)) and the
+ * workspace a traced run needs (the batch's own plus the segment records).
+ *
+ * z2h_batch_run_trace: like z2h_batch_run (d_obs receives the final
+ * observables), plus d_trace (device, samples * njobs * Z2H_OBS_DOUBLES
+ * doubles, sample-major: the record of job j in sample s starts at
+ * (s * njobs + j) * Z2H_OBS_DOUBLES).  The launch sequence is recorded in a
+ * HIP graph of its own (or issued directly with timing enabled).  The first
+ * run with a workspace or interval uploads the segment records into the
+ * workspace tail (synchronizing the stream); later runs with the same
+ * workspace and interval reuse them, so the caller must not write into the
+ * workspace between such runs.  Errors: Z2H_ERR_INVALID for a NULL or
+ * misaligned buffer, every < 1, mixed step orders within a lattice or a
+ * batch created on another device; Z2H_ERR_WORKSPACE if ws_bytes is below
+ * z2h_batch_trace_sizes' figure.
+ */
+z2h_status z2h_batch_trace_sizes(const z2h_batch *batch, int32_t every, int64_t *samples_per_job,
+                                 size_t *ws_bytes);
+z2h_status z2h_batch_run_trace(z2h_batch *batch, void *d_states, void *d_ws, size_t ws_bytes, double *d_obs,
+                               int32_t every, double *d_trace, void *stream);
+
 /* Per-kind pass-kernel times (see z2h_timing_read) of the most recent
  * z2h_batch_run made while timing was enabled.  With timing enabled a batch
  * run issues its launch sequence directly on the stream, with an event pair

@@ -67,6 +67,13 @@ struct z2h_batch {
     double *g_obs;
     void *up_ws;                     // workspace the device job records point into
     int chunk_jobs;                  // jobs evolved together (0: all)
+    // traced runs (z2h_batch_run_trace): graph and the inputs it was recorded for
+    hipGraphExec_t exec_t;
+    void *t_states, *t_ws;
+    double *t_obs, *t_trace;
+    int t_every;
+    void *t_up_ws;                   // workspace holding the uploaded segment records
+    int t_up_every;
     std::vector<TimedLaunch> timed;  // event pairs of the last timed run
     int device;
 };
@@ -84,6 +91,7 @@ static void loops_for(const Plan &P, uint32_t *zl, int &nz, uint32_t *xl, int &n
 static void free_batch(z2h_batch *b) {
     if (!b) return;
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->exec_t) (void)hipGraphExecDestroy(b->exec_t);
     for (auto &t : b->timed) {
         (void)hipEventDestroy(t.a);
         (void)hipEventDestroy(t.b);
@@ -189,6 +197,140 @@ static z2h_status enqueue(z2h_batch *b, void *states, void *ws, double *obs, hip
         if (st) return st;
     }
     return Z2H_OK;
+}
+
+// ---------------------------------------------------------------- traces
+//
+// A traced run splits every job's ramp into segments of `every` steps
+// (steps [s*every, (s+1)*every) of job j, clipped to its M steps) and observes
+// all jobs after each segment.  Segments join with unmerged x halves, so the
+// sampled states are exactly those of the uninterrupted Trotter product.  The
+// per-segment job records and observation couplings live after the batch's
+// own workspace.
+
+static int64_t trace_samples(const z2h_batch *b, int every) {
+    int64_t maxM = 0;
+    for (const auto &g : b->groups)
+        for (const auto &J : g.h_jobs) maxM = std::max<int64_t>(maxM, J.steps);
+    return maxM <= 0 ? 0 : (maxM + every - 1) / every;
+}
+
+static size_t trace_ws_bytes(const z2h_batch *b, int64_t nseg) {
+    Carver c{nullptr, b->ws_bytes};
+    for (const auto &g : b->groups) {
+        c.take(sizeof(JobDev) * g.h_jobs.size() * (size_t)nseg);
+        c.take(sizeof(double) * 4 * g.h_jobs.size() * (size_t)nseg);
+    }
+    return align256(c.off);
+}
+
+struct TracePieces {
+    std::vector<JobDev *> d_seg;              // per group: nseg x nj records
+    std::vector<double *> d_segH;             // per group: nseg x nj x 4 couplings
+    std::vector<std::vector<JobDev>> h_seg;   // host copies (step counts for the launch sequence)
+};
+
+static void trace_layout(const z2h_batch *b, int64_t nseg, char *ws, TracePieces &T) {
+    Carver c{ws, b->ws_bytes};
+    T.d_seg.clear();
+    T.d_segH.clear();
+    for (const auto &g : b->groups) {
+        T.d_seg.push_back((JobDev *)c.take(sizeof(JobDev) * g.h_jobs.size() * (size_t)nseg));
+        T.d_segH.push_back((double *)c.take(sizeof(double) * 4 * g.h_jobs.size() * (size_t)nseg));
+    }
+}
+
+// Host records of every segment (norm partials from the current workspace).
+static void trace_records(const z2h_batch *b, int every, int64_t nseg, TracePieces &T,
+                          std::vector<std::vector<double>> &H) {
+    T.h_seg.assign(b->groups.size(), {});
+    H.assign(b->groups.size(), {});
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        const Group &g = b->groups[gi];
+        const size_t nj = g.h_jobs.size();
+        auto &rec = T.h_seg[gi];
+        auto &hh = H[gi];
+        rec.resize(nj * (size_t)nseg);
+        hh.resize(4 * nj * (size_t)nseg);
+        for (int64_t sg = 0; sg < nseg; ++sg) {
+            for (size_t j = 0; j < nj; ++j) {
+                JobDev r = g.h_jobs[j];
+                const int64_t M = r.M;
+                const int64_t k0 = std::min<int64_t>(sg * every, M), k1 = std::min<int64_t>((sg + 1) * every, M);
+                r.k_begin = (int32_t)k0;
+                r.steps = (int32_t)(k1 - k0);
+                r.norm_trace = nullptr;
+                rec[(size_t)sg * nj + j] = r;
+                const double f = M > 0 ? (double)k1 / (double)M : 1.0;
+                for (int q = 0; q < 4; ++q) hh[((size_t)sg * nj + j) * 4 + q] = r.c0[q] + f * (r.c1[q] - r.c0[q]);
+            }
+        }
+    }
+}
+
+static z2h_status enqueue_init(z2h_batch *b, void *states, hipStream_t s) {
+    for (auto &g : b->groups) {
+        InitArgs a;
+        memset(&a, 0, sizeof a);
+        a.states = states;
+        a.jobs = g.d_init;
+        a.lat = g.P.lat;
+        hipError_t e = launch_init(g.P.c128, a, (unsigned)g.jobs.size(), s);
+        if (e != hipSuccess) return fail(Z2H_ERR_HIP, "init launch failed: %s", hipGetErrorString(e));
+        if (!g.h_p1p.empty()) {
+            JobSet J;
+            memset(&J, 0, sizeof J);
+            J.d_jobs = g.d_p1p;
+            J.h_jobs = g.h_p1p.data();
+            J.njobs = (int)g.h_p1p.size();
+            z2h_status st = full_transform(g.P, states, J, s);
+            if (st) return st;
+        }
+    }
+    return Z2H_OK;
+}
+
+static z2h_status enqueue_observe(z2h_batch *b, void *states, void *scratch, double *out,
+                                  const std::vector<const double *> &Hsel, hipStream_t s) {
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        Group &g = b->groups[gi];
+        ObsBuffers B;
+        memset(&B, 0, sizeof B);
+        B.scratch = scratch;
+        B.src_off = g.d_off;
+        B.dst_off = g.d_off;
+        B.partZ = g.partZ;
+        B.partX = g.partX;
+        B.H = Hsel[gi];
+        B.out = out;
+        B.out_index = g.d_out;
+        z2h_status st = run_observe(g.P, states, (int)g.jobs.size(), B, g.zl, g.nz, g.xl, g.nx, s);
+        if (st) return st;
+    }
+    return Z2H_OK;
+}
+
+static z2h_status enqueue_traced(z2h_batch *b, void *states, void *ws, double *obs, double *trace,
+                                 int64_t nseg, const TracePieces &T, hipStream_t s) {
+    z2h_status st = enqueue_init(b, states, s);
+    if (st) return st;
+    std::vector<const double *> Hs(b->groups.size());
+    for (int64_t sg = 0; sg < nseg; ++sg) {
+        for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+            const Group &g = b->groups[gi];
+            const size_t nj = g.h_jobs.size();
+            JobSet J;
+            memset(&J, 0, sizeof J);
+            J.d_jobs = T.d_seg[gi] + (size_t)sg * nj;
+            J.h_jobs = T.h_seg[gi].data() + (size_t)sg * nj;
+            J.njobs = (int)nj;
+            if ((st = run_levels(g.P, states, J, s))) return st;
+            Hs[gi] = T.d_segH[gi] + (size_t)sg * nj * 4;
+        }
+        if ((st = enqueue_observe(b, states, ws, trace + (size_t)sg * b->njobs * kObsQ, Hs, s))) return st;
+    }
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) Hs[gi] = b->groups[gi].d_H;
+    return enqueue_observe(b, states, ws, obs, Hs, s);
 }
 
 static z2h_status upload_jobs(z2h_batch *b, void *ws) {
@@ -454,6 +596,100 @@ z2h_status z2h_batch_timing(z2h_batch *b, int64_t counts[4], double ms[4]) {
         ms[t.kind] += x;
     }
     return Z2H_OK;
+}
+
+z2h_status z2h_batch_trace_sizes(const z2h_batch *b, int32_t every, int64_t *samples_per_job, size_t *ws_bytes) {
+    if (!b) return fail(Z2H_ERR_INVALID, "batch is NULL");
+    if (every < 1) return fail(Z2H_ERR_INVALID, "trace interval %d < 1", every);
+    const int64_t ns = trace_samples(b, every);
+    if (samples_per_job) *samples_per_job = ns;
+    if (ws_bytes) *ws_bytes = trace_ws_bytes(b, ns);
+    return Z2H_OK;
+}
+
+z2h_status z2h_batch_run_trace(z2h_batch *b, void *d_states, void *d_ws, size_t ws_bytes, double *d_obs,
+                               int32_t every, double *d_trace, void *stream) {
+    try {
+        if (!b) return fail(Z2H_ERR_INVALID, "batch is NULL");
+        z2h_status st = validate_state_ptr(d_states, "d_states");
+        if (st) return st;
+        if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(Z2H_ERR_INVALID, "d_ws NULL or not 256-byte aligned");
+        if (!d_obs || !d_trace) return fail(Z2H_ERR_INVALID, "d_obs or d_trace is NULL");
+        if (every < 1) return fail(Z2H_ERR_INVALID, "trace interval %d < 1", every);
+        for (const auto &g : b->groups)
+            for (const auto &J : g.h_jobs)
+                if (J.order != g.h_jobs[0].order)
+                    return fail(Z2H_ERR_INVALID, "traced batches need one step order per lattice");
+        const int64_t nseg = trace_samples(b, every);
+        const size_t need = trace_ws_bytes(b, nseg);
+        if (ws_bytes < need) return fail(Z2H_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+        int dev = -1;
+        if (hipGetDevice(&dev) != hipSuccess || (b->device >= 0 && dev != b->device))
+            return fail(Z2H_ERR_INVALID, "batch used on another device");
+        hipStream_t s = (hipStream_t)stream;
+        if (b->up_ws != d_ws) {
+            HIP_TRY(hipStreamSynchronize(s));
+            if ((st = upload_jobs(b, d_ws))) return st;
+            b->up_ws = d_ws;
+        }
+        TracePieces T;
+        std::vector<std::vector<double>> H;
+        trace_layout(b, nseg, (char *)d_ws, T);
+        trace_records(b, every, nseg, T, H);
+        if (b->t_up_ws != d_ws || b->t_up_every != every) {
+            HIP_TRY(hipStreamSynchronize(s));
+            for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+                HIP_TRY(hipMemcpy(T.d_seg[gi], T.h_seg[gi].data(), sizeof(JobDev) * T.h_seg[gi].size(),
+                                  hipMemcpyHostToDevice));
+                HIP_TRY(hipMemcpy(T.d_segH[gi], H[gi].data(), sizeof(double) * H[gi].size(), hipMemcpyHostToDevice));
+            }
+            b->t_up_ws = d_ws;
+            b->t_up_every = every;
+        }
+        if (t_timing) {
+            HIP_TRY(hipStreamSynchronize(s));
+            for (auto &t : b->timed) {
+                (void)hipEventDestroy(t.a);
+                (void)hipEventDestroy(t.b);
+            }
+            b->timed.clear();
+            std::vector<TimedLaunch> saved;
+            saved.swap(t_launches);
+            st = enqueue_traced(b, d_states, d_ws, d_obs, d_trace, nseg, T, s);
+            b->timed.swap(t_launches);
+            t_launches.swap(saved);
+            return st;
+        }
+        if (!b->exec_t || b->t_states != d_states || b->t_ws != d_ws || b->t_obs != d_obs ||
+            b->t_trace != d_trace || b->t_every != every) {
+            if (b->exec_t) {
+                HIP_TRY(hipStreamSynchronize(s));
+                (void)hipGraphExecDestroy(b->exec_t);
+                b->exec_t = nullptr;
+            }
+            HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
+            st = enqueue_traced(b, d_states, d_ws, d_obs, d_trace, nseg, T, b->cap);
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamEndCapture(b->cap, &graph);
+            if (st) {
+                if (graph) (void)hipGraphDestroy(graph);
+                return st;
+            }
+            if (e != hipSuccess) return fail(Z2H_ERR_HIP, "graph capture failed: %s", hipGetErrorString(e));
+            e = hipGraphInstantiate(&b->exec_t, graph, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) return fail(Z2H_ERR_HIP, "graph instantiation failed: %s", hipGetErrorString(e));
+            b->t_states = d_states;
+            b->t_ws = d_ws;
+            b->t_obs = d_obs;
+            b->t_trace = d_trace;
+            b->t_every = every;
+        }
+        HIP_TRY(hipGraphLaunch(b->exec_t, s));
+        return Z2H_OK;
+    } catch (...) {
+        return fail(Z2H_ERR_OOM, "exception in z2h_batch_run_trace");
+    }
 }
 
 void z2h_batch_destroy(z2h_batch *b) { free_batch(b); }

@@ -103,6 +103,8 @@ SIGNATURES = {
     "z2h_tune_load": (_i32, [ctypes.c_char_p]),
     "z2h_plan_create_config": (_i32, [_i32, _i32, _i32, ctypes.c_char_p, ctypes.POINTER(_P)]),
     "z2h_tune_candidates": (_i32, [_i32, _i32, _i32, ctypes.c_char_p, _sz]),
+    "z2h_batch_trace_sizes": (_i32, [_P, _i32, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_sz)]),
+    "z2h_batch_run_trace": (_i32, [_P, _P, _P, _sz, _P, _i32, _P, _P]),
     "z2h_path_evolve": (_i32, [_P, _P, _P, _sz, ctypes.POINTER(z2h_path), _P, _i32, _P, _i32, _P,
                                 ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _P]),
     "z2h_timing_enable": (_i32, [_i32]),
@@ -360,6 +362,18 @@ def z2h_batch_create(Lx, Ly, scheds, inits, obsH, dtype):
 def z2h_batch_run(batch, states, ws, d_obs, stream=None):
     _check(lib().z2h_batch_run(batch.handle, _ptr(states), _ptr(ws), ws.numel() * ws.element_size(),
                                _ptr(d_obs), _stream(stream)))
+
+
+def z2h_batch_trace_sizes(batch, every):
+    ns = ctypes.c_int64()
+    wb = ctypes.c_size_t()
+    _check(lib().z2h_batch_trace_sizes(batch.handle, int(every), ctypes.byref(ns), ctypes.byref(wb)))
+    return ns.value, wb.value
+
+
+def z2h_batch_run_trace(batch, states, ws, d_obs, every, d_trace, stream=None):
+    _check(lib().z2h_batch_run_trace(batch.handle, _ptr(states), _ptr(ws), ws.numel() * ws.element_size(),
+                                     _ptr(d_obs), int(every), _ptr(d_trace), _stream(stream)))
 
 
 def z2h_batch_destroy(batch):

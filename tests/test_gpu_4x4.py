@@ -173,9 +173,11 @@ def test_three_group_schedule_against_oracle(Lx, Ly, dtype, M):
 def test_4x4_two_tile_schedule_bitwise():
     """The autotuned complex64 4x4 schedule (two 128-byte tiles per block in
     both strided groups) computes exactly what the planner's default schedule
-    computes: blocks only regroup tiles, so 6 Trotter steps of the 4x4 ramp
-    leave bit-identical states (checked on 2^20 sampled amplitudes and the
-    full-state observables)."""
+    computes: blocks only regroup tiles and the renormalisation sums per-tile
+    partials in the same order, so 6 Trotter steps of the 4x4 ramp leave
+    bit-identical states (checked on 2^20 sampled amplitudes). The observables
+    are FP64 sums whose partials follow each plan's own first-group tiling,
+    so they agree to rounding (1e-13 relative)."""
     print("case 4x4 c64 two-tile schedule vs default", flush=True)
     cfg = "split=12:4:12:0/10:5:14:4:2/10:5:14:4:2"
     plans = [z2h.z2h_plan_create(4, 4, z2h.Z2H_C64), z2h.z2h_plan_create_config(4, 4, z2h.Z2H_C64, cfg)]
@@ -194,4 +196,5 @@ def test_4x4_two_tile_schedule_bitwise():
         samples.append(torch.view_as_real(psi[idx]).cpu())
         obs.append(z2h.z2h_observe(plan, psi, ws, job["c1"]))
     assert torch.equal(samples[0], samples[1])
-    assert obs[0]["energy"] == obs[1]["energy"] and obs[0]["norm"] == obs[1]["norm"]
+    for key in ("energy", "norm", "mx", "mz"):
+        assert abs(obs[0][key] - obs[1][key]) <= 1e-13 * max(1.0, abs(obs[0][key])), key

@@ -128,3 +128,49 @@ def test_full_scan_1024_points():
         oo = oracle_observables(3, 3, o, job["c1"])
         assert abs(oo["energy"] - ref[j]["energy"]) < 1e-10
         compare_observables(row_to_obs(obs[j]), oo, 1e-5, 18)
+
+
+@pytest.mark.parametrize("dtype", [z2h.Z2H_C128, z2h.Z2H_C64])
+def test_traced_batch_against_oracle(dtype):
+    """z2h_batch_run_trace on a mixed batch (2x2, 2x3, 3x3; uneven step
+    counts): every sample of every job equals the oracle's observables after
+    the same steps (observed with the couplings of the point reached; a job
+    that has finished repeats its final state), and the final record equals
+    the untraced run's to rounding."""
+    rng = np.random.default_rng(11)
+    jobs = []
+    for (Lx, Ly) in ((3, 3), (2, 2), (2, 3), (3, 3), (2, 3), (2, 2)):
+        hx, hz = rng.uniform(0, 0.6, 2)
+        M = int(rng.integers(8, 30))
+        jobs.append(dict(Lx=Lx, Ly=Ly, c0=workloads.TORIC, c1=(1.0, 1.0, hx, hz), T=0.06 * M, M=M))
+    every = 6
+    print(f"case traced batch dtype={dtype}", flush=True)
+    b, states, obs_plain = run_batch(jobs, dtype)
+    ns, wsb = z2h.z2h_batch_trace_sizes(b, every)
+    assert ns == -(-max(j["M"] for j in jobs) // every)
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    obs = torch.zeros(len(jobs) * z2h.Z2H_OBS_DOUBLES, dtype=torch.float64, device="cuda")
+    trace = torch.zeros(ns * len(jobs) * z2h.Z2H_OBS_DOUBLES, dtype=torch.float64, device="cuda")
+    for _ in range(2):  # graph recorded, then replayed
+        z2h.z2h_batch_run_trace(b, states, ws, obs, every, trace)
+    torch.cuda.synchronize()
+    tr = trace.cpu().numpy().reshape(ns, len(jobs), -1)
+    ob = obs.cpu().numpy().reshape(len(jobs), -1)
+    tol = 1e-10 if dtype == z2h.Z2H_C128 else 1e-5
+    for j, job in enumerate(jobs):
+        n = 2 * job["Lx"] * job["Ly"]
+        psi = oracle.init_psi1(job["Lx"], job["Ly"])
+        a, c = np.array(job["c0"], float), np.array(job["c1"], float)
+        M, dt = job["M"], job["T"] / job["M"]
+        done = 0
+        for s in range(ns):
+            k1 = min((s + 1) * every, M)
+            if k1 > done:
+                ks = np.arange(done, k1)
+                sv = (ks + 0.5) / M
+                oracle.evolve(job["Lx"], job["Ly"], psi, tuple(a), tuple(c), k1 - done, dt, sZ=sv, sX=sv)
+                done = k1
+            ref = oracle_observables(job["Lx"], job["Ly"], psi, tuple(a + (k1 / M) * (c - a)))
+            compare_observables(row_to_obs(tr[s, j]), ref, tol, n)
+        assert tr[ns - 1, j, 1] == ob[j, 1]
+        compare_observables(row_to_obs(ob[j]), row_to_obs(obs_plain[j]), tol, n)
