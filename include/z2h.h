@@ -321,6 +321,76 @@ z2h_status z2h_batch_run_trace(z2h_batch *batch, void *d_states, void *d_ws, siz
  * and their order are the same).  Synchronizes. */
 z2h_status z2h_batch_timing(z2h_batch *batch, int64_t counts[4], double ms[4]);
 
+/* ------------------------------------------------------------------ exact solvers */
+
+/*
+ * Exact references for the Trotterized evolution (Sec. VII compares against
+ * exact diagonalisation; these extend it to every lattice the plans cover).
+ * They act on states of the plan's lattice and precision (device buffers,
+ * 256-byte aligned, library bit order) and share its pass geometry.
+ *
+ * z2h_hamiltonian_apply: d_y = H d_x with H the Hamiltonian of Eq. (effi),
+ * H = -JA sum_v A_v - JB sum_p B_p - hx sum_l X_l - hz sum_l Z_l.  d_x and
+ * d_y must not overlap; d_x is not modified.  Needs no workspace.  Computed
+ * as D_Z x + 2^-n W D_X W x (W: Walsh-Hadamard transform over all links,
+ * D_Z / D_X: the diagonal terms in the computational / Hadamard basis).
+ * Errors: Z2H_ERR_INVALID for NULL, misaligned or overlapping buffers or
+ * non-finite couplings.
+ */
+z2h_status z2h_hamiltonian_apply(const z2h_plan *plan, const void *d_x, void *d_y, const z2h_couplings *H,
+                                 void *stream);
+
+/*
+ * Ground energy of H by the Lanczos recurrence.  d_v holds the start vector
+ * on entry (any nonzero vector; the library's Z2H_INIT_PLUS state overlaps
+ * the ground state whenever all couplings are >= 0, as H is then stoquastic)
+ * and is overwritten by Lanczos vectors.  d_ws: z2h_lanczos_sizes bytes (two
+ * state-sized vectors plus coefficients); must not overlap d_v.  The
+ * recurrence runs without reorthogonalisation; every 8 iterations the
+ * lowest eigenvalue of the tridiagonal matrix T is found by Sturm bisection,
+ * and the run stops when it changes by at most tol * max(1, |e0|) between
+ * checks, when an invariant subspace is reached (beta ~ 0), or after
+ * max_iter iterations.  Outputs (host): *e0 the lowest eigenvalue of T,
+ * *iters its dimension, h_alpha / h_beta (may be NULL; max_iter entries):
+ * T's diagonal and the beta_1 .. beta_iters of the recurrence (h_beta[i]
+ * couples Lanczos vectors i and i + 1).  Synchronizes the stream.  Errors:
+ * Z2H_ERR_INVALID (arguments, max_iter outside [1, 100000], tol < 0),
+ * Z2H_ERR_WORKSPACE, Z2H_ERR_NUMERIC (zero start vector, non-finite
+ * coefficients).
+ */
+z2h_status z2h_lanczos_sizes(const z2h_plan *plan, int32_t max_iter, size_t *ws_bytes);
+z2h_status z2h_lanczos_ground(const z2h_plan *plan, void *d_v, void *d_ws, size_t ws_bytes, const z2h_couplings *H,
+                              int32_t max_iter, double tol, double *h_alpha, double *h_beta, int32_t *iters,
+                              double *e0, void *stream);
+
+/*
+ * Exact stepwise evolution: for every step k_begin <= k < k_end of the
+ * schedule, d_state <- exp(-i dt H_k) d_state, where H_k has the couplings
+ * the Trotter step k uses (z-type JB, hz at sZ[k] or s_k; x-type JA, hx at
+ * sX[k] or s_k), i.e. the product of exact exponentials that the Trotter
+ * product of Eq. (decom) approximates.  Each exponential is taken in the
+ * Krylov space of dimension krylov_dim (1..32) spanned by the state and
+ * its images under H (Lanczos basis; exp(-i dt T) e_1 from a Jacobi
+ * eigendecomposition of the small tridiagonal T).  order and renorm of the
+ * schedule are ignored.  *err_est (may be NULL): the sum over steps of the
+ * a posteriori estimate |psi| beta_m |(exp(-i dt T) e_1)_m| of the Krylov
+ * truncation error.  d_ws: z2h_exact_sizes bytes (krylov_dim + 1 state-sized
+ * vectors plus coefficients); must not overlap d_state.  Synchronizes the
+ * stream once per step.  Errors as z2h_lanczos_ground, plus the schedule
+ * checks of z2h_evolve.
+ */
+z2h_status z2h_exact_sizes(const z2h_plan *plan, int32_t krylov_dim, size_t *ws_bytes);
+z2h_status z2h_exact_evolve(const z2h_plan *plan, void *d_state, void *d_ws, size_t ws_bytes,
+                            const z2h_schedule *sched, int32_t krylov_dim, double *err_est, void *stream);
+
+/* Host-only helpers of the two solvers above, for a symmetric tridiagonal
+ * matrix with diagonal alpha[0..m) and off-diagonal beta[0..m-1):
+ * z2h_tridiag_lowest: its lowest eigenvalue (Sturm bisection);
+ * z2h_tridiag_expv: exp(-i tau T) e_1 (m <= 32; Jacobi eigendecomposition). */
+z2h_status z2h_tridiag_lowest(int32_t m, const double *alpha, const double *beta, double *out);
+z2h_status z2h_tridiag_expv(int32_t m, const double *alpha, const double *beta, double tau, double *out_re,
+                            double *out_im);
+
 /* ------------------------------------------------------------------ tuning */
 
 /*

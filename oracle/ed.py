@@ -67,6 +67,34 @@ def hamiltonian(Lx, Ly, c, parts=None):
     return (-JA * P["A"] - JB * P["B"] - hx * P["X"] - hz * P["Z"]).tocsr()
 
 
+def hamiltonian_rows(Lx, Ly, c, rows, fetch):
+    """Entries (H x)_r for the oracle-basis indices r in `rows`, from the
+    definition of Eq. (effi) row by row: the plaquette and z-field terms are
+    diagonal, a star or an x field flips its links, so
+
+        (H x)_r = [-JB sum_p (-1)^{par(r & p)} - hz sum_l (1 - 2 r_l)] x_r
+                  - JA sum_v x_{r ^ v} - hx sum_l x_{r ^ 2^l}.
+
+    fetch(idx) must return x at the oracle-basis indices idx (int64 array).
+    Any lattice size: only the sampled rows and their neighbours are read."""
+    n = 2 * Lx * Ly
+    st, pl = masks(Lx, Ly)
+    JA, JB, hx, hz = (float(v) for v in c)
+    r = np.asarray(rows, dtype=np.uint64)
+    dZ = np.zeros(r.shape)
+    for m in pl:
+        dZ += 1 - 2 * _parity(r, m)
+    wz = np.zeros(r.shape)
+    for l in range(n):
+        wz += 1 - 2 * ((r >> np.uint64(l)) & np.uint64(1)).astype(np.int64)
+    out = (-JB * dZ - hz * wz) * fetch(r.astype(np.int64))
+    for m in st:
+        out = out - JA * fetch((r ^ np.uint64(int(m))).astype(np.int64))
+    for l in range(n):
+        out = out - hx * fetch((r ^ np.uint64(1 << l)).astype(np.int64))
+    return out
+
+
 def spectrum(Lx, Ly, c):
     """All eigenvalues by dense diagonalisation (small lattices only)."""
     H = hamiltonian(Lx, Ly, c).toarray()
@@ -97,6 +125,26 @@ def exact_stepwise(Lx, Ly, psi0, c0, c1, M, dt, sampling=0):
         c = (1 - s) * c0 + s * c1
         H = -c[0] * dense["A"] - c[1] * dense["B"] - c[2] * dense["X"] - c[3] * dense["Z"]
         psi = sla.expm(-1j * dt * H) @ psi
+    return psi
+
+
+def exact_stepwise_sparse(Lx, Ly, psi0, c0, c1, M, dt, sampling=0, sZ=None, sX=None):
+    """The same product of exact exponentials as exact_stepwise, applied with
+    scipy's expm_multiply to the sparse H (reaches 3x3).  sZ / sX (optional
+    arrays of M values) replace s_k for the plaquette/z-field and the
+    star/x-field couplings of step k."""
+    P = hamiltonian_parts(Lx, Ly)
+    c0 = np.asarray(c0, float)
+    c1 = np.asarray(c1, float)
+    psi = np.array(psi0, np.complex128)
+    for k in range(M):
+        s = (k + 1) / M if sampling else (k + 0.5) / M
+        sz = s if sZ is None else sZ[k]
+        sx = s if sX is None else sX[k]
+        cz = (1 - sz) * c0 + sz * c1
+        cx = (1 - sx) * c0 + sx * c1
+        H = (-cx[0] * P["A"] - cz[1] * P["B"] - cx[2] * P["X"] - cz[3] * P["Z"]).tocsr()
+        psi = spla.expm_multiply(-1j * dt * H, psi)
     return psi
 
 

@@ -18,7 +18,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           f"--offload-arch={ARCH}"]
 
-SOURCES = ["z2h_kernels.hip", "z2h_host.cpp", "z2h_batch.cpp", "z2h_adjoint.cpp", "z2h_tune.cpp", "z2h_path.cpp"]
+SOURCES = ["z2h_kernels.hip", "z2h_host.cpp", "z2h_batch.cpp", "z2h_adjoint.cpp", "z2h_tune.cpp", "z2h_path.cpp",
+           "z2h_krylov_kernels.hip", "z2h_krylov.cpp"]
 
 
 def _compile(src, verbose):

@@ -124,6 +124,75 @@ hipError_t launch_init(bool c128, const InitArgs &a, unsigned njobs, hipStream_t
 hipError_t launch_reduce_parts(const JobDev *jobs, const JobDev &inline_job, int njobs, int parts,
                                hipStream_t s);
 
+// ---- exact solvers (Hamiltonian application, Lanczos, Krylov exponential)
+
+// One tile pass of y = H x.  The passes visit groups 0, 1, .., K-1, .., 1, 0;
+// the top group multiplies by the Hadamard-basis diagonal between its
+// forward and backward transform, and the last pass adds the computational-
+// basis diagonal times x.
+struct HamArgs {
+    const void *src;           // read by this pass
+    void *dst;                 // written by this pass (may equal src)
+    const void *x;             // final pass: the vector H acts on; else null
+    double *part;              // final pass: per-workgroup Re<x, Hx> partials, or null
+    GroupGeom geom;
+    LatticeDev lat;
+    int32_t top;               // 1: transform, X-basis diagonal, transform back
+    int32_t final_pass;        // 1: add D_Z x after the transform
+    double JA, JB, hx, hz;
+    double xscale;             // 2^-n: the two unnormalised transforms
+};
+
+// Lanczos coefficients of iteration k (device): v_k = sigma_k u_k with u_k
+// the stored vector; beta_k = |u_k| (|u_0| for the start vector).
+struct LanczosCoef {
+    double alpha, beta, sigma, pad;
+};
+
+// w = sigma_k (y - alpha_k u) - beta_k sigma_{k-1} p (elementwise; w may equal p)
+// with alpha_k = sigma_k^2 sum(apart); per-block |w|^2 partials.  mode 1:
+// partials of |u|^2 only (start vector).
+struct VecArgs {
+    const void *y, *u, *p;
+    void *w;
+    uint64_t nelem;
+    const double *apart;       // Re<u, H u> partials of the final Hamiltonian pass
+    int32_t napart;
+    int32_t k;                 // iteration
+    int32_t use_prev;          // 0 at k = 0 (p not read)
+    int32_t mode;              // 0 update, 1 norm of u
+    const LanczosCoef *coef;
+    double *part;              // per-block |w|^2 (or |u|^2) partials
+};
+
+// One block: coef[k].alpha from the Hamiltonian partials and coef[k+1]
+// (beta, sigma) from the |w|^2 partials; mode 1: coef[0] from |u_0|^2.
+struct ScalarArgs {
+    const double *apart, *wpart;
+    int32_t napart, nwpart;
+    int32_t k, mode;
+    LanczosCoef *coef;
+};
+
+constexpr int kKrylovMax = 32;   // Krylov basis vectors of one exponential
+
+// psi = sum_j c_j u_j (complex coefficients from the host; u_0 may be psi).
+struct CombineArgs {
+    void *psi;
+    const void *u[kKrylovMax];
+    double cre[kKrylovMax], cim[kKrylovMax];
+    int32_t m, pad;
+    uint64_t nelem;
+};
+
+constexpr int kVecBlocks = 2048;   // blocks of the elementwise Lanczos kernels
+constexpr int kHamWorkersMax = 2048;
+
+hipError_t launch_ham(bool c128, int R, const HamArgs &a, unsigned workers, size_t lds, hipStream_t s);
+hipError_t launch_vec(bool c128, const VecArgs &a, unsigned blocks, hipStream_t s);
+hipError_t launch_scalar(const ScalarArgs &a, hipStream_t s);
+hipError_t launch_combine(bool c128, const CombineArgs &a, unsigned blocks, hipStream_t s);
+
 LevelOp level_op_host(int lev, int K, int S, int k0, int order);
 
 // Register-window shapes (R, NL) with a compiled straight-line kernel.

@@ -107,6 +107,14 @@ SIGNATURES = {
     "z2h_batch_run_trace": (_i32, [_P, _P, _P, _sz, _P, _i32, _P, _P]),
     "z2h_path_evolve": (_i32, [_P, _P, _P, _sz, ctypes.POINTER(z2h_path), _P, _i32, _P, _i32, _P,
                                 ctypes.c_int64, ctypes.POINTER(ctypes.c_int64), _P]),
+    "z2h_hamiltonian_apply": (_i32, [_P, _P, _P, ctypes.POINTER(z2h_couplings), _P]),
+    "z2h_lanczos_sizes": (_i32, [_P, _i32, ctypes.POINTER(_sz)]),
+    "z2h_lanczos_ground": (_i32, [_P, _P, _P, _sz, ctypes.POINTER(z2h_couplings), _i32, _dbl, _P, _P,
+                                  ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _P]),
+    "z2h_exact_sizes": (_i32, [_P, _i32, ctypes.POINTER(_sz)]),
+    "z2h_exact_evolve": (_i32, [_P, _P, _P, _sz, ctypes.POINTER(z2h_schedule), _i32, ctypes.POINTER(_dbl), _P]),
+    "z2h_tridiag_lowest": (_i32, [_i32, _P, _P, ctypes.POINTER(_dbl)]),
+    "z2h_tridiag_expv": (_i32, [_i32, _P, _P, _dbl, _P, _P]),
     "z2h_timing_enable": (_i32, [_i32]),
     "z2h_timing_read": (_i32, [_P, _P]),
     "z2h_version": (ctypes.c_char_p, []),
@@ -327,6 +335,71 @@ def z2h_path_evolve(plan, state, ws, path, zmasks=None, xmasks=None, stream=None
     _check(L.z2h_path_evolve(plan.handle, _ptr(state), _ptr(ws), ws.numel() * ws.element_size(),
                              ctypes.byref(path), zp, nz, xp, nx, _ptr(trace), ns.value, None, _stream(stream)))
     return trace
+
+
+# ------------------------------------------------------------------ exact solvers
+
+def z2h_hamiltonian_apply(plan, x, y, H, stream=None):
+    """y = H x (device states of the plan; must not overlap)."""
+    Hc = H if isinstance(H, z2h_couplings) else couplings(*H)
+    _check(lib().z2h_hamiltonian_apply(plan.handle, _ptr(x), _ptr(y), ctypes.byref(Hc), _stream(stream)))
+
+
+def z2h_lanczos_sizes(plan, max_iter):
+    n = ctypes.c_size_t()
+    _check(lib().z2h_lanczos_sizes(plan.handle, int(max_iter), ctypes.byref(n)))
+    return n.value
+
+
+def z2h_lanczos_ground(plan, v, ws, H, max_iter=300, tol=1e-13, stream=None):
+    """Ground energy by Lanczos from the start vector v (overwritten).
+    Returns (e0, iterations, alpha, beta) with alpha / beta numpy arrays."""
+    import numpy as np
+    Hc = H if isinstance(H, z2h_couplings) else couplings(*H)
+    a = np.zeros(int(max_iter))
+    b = np.zeros(int(max_iter))
+    it = ctypes.c_int32()
+    e0 = ctypes.c_double()
+    _check(lib().z2h_lanczos_ground(plan.handle, _ptr(v), _ptr(ws), ws.numel() * ws.element_size(),
+                                    ctypes.byref(Hc), int(max_iter), float(tol), a.ctypes.data_as(_P),
+                                    b.ctypes.data_as(_P), ctypes.byref(it), ctypes.byref(e0), _stream(stream)))
+    return e0.value, it.value, a[:it.value].copy(), b[:it.value].copy()
+
+
+def z2h_exact_sizes(plan, krylov_dim):
+    n = ctypes.c_size_t()
+    _check(lib().z2h_exact_sizes(plan.handle, int(krylov_dim), ctypes.byref(n)))
+    return n.value
+
+
+def z2h_exact_evolve(plan, state, ws, sched, krylov_dim=16, stream=None):
+    """Stepwise exact evolution of state (in place); returns the Krylov
+    truncation error estimate summed over steps."""
+    err = ctypes.c_double()
+    _check(lib().z2h_exact_evolve(plan.handle, _ptr(state), _ptr(ws), ws.numel() * ws.element_size(),
+                                  ctypes.byref(sched), int(krylov_dim), ctypes.byref(err), _stream(stream)))
+    return err.value
+
+
+def z2h_tridiag_lowest(alpha, beta):
+    import numpy as np
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    out = ctypes.c_double()
+    _check(lib().z2h_tridiag_lowest(len(a), a.ctypes.data_as(_P), b.ctypes.data_as(_P) if len(b) else None,
+                                    ctypes.byref(out)))
+    return out.value
+
+
+def z2h_tridiag_expv(alpha, beta, tau):
+    import numpy as np
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    re = np.zeros(len(a))
+    im = np.zeros(len(a))
+    _check(lib().z2h_tridiag_expv(len(a), a.ctypes.data_as(_P), b.ctypes.data_as(_P) if len(b) else None,
+                                  float(tau), re.ctypes.data_as(_P), im.ctypes.data_as(_P)))
+    return re + 1j * im
 
 
 class Batch:

@@ -325,3 +325,64 @@ def test_path_sample_count_and_validation():
     assert L.z2h_path_evolve(plan.handle, ctypes.c_void_p(4096), ctypes.c_void_p(8192), 1 << 30,
                              ctypes.byref(p), None, 0, None, 0, ctypes.c_void_p(4096), 2,
                              ctypes.byref(ns), None) == z2h.Z2H_ERR_WORKSPACE
+
+
+# ------------------------------------------------------------------ exact solvers (host parts)
+
+def _tridiag(m, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(size=m) * 3.0, rng.uniform(0.05, 2.0, size=m - 1)
+
+
+@pytest.mark.parametrize("m", [1, 2, 7, 40, 300])
+def test_tridiag_lowest_against_eigvalsh(m):
+    """Sturm bisection of the Lanczos matrix: the lowest eigenvalue equals
+    numpy's dense symmetric eigensolver on the same tridiagonal matrix."""
+    a, b = _tridiag(m, m)
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    ref = np.linalg.eigvalsh(T)[0]
+    got = z2h.z2h_tridiag_lowest(a, b)
+    assert abs(got - ref) <= 1e-12 * max(1.0, abs(ref)), (got, ref)
+
+
+def test_tridiag_lowest_degenerate_cases():
+    """A split matrix (beta = 0) and a multiple eigenvalue."""
+    a = np.array([3.0, -1.0, 2.0, -1.0])
+    b = np.array([0.0, 0.0, 0.0])
+    assert z2h.z2h_tridiag_lowest(a, b) == pytest.approx(-1.0, abs=1e-14)
+    a, b = np.array([2.0, 2.0]), np.array([0.0])
+    assert z2h.z2h_tridiag_lowest(a, b) == pytest.approx(2.0, abs=1e-14)
+
+
+@pytest.mark.parametrize("m,tau", [(1, 0.3), (2, 0.7), (12, 0.02), (32, 0.5), (32, 3.0)])
+def test_tridiag_expv_against_expm(m, tau):
+    """exp(-i tau T) e_1 of the Krylov step equals scipy's dense expm."""
+    import scipy.linalg as sla
+    a, b = _tridiag(m, 100 + m)
+    T = np.diag(a) + np.diag(b, 1) + np.diag(b, -1)
+    ref = sla.expm(-1j * tau * T)[:, 0]
+    got = z2h.z2h_tridiag_expv(a, b, tau)
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_exact_solver_sizes_and_argument_checks():
+    """Workspace sizes (state-sized vectors plus coefficient records) and the
+    rejections that happen before any device work."""
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C128)
+    state = 16 << 18
+    w_l = z2h.z2h_lanczos_sizes(plan, 100)
+    assert 2 * state <= w_l < 2 * state + 64 * 1024
+    w_e = z2h.z2h_exact_sizes(plan, 12)
+    assert 13 * state <= w_e < 13 * state + 64 * 1024
+    for bad in (0, 100001):
+        with pytest.raises(z2h.Z2HError):
+            z2h.z2h_lanczos_sizes(plan, bad)
+    for bad in (0, 33):
+        with pytest.raises(z2h.Z2HError):
+            z2h.z2h_exact_sizes(plan, bad)
+    with pytest.raises(z2h.Z2HError):
+        z2h.lib()  # library loads; the call below fails on the NULL buffers
+        code = z2h.lib().z2h_hamiltonian_apply(plan.handle, None, None, ctypes.byref(z2h.couplings()), None)
+        z2h._check(code)
+    with pytest.raises(z2h.Z2HError):
+        z2h._check(z2h.lib().z2h_tridiag_expv(33, None, None, 0.1, None, None))

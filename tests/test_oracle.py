@@ -302,6 +302,57 @@ def test_trotter_error_is_second_order_in_dt():
     assert 3.8 < errs[1] / errs[2] < 4.2
 
 
+def test_hamiltonian_rows_equal_sparse_matrix():
+    """Row-by-row H x (used at sizes the sparse matrix cannot reach) equals
+    the sparse H of the same couplings on every row."""
+    for Lx, Ly in ((2, 2), (2, 3)):
+        n = 2 * Lx * Ly
+        x = _rand_state(n, 9)
+        c = (0.7, 1.1, 0.3, -0.45)
+        ref = ed.hamiltonian(Lx, Ly, c) @ x
+        got = ed.hamiltonian_rows(Lx, Ly, c, np.arange(1 << n), lambda i: x[i])
+        assert np.abs(got - ref).max() < 1e-13
+
+
+def test_sparse_exact_stepwise_equals_dense():
+    """The sparse exact evolution (expm_multiply) and the dense one (expm)
+    are two algorithms for the same product of exponentials."""
+    for Lx, Ly, M, dt in ((2, 2, 7, 0.3), (2, 2, 3, 1.1)):
+        psi0 = _rand_state(2 * Lx * Ly, 5)
+        c0, c1 = (1.0, 0.8, 0.1, 0.0), (0.6, 1.0, 0.5, 0.3)
+        a = ed.exact_stepwise(Lx, Ly, psi0, c0, c1, M, dt, sampling=1)
+        b = ed.exact_stepwise_sparse(Lx, Ly, psi0, c0, c1, M, dt, sampling=1)
+        assert np.abs(a - b).max() < 1e-12
+
+
+def test_sparse_exact_stepwise_product_state():
+    """JA = JB = 0 from |0...0> at 3x3, with separate schedule values for the
+    x field (sX) and the z field (sZ): every link evolves by
+    exp(-i dt (-hx X - hz Z)) per step, amplitudes alpha^(n-w) beta^w."""
+    Lx, Ly, n, M, dt = 3, 3, 18, 6, 0.3
+    c0, c1 = (0.0, 0.0, 0.2, 0.5), (0.0, 0.0, 0.9, -0.1)
+    rng = np.random.default_rng(2)
+    sZ, sX = rng.uniform(0, 1, M), rng.uniform(0, 1, M)
+    psi0 = oracle.state(n)
+    psi0[0] = 1
+    psi = ed.exact_stepwise_sparse(Lx, Ly, psi0, c0, c1, M, dt, sZ=sZ, sX=sX)
+    u = np.array([1, 0], complex)
+    for k in range(M):
+        hx = (1 - sX[k]) * c0[2] + sX[k] * c1[2]
+        hz = (1 - sZ[k]) * c0[3] + sZ[k] * c1[3]
+        u = sla.expm(1j * dt * (hx * SX + hz * SZ)) @ u
+    w = np.array([bin(i).count("1") for i in range(1 << n)])
+    assert np.abs(psi - u[0] ** (n - w) * u[1] ** w).max() < 1e-12
+
+
+def test_sparse_exact_stepwise_zero_field_phase():
+    """Zero field at 3x3: psi_1 only gains exp(+i (JA Ns + JB Np) T)."""
+    JA, JB, M, dt = 0.5, 0.9, 4, 0.37
+    psi0 = oracle.init_psi1(3, 3)
+    psi = ed.exact_stepwise_sparse(3, 3, psi0, (JA, JB, 0, 0), (JA, JB, 0, 0), M, dt)
+    assert np.abs(psi - np.exp(1j * (JA + JB) * 9 * M * dt) * psi0).max() < 1e-12
+
+
 def test_norm_conserved():
     psi = oracle.init_psi1(3, 3)
     oracle.evolve(3, 3, psi, (1, 1, 0, 0), (1, 1, 0.3, 0.3), 20, 0.1)
