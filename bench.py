@@ -41,12 +41,19 @@ HBM_PEAK_GBS = 8000.0     # MI355X HBM3E, GB/s
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_scan_3x3_c64.json")
 # schedules chosen by the autotuner on an MI355X (lines: n c128 batch-class schedule)
 SHIPPED_TABLE = os.path.join(ROOT, "paper_2108_13410_amd", "tuned_mi355x.txt")
-KERNEL_SRC = os.path.join(ROOT, "paper_2108_13410_amd", "csrc", "z2h_kernels.hip")
+# sources the scan's pass kernels are compiled from (the traffic record is
+# keyed by their hash)
+EXACT_4X4_SPLIT = "split=12:4:12:0/10:4:13:3/10:4:13:3"
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2108_13410_amd", "csrc", f)
+               for f in ("z2h_kernels.hip", "z2h_tile.h", "z2h_kernels.h", "z2h_internal.h")]
 
 
 def kernel_hash():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for path in KERNEL_SRCS:
+        with open(path, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def ensure_built():
@@ -330,6 +337,69 @@ def mixed_leg(z2h, torch):
             "amp_updates_per_s": amp / el, "launch": "HIP graph (resident small lattices on a side stream)"}
 
 
+def exact_leg(z2h, torch):
+    """Exact solvers on the GPU.
+    - 4x4 torus, complex128 (2^32 amplitudes; start vector plus two Lanczos
+      vectors = 192 GiB): Lanczos ground energy of H at the paper's point
+      P(g = 0.5, lambda = 0), J = 1/2, from |+...+>, and one H x.
+      Algorithmic bytes: an H x is 2 (2K - 1) + 1 state passes (read + write
+      per pass, x read again by the last); a fused Lanczos iteration is 4K
+      (the last pass reads y, u and the previous vector and writes the next).
+    - 3x3, complex128: the stepwise exact evolution of a 200-step ramp with a
+      16-dimensional Krylov basis per step."""
+    torch.cuda.empty_cache()
+    out = {}
+    c = (0.5, 0.5, 0.5, 0.0)
+    # H x makes 2K - 1 passes over K transform groups: the planner's
+    # three-group split (12 + 10 + 10 links), not a Trotter-tuned schedule
+    # with more groups
+    plan = z2h.z2h_plan_create_config(4, 4, z2h.Z2H_C128, EXACT_4X4_SPLIT)
+    K = len(z2h.z2h_plan_describe(plan)["groups"])
+    V = 16 << 32
+    v = z2h.alloc_state(plan)
+    ws = z2h.alloc_bytes(z2h.z2h_lanczos_sizes(plan, 64))
+    y = ws[:V].view(torch.complex128)
+    z2h.z2h_state_init(plan, v, z2h.Z2H_INIT_PLUS)
+    z2h.z2h_hamiltonian_apply(plan, v, y, c)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(2):
+        z2h.z2h_hamiltonian_apply(plan, v, y, c)
+    torch.cuda.synchronize()
+    t_hx = (time.perf_counter() - t0) / 2
+    del y
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    e0, it, _, beta = z2h.z2h_lanczos_ground(plan, v, ws, c, max_iter=64, tol=1e-11)
+    t_l = time.perf_counter() - t0
+    hx_bytes = (2 * (2 * K - 1) + 1) * V
+    it_bytes = 4 * K * V
+    out["lanczos_4x4"] = {
+        "couplings": c, "precision": "complex128", "groups": K, "E0": e0, "iterations": it,
+        "last_beta": float(beta[-1]) if len(beta) else None,
+        "seconds": t_l, "ms_per_iteration": t_l / it * 1e3,
+        "iteration_GBps_algorithmic": it_bytes / (t_l / it) / 1e9,
+        "hx_ms": t_hx * 1e3, "hx_GBps_algorithmic": hx_bytes / t_hx / 1e9,
+        "hx_frac_of_hbm_peak": hx_bytes / t_hx / 1e9 / HBM_PEAK_GBS,
+    }
+    del v, ws
+    torch.cuda.empty_cache()
+    plan3 = z2h.z2h_plan_create(3, 3, z2h.Z2H_C128)
+    psi = z2h.alloc_state(plan3)
+    ws3 = z2h.alloc_bytes(z2h.z2h_exact_sizes(plan3, 16))
+    M = 200
+    sched = z2h.schedule((0.5, 0.5, 0.0, 0.0), (0.5, 0.5, 0.3, 0.2), M, 0.02)
+    z2h.z2h_state_init(plan3, psi, z2h.Z2H_INIT_PSI1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    err = z2h.z2h_exact_evolve(plan3, psi, ws3, sched, krylov_dim=16)
+    torch.cuda.synchronize()
+    t_e = time.perf_counter() - t0
+    out["exact_evolve_3x3"] = {"steps": M, "krylov_dim": 16, "ms_per_step": t_e / M * 1e3,
+                               "krylov_error_estimate": err}
+    return out
+
+
 def cpu_baseline(seconds_hint):
     """The FP64 oracle (test infrastructure, untuned) on one scan point."""
     import numpy as np  # noqa: F401
@@ -363,6 +433,7 @@ def main():
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-protocol", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint and mixed-batch legs")
+    ap.add_argument("--no-exact", action="store_true", help="skip the exact-solver leg (Lanczos, Krylov)")
     ap.add_argument("--tune-cache", default=None,
                     help="schedule cache: loaded if it has the needed entries, else written by the autotuner "
                          "(default: the table shipped with the package, never written)")
@@ -499,6 +570,11 @@ def main():
         line["mixed_batch"] = mixed_leg(z2h, torch)
         print(f"adjoint: {line['adjoint']['backward_ms']:.1f} ms, mixed batch: {line['mixed_batch']['ms_per_run']:.1f} ms",
               file=sys.stderr, flush=True)
+    if not args.no_exact:
+        line["exact"] = exact_leg(z2h, torch)
+        lz = line["exact"]["lanczos_4x4"]
+        print(f"exact: 4x4 E0 = {lz['E0']:.10f} ({lz['iterations']} it, {lz['ms_per_iteration']:.0f} ms/it), "
+              f"H x {lz['hx_GBps_algorithmic']:.0f} GB/s", file=sys.stderr, flush=True)
     if not args.no_protocol:
         line["paper_protocol"] = paper_protocol(z2h, torch)
         print(f"paper protocol: {line['paper_protocol']['trotter_steps_per_s']:.0f} steps/s", file=sys.stderr, flush=True)

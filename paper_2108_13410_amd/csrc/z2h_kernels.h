@@ -126,27 +126,43 @@ hipError_t launch_reduce_parts(const JobDev *jobs, const JobDev &inline_job, int
 
 // ---- exact solvers (Hamiltonian application, Lanczos, Krylov exponential)
 
+// Lanczos coefficients of iteration k (device): v_k = sigma_k u_k with u_k
+// the stored vector; beta_k = |u_k| (|u_0| for the start vector).
+struct LanczosCoef {
+    double alpha, beta, sigma, pad;
+};
+
 // One tile pass of y = H x.  The passes visit groups 0, 1, .., K-1, .., 1, 0;
 // the top group multiplies by the Hadamard-basis diagonal between its
 // forward and backward transform, and the last pass adds the computational-
 // basis diagonal times x.
+//
+// Lanczos form (lz = 1, K > 1): the first pass also reduces sum D_Z |x|^2 and
+// the top pass 2^-n sum D_X |W x|^2, so <x, H x> is known when the last pass
+// runs; that pass then writes the next Lanczos vector
+//   w = sigma_k (H x - alpha_k x) - beta_k sigma_{k-1} p,
+//   alpha_k = sigma_k^2 (sum of both partial sets),
+// to w instead of H x to dst, with per-workgroup |w|^2 partials.
 struct HamArgs {
     const void *src;           // read by this pass
     void *dst;                 // written by this pass (may equal src)
     const void *x;             // final pass: the vector H acts on; else null
     double *part;              // final pass: per-workgroup Re<x, Hx> partials, or null
+    double *part_z;            // first pass: per-workgroup sum D_Z |x|^2, or null
+    double *part_x;            // top pass: per-workgroup 2^-n sum D_X |W x|^2, or null
+    const void *p;             // Lanczos final pass: previous vector (read if use_prev)
+    void *w;                   // Lanczos final pass: output (may equal p)
+    double *part_w;            // Lanczos final pass: |w|^2 partials
+    const double *apart_z, *apart_x;
+    const LanczosCoef *coef;
+    int32_t napart_z, napart_x;
+    int32_t k, use_prev, lz;
     GroupGeom geom;
     LatticeDev lat;
     int32_t top;               // 1: transform, X-basis diagonal, transform back
     int32_t final_pass;        // 1: add D_Z x after the transform
     double JA, JB, hx, hz;
     double xscale;             // 2^-n: the two unnormalised transforms
-};
-
-// Lanczos coefficients of iteration k (device): v_k = sigma_k u_k with u_k
-// the stored vector; beta_k = |u_k| (|u_0| for the start vector).
-struct LanczosCoef {
-    double alpha, beta, sigma, pad;
 };
 
 // w = sigma_k (y - alpha_k u) - beta_k sigma_{k-1} p (elementwise; w may equal p)
@@ -165,11 +181,11 @@ struct VecArgs {
     double *part;              // per-block |w|^2 (or |u|^2) partials
 };
 
-// One block: coef[k].alpha from the Hamiltonian partials and coef[k+1]
+// One block: coef[k].alpha from the Hamiltonian partials (one or two sets) and coef[k+1]
 // (beta, sigma) from the |w|^2 partials; mode 1: coef[0] from |u_0|^2.
 struct ScalarArgs {
-    const double *apart, *wpart;
-    int32_t napart, nwpart;
+    const double *apart, *apart2, *wpart;   // alpha: sum of apart and apart2 (may be null)
+    int32_t napart, napart2, nwpart;
     int32_t k, mode;
     LanczosCoef *coef;
 };

@@ -19,6 +19,7 @@ using namespace z2h::rt;
 namespace {
 
 constexpr int kCheckEvery = 8;   // Lanczos iterations between convergence checks
+static_assert(kHamWorkersMax <= kVecBlocks, "the |w|^2 partials of a fused pass fit the vector-kernel slots");
 
 size_t state_bytes(const Plan &P) { return P.esize << P.n; }
 
@@ -65,7 +66,7 @@ z2h_status ham_passes(const Plan &P, const void *x, void *y, const z2h_couplings
 // Scratch of the Lanczos recurrence inside a workspace.
 struct LanczosWs {
     void *vec[kKrylovMax + 1];   // state-sized buffers
-    double *apart, *wpart;
+    double *apart, *apart_x, *wpart;
     LanczosCoef *coef;
 };
 
@@ -75,6 +76,7 @@ size_t lanczos_carve(const Plan &P, int nvec, int ncoef, char *base, LanczosWs *
     memset(&tmp, 0, sizeof tmp);
     for (int i = 0; i < nvec; ++i) tmp.vec[i] = c.take(state_bytes(P));
     tmp.apart = (double *)c.take(sizeof(double) * kHamWorkersMax);
+    tmp.apart_x = (double *)c.take(sizeof(double) * kHamWorkersMax);
     tmp.wpart = (double *)c.take(sizeof(double) * kVecBlocks);
     tmp.coef = (LanczosCoef *)c.take(sizeof(LanczosCoef) * (size_t)ncoef);
     if (L) *L = tmp;
@@ -103,10 +105,70 @@ z2h_status norm_start(const Plan &P, const void *u, const LanczosWs &L, hipStrea
     return Z2H_OK;
 }
 
-// One Lanczos iteration k: y = H u; w = sigma_k (y - alpha_k u) - beta_k
-// sigma_{k-1} p written to w; coef[k].alpha and coef[k+1] (beta, sigma).
+z2h_status launch_scalar_k(const LanczosWs &L, int k, int napart, int napart2, int nwpart, hipStream_t s) {
+    ScalarArgs sa;
+    memset(&sa, 0, sizeof sa);
+    sa.apart = L.apart;
+    sa.napart = napart;
+    sa.apart2 = napart2 ? L.apart_x : nullptr;
+    sa.napart2 = napart2;
+    sa.wpart = L.wpart;
+    sa.nwpart = nwpart;
+    sa.k = k;
+    sa.mode = 0;
+    sa.coef = L.coef;
+    hipError_t e = launch_scalar(sa, s);
+    if (e != hipSuccess) return fail(Z2H_ERR_HIP, "Lanczos coefficient kernel failed: %s", hipGetErrorString(e));
+    return Z2H_OK;
+}
+
+// One Lanczos iteration k: w = sigma_k (H u - alpha_k u) - beta_k sigma_{k-1} p
+// written to w; coef[k].alpha and coef[k+1] (beta, sigma).  With several
+// groups the update is fused into the Hamiltonian's passes (alpha from the
+// first and the top pass, w written by the last one); a one-group plan
+// forms y = H u and updates in an elementwise kernel.
 z2h_status lanczos_iter(const Plan &P, const z2h_couplings &H, int k, const void *u, const void *p, void *w,
                         void *y, const LanczosWs &L, hipStream_t s) {
+    if (P.K > 1) {
+        HamArgs a;
+        memset(&a, 0, sizeof a);
+        a.lat = P.lat;
+        a.JA = H.JA;
+        a.JB = H.JB;
+        a.hx = H.hx;
+        a.hz = H.hz;
+        a.xscale = std::ldexp(1.0, -P.n);
+        const int K = P.K, npass = 2 * K - 1;
+        const int nz = ham_workers(P.geom[0]), nx = ham_workers(P.geom[K - 1]);
+        for (int i = 0; i < npass; ++i) {
+            const int gi = i < K ? i : 2 * K - 2 - i;
+            a.geom = P.geom[gi];
+            a.src = i == 0 ? u : y;
+            a.dst = y;
+            a.top = gi == K - 1;
+            a.final_pass = i == npass - 1;
+            a.part_z = i == 0 ? L.apart : nullptr;
+            a.part_x = gi == K - 1 ? L.apart_x : nullptr;
+            if (a.final_pass) {
+                a.x = u;
+                a.lz = 1;
+                a.p = k > 0 ? p : nullptr;
+                a.use_prev = k > 0;
+                a.w = w;
+                a.part_w = L.wpart;
+                a.apart_z = L.apart;
+                a.napart_z = nz;
+                a.apart_x = L.apart_x;
+                a.napart_x = nx;
+                a.coef = L.coef;
+                a.k = k;
+            }
+            hipError_t e = launch_ham(P.c128, a.geom.R, a, (unsigned)ham_workers(a.geom),
+                                      obs_lds_bytes(P, a.geom, a.geom.R), s);
+            if (e != hipSuccess) return fail(Z2H_ERR_HIP, "Lanczos pass failed: %s", hipGetErrorString(e));
+        }
+        return launch_scalar_k(L, k, nz, nx, nz, s);
+    }
     int napart = 0;
     z2h_status st = ham_passes(P, u, y, H, L.apart, &napart, s);
     if (st) return st;
@@ -126,20 +188,8 @@ z2h_status lanczos_iter(const Plan &P, const z2h_couplings &H, int k, const void
     v.part = L.wpart;
     const unsigned nb = vec_blocks(P);
     hipError_t e = launch_vec(P.c128, v, nb, s);
-    if (e == hipSuccess) {
-        ScalarArgs sa;
-        memset(&sa, 0, sizeof sa);
-        sa.apart = L.apart;
-        sa.napart = napart;
-        sa.wpart = L.wpart;
-        sa.nwpart = (int)nb;
-        sa.k = k;
-        sa.mode = 0;
-        sa.coef = L.coef;
-        e = launch_scalar(sa, s);
-    }
     if (e != hipSuccess) return fail(Z2H_ERR_HIP, "Lanczos update failed: %s", hipGetErrorString(e));
-    return Z2H_OK;
+    return launch_scalar_k(L, k, napart, 0, (int)nb, s);
 }
 
 // Both pointers valid and the byte ranges [a, a + na) and [b, b + nb) disjoint.

@@ -29,29 +29,56 @@ __device__ __forceinline__ double diag_value(int nst, int n, uint32_t s, int w, 
     return -(J * (double)(nst - 2 * popc(s)) + h * (double)(n - 2 * w));
 }
 
-// v *= scale * D_X for the register elements of layout L (Hadamard basis).
+// v *= scale * D_X for the register elements of layout L (Hadamard basis);
+// accx (if not null) accumulates scale * sum D_X |v|^2 of the values before
+// (a pointer: the accumulator then lives in a scratch slot rather than in
+// one of the registers the two prefetched tiles need).
 template <typename Real, int R>
 __device__ __forceinline__ void mul_diag_x(Cx<Real> (&v)[1 << R], const LayCtx<R> &L, const LatticeDev &lat,
-                                           double J, double h, double scale) {
+                                           double J, double h, double scale, double *accx) {
     uint32_t s = L.s0x;
 #pragma unroll
     for (int idx = 0; idx < (1 << R); ++idx) {
         const int q = idx ^ (idx >> 1);
         if (idx) s ^= L.lx[__builtin_ctz(idx)];
-        const Real d = (Real)(scale * diag_value(lat.nst, lat.n, s, L.w0 + __builtin_popcount(q), J, h));
+        const double dd = scale * diag_value(lat.nst, lat.n, s, L.w0 + __builtin_popcount(q), J, h);
+        if (accx) *accx += dd * ((double)v[q].x * (double)v[q].x + (double)v[q].y * (double)v[q].y);
+        const Real d = (Real)dd;
         v[q].x *= d;
         v[q].y *= d;
     }
 }
 
+// sum D_Z |v|^2 over the register elements of layout L (computational basis).
+template <typename Real, int R>
+__device__ __forceinline__ double diag_norm_z(const Cx<Real> (&v)[1 << R], const LayCtx<R> &L,
+                                              const LatticeDev &lat, double J, double h) {
+    uint32_t s = L.s0z;
+    double acc = 0.0;
+#pragma unroll
+    for (int idx = 0; idx < (1 << R); ++idx) {
+        const int q = idx ^ (idx >> 1);
+        if (idx) s ^= L.lz[__builtin_ctz(idx)];
+        acc += diag_value(lat.nst, lat.n, s, L.w0 + __builtin_popcount(q), J, h) *
+               ((double)v[q].x * (double)v[q].x + (double)v[q].y * (double)v[q].y);
+    }
+    return acc;
+}
+
+// Elements of x at the register positions of layout L, eight Gray-code steps
+// at a time (each chunk covers eight register elements), so that at most
+// eight extra elements of each operand are live beside the tile.
+template <int R>
+struct Chunk {
+    static constexpr int C = (1 << R) < 8 ? (1 << R) : 8;
+};
+
 // v += D_Z x for the register elements of layout L (computational basis),
-// accumulating Re(conj(x) v) of the result.  x is read in chunks of eight
-// Gray-code steps (each chunk covers eight register elements) so that at
-// most eight extra elements are live beside the tile.
+// accumulating Re(conj(x) v) of the result.
 template <typename Real, int R>
 __device__ __forceinline__ void add_diag_z(Cx<Real> (&v)[1 << R], const Cx<Real> *x, const LayCtx<R> &L,
                                            const LatticeDev &lat, double J, double h, double &acc) {
-    constexpr int C = (1 << R) < 8 ? (1 << R) : 8;
+    constexpr int C = Chunk<R>::C;
     uint32_t s = L.s0z;
     const Cx<Real> *b = x + L.i0;
 #pragma unroll
@@ -75,7 +102,45 @@ __device__ __forceinline__ void add_diag_z(Cx<Real> (&v)[1 << R], const Cx<Real>
     }
 }
 
+// Lanczos form of the last pass: with v = (2^-n W D_X W u) at the register
+// positions of layout L, write w = sig (v + D_Z u - alpha u) - cp p and
+// accumulate |w|^2.
 template <typename Real, int R>
+__device__ __forceinline__ void lanczos_out(const Cx<Real> (&v)[1 << R], const Cx<Real> *u, const Cx<Real> *p,
+                                            Cx<Real> *w, const LayCtx<R> &L, const LatticeDev &lat, double J,
+                                            double h, double sig, double alpha, double cp, bool use_prev,
+                                            double &acc) {
+    constexpr int C = Chunk<R>::C;
+    uint32_t s = L.s0z;
+    const Cx<Real> *bu = u + L.i0;
+    const Cx<Real> *bp = p + L.i0;
+    Cx<Real> *bw = w + L.i0;
+    const Real rs = (Real)sig, rc = (Real)cp;
+#pragma unroll
+    for (int c0 = 0; c0 < (1 << R); c0 += C) {
+        Cx<Real> uv[C], pv[C];
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const int q = (c0 + i) ^ ((c0 + i) >> 1);
+            uv[i] = bu[(uint64_t)q << L.gs];
+            pv[i] = use_prev ? bp[(uint64_t)q << L.gs] : Cx<Real>{(Real)0, (Real)0};
+        }
+#pragma unroll
+        for (int i = 0; i < C; ++i) {
+            const int idx = c0 + i, q = idx ^ (idx >> 1);
+            if (idx) s ^= L.lz[__builtin_ctz(idx)];
+            const Real d = (Real)(diag_value(lat.nst, lat.n, s, L.w0 + __builtin_popcount(q), J, h) - alpha);
+            Cx<Real> r{rs * (v[q].x + d * uv[i].x) - rc * pv[i].x, rs * (v[q].y + d * uv[i].y) - rc * pv[i].y};
+            bw[(uint64_t)q << L.gs] = r;
+            acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+}
+
+// PF: the next tile's elements are loaded while the current one is
+// transformed (two register tiles; used where they fit without spilling).
+template <typename Real, int R, bool PF>
 __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const GroupGeom &g = a.geom;
@@ -87,13 +152,49 @@ __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
     const Cx<Real> *src = reinterpret_cast<const Cx<Real> *>(a.src);
     Cx<Real> *dst = reinterpret_cast<Cx<Real> *>(a.dst);
     const Cx<Real> *x = reinterpret_cast<const Cx<Real> *>(a.x);
-    double acc = 0.0;
+    const bool lz = a.lz && a.final_pass;
+    double acc = 0.0, accz = 0.0, accx = 0.0;
 
-    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+    // Lanczos coefficients of this iteration (every block sums the partials
+    // of the first and the top pass itself)
+    double sig = 0.0, alpha = 0.0, cp = 0.0;
+    if (lz) {
+        const LanczosCoef ck = a.coef[a.k];
+        sig = ck.sigma;
+        double sm = 0.0;
+        for (int j = (int)t; j < a.napart_z; j += (int)blockDim.x) sm += a.apart_z[j];
+        for (int j = (int)t; j < a.napart_x; j += (int)blockDim.x) sm += a.apart_x[j];
+        alpha = sig * sig * block_sum(sm, red);
+        cp = a.use_prev ? ck.beta * a.coef[a.k - 1].sigma : 0.0;
+    }
+
+    const bool syn0 = a.final_pass || a.part_z;
+    uint64_t tile = blockIdx.x;
+    Cx<Real> vn[PF ? (1 << R) : 1];
+    LayCtx<R> Ln;
+    if constexpr (PF) {
+        if (tile < tiles) {
+            lay_ctx<R>(Ln, g, a.lat, tile, g.p[0], t, syn0);
+            load_tile<Real, R>(vn, src, Ln);
+        }
+    }
+    for (; tile < tiles; tile += gridDim.x) {
         Cx<Real> v[1 << R];
         LayCtx<R> L0;
-        lay_ctx<R>(L0, g, a.lat, tile, g.p[0], t, a.final_pass != 0);
-        load_tile<Real, R>(v, src, L0);
+        if constexpr (PF) {
+            L0 = Ln;
+#pragma unroll
+            for (int q = 0; q < (1 << R); ++q) v[q] = vn[q];
+            const uint64_t nt = tile + gridDim.x;
+            if (nt < tiles) {
+                lay_ctx<R>(Ln, g, a.lat, nt, g.p[0], t, syn0);
+                load_tile<Real, R>(vn, src, Ln);
+            }
+        } else {
+            lay_ctx<R>(L0, g, a.lat, tile, g.p[0], t, syn0);
+            load_tile<Real, R>(v, src, L0);
+        }
+        if (a.part_z) accz += diag_norm_z<Real, R>(v, L0, a.lat, a.JB, a.hz);
         int cur = 0;
         for (int j = 0; j < g.nlay; ++j) {
             if (j > 0) exchange<Real, R>(v, lds, g.p[j - 1], g.p[j], t);
@@ -103,7 +204,7 @@ __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
         if (a.top) {
             LayCtx<R> Lm;
             lay_ctx<R>(Lm, g, a.lat, tile, g.p[cur], t, true);
-            mul_diag_x<Real, R>(v, Lm, a.lat, a.JA, a.hx, a.xscale);
+            mul_diag_x<Real, R>(v, Lm, a.lat, a.JA, a.hx, a.xscale, a.part_x ? &accx : nullptr);
             for (int j = g.nlay - 1; j >= 0; --j) {
                 if (j != cur) {
                     exchange<Real, R>(v, lds, g.p[cur], g.p[j], t);
@@ -113,12 +214,29 @@ __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
             }
         }
         if (cur != 0) exchange<Real, R>(v, lds, g.p[cur], g.p[0], t);
+        if (lz) {
+            lanczos_out<Real, R>(v, x, reinterpret_cast<const Cx<Real> *>(a.p), reinterpret_cast<Cx<Real> *>(a.w),
+                                 L0, a.lat, a.JB, a.hz, sig, alpha, cp, a.use_prev != 0, acc);
+            continue;
+        }
         if (a.final_pass) add_diag_z<Real, R>(v, x, L0, a.lat, a.JB, a.hz, acc);
         store_tile<Real, R>(v, dst, L0);
     }
     if (a.part) {
         const double s = block_sum(acc, red);
         if (t == 0) a.part[blockIdx.x] = s;
+    }
+    if (a.part_w) {
+        const double s = block_sum(acc, red);
+        if (t == 0) a.part_w[blockIdx.x] = s;
+    }
+    if (a.part_z) {
+        const double s = block_sum(accz, red);
+        if (t == 0) a.part_z[blockIdx.x] = s;
+    }
+    if (a.part_x) {
+        const double s = block_sum(accx, red);
+        if (t == 0) a.part_x[blockIdx.x] = s;
     }
 }
 
@@ -176,7 +294,7 @@ __global__ void __launch_bounds__(256) scalar_kernel(ScalarArgs a) {
         return;
     }
     const double sig = a.coef[a.k].sigma;
-    const double alpha = sig * sig * sum_parts(a.apart, a.napart, red);
+    const double alpha = sig * sig * (sum_parts(a.apart, a.napart, red) + sum_parts(a.apart2, a.napart2, red));
     const double nn = sum_parts(a.wpart, a.nwpart, red);
     if (threadIdx.x == 0) {
         a.coef[a.k].alpha = alpha;
@@ -214,14 +332,23 @@ static hipError_t allow_lds(const void *fn, size_t lds) {
     return e;
 }
 
+template <typename Real, int R, bool PF>
+static hipError_t do_ham_pf(const HamArgs &a, unsigned workers, size_t lds, hipStream_t s) {
+    const void *fn = reinterpret_cast<const void *>(&ham_kernel<Real, R, PF>);
+    hipError_t e = allow_lds(fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((ham_kernel<Real, R, PF>), dim3(workers), dim3(1u << (a.geom.m - R)), lds, s, a);
+    return hipGetLastError();
+}
+
+// Two register tiles fit without spilling up to 256 bytes of elements per
+// thread, except complex64 at R = 5, whose 32 elements per tile need more
+// index and syndrome registers than the other shapes.
 template <typename Real, int R>
 static hipError_t do_ham(const HamArgs &a, unsigned workers, size_t lds, hipStream_t s) {
     if (a.geom.m - R < 6 || a.geom.m - R > 9) return hipErrorInvalidConfiguration;  // launch bounds
-    const void *fn = reinterpret_cast<const void *>(&ham_kernel<Real, R>);
-    hipError_t e = allow_lds(fn, lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((ham_kernel<Real, R>), dim3(workers), dim3(1u << (a.geom.m - R)), lds, s, a);
-    return hipGetLastError();
+    constexpr bool pf = (2 * sizeof(Real) << R) <= 256 && !(sizeof(Real) == 4 && R == 5);
+    return do_ham_pf<Real, R, pf>(a, workers, lds, s);
 }
 
 hipError_t launch_ham(bool c128, int R, const HamArgs &a, unsigned workers, size_t lds, hipStream_t s) {

@@ -192,7 +192,7 @@ __device__ __forceinline__ double wave_sum(double x) {
 }
 
 // Deterministic block sum; every thread gets the result.
-__device__ inline double block_sum(double x, double *red) {
+__device__ double block_sum(double x, double *red) {
     x = wave_sum(x);
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nw = (blockDim.x + 63) >> 6;
     __syncthreads();
