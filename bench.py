@@ -400,6 +400,57 @@ def exact_leg(z2h, torch):
     return out
 
 
+def circuit_leg(z2h, torch, with_4x4=False):
+    """The paper's circuit at gate level (Sec. III; n links + 1 ancilla) beside
+    the fused Trotter path, per Trotter step: 3x3 in complex128 gate by gate
+    (522 launches) and in fused LDS passes; optionally 4x4 (33 qubits,
+    complex64, 64 GiB) in fused passes."""
+    out = {}
+    c0, c1, M, dt = (0.5, 0.5, 0.0, 0.0), (0.5, 0.5, 0.3, 0.2), 100, 0.02
+
+    def gate_level(Lx, Ly, dtype, fuse, steps):
+        n = 2 * Lx * Ly
+        psi = torch.zeros(1 << (n + 1), dtype=torch.complex128 if dtype == z2h.Z2H_C128 else torch.complex64,
+                          device="cuda")
+        psi[0] = 1
+        ws = z2h.alloc_bytes(z2h.z2h_gates_ws_bytes(n + 1))
+        z2h.z2h_circuit_evolve(Lx, Ly, dtype, psi, ws, z2h.schedule(c0, c1, M, dt, k_end=1), fuse=fuse)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        z2h.z2h_circuit_evolve(Lx, Ly, dtype, psi, ws, z2h.schedule(c0, c1, M, dt, k_begin=1, k_end=1 + steps),
+                               fuse=fuse)
+        torch.cuda.synchronize()
+        del psi
+        torch.cuda.empty_cache()
+        return (time.perf_counter() - t0) / steps
+
+    def trotter_path(Lx, Ly, dtype, steps):
+        plan = z2h.z2h_plan_create(Lx, Ly, dtype)
+        phi = z2h.alloc_state(plan)
+        z2h.z2h_state_init(plan, phi, z2h.Z2H_INIT_PSI1)
+        ws = z2h.alloc_bytes(z2h.z2h_plan_sizes(plan)["ws_evolve"])
+        z2h.z2h_evolve(plan, phi, ws, z2h.schedule(c0, c1, steps, dt))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        z2h.z2h_evolve(plan, phi, ws, z2h.schedule(c0, c1, steps, dt))
+        torch.cuda.synchronize()
+        del phi
+        torch.cuda.empty_cache()
+        return (time.perf_counter() - t0) / steps
+
+    ng = z2h.z2h_circuit_step(3, 3, c0, c0, dt)[1]
+    a, b, c = gate_level(3, 3, z2h.Z2H_C128, 0, 10), gate_level(3, 3, z2h.Z2H_C128, 1, 20), \
+        trotter_path(3, 3, z2h.Z2H_C128, 200)
+    out["3x3_c128"] = {"gates_per_step": ng, "gate_by_gate_ms_per_step": a * 1e3, "fused_gates_ms_per_step": b * 1e3,
+                       "trotter_path_ms_per_step": c * 1e3, "trotter_path_speedup_over_fused_gates": b / c}
+    if with_4x4:
+        ng4 = z2h.z2h_circuit_step(4, 4, c0, c0, dt)[1]
+        b4, c4 = gate_level(4, 4, z2h.Z2H_C64, 1, 1), trotter_path(4, 4, z2h.Z2H_C64, 3)
+        out["4x4_c64"] = {"gates_per_step": ng4, "fused_gates_ms_per_step": b4 * 1e3,
+                          "trotter_path_ms_per_step": c4 * 1e3, "trotter_path_speedup_over_fused_gates": b4 / c4}
+    return out
+
+
 def cpu_baseline(seconds_hint):
     """The FP64 oracle (test infrastructure, untuned) on one scan point."""
     import numpy as np  # noqa: F401
@@ -434,6 +485,8 @@ def main():
     ap.add_argument("--no-protocol", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint and mixed-batch legs")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact-solver leg (Lanczos, Krylov)")
+    ap.add_argument("--no-circuit", action="store_true", help="skip the gate-level circuit leg")
+    ap.add_argument("--circuit-4x4", action="store_true", help="add the 33-qubit gate-level step (about 10 s)")
     ap.add_argument("--tune-cache", default=None,
                     help="schedule cache: loaded if it has the needed entries, else written by the autotuner "
                          "(default: the table shipped with the package, never written)")
@@ -575,6 +628,11 @@ def main():
         lz = line["exact"]["lanczos_4x4"]
         print(f"exact: 4x4 E0 = {lz['E0']:.10f} ({lz['iterations']} it, {lz['ms_per_iteration']:.0f} ms/it), "
               f"H x {lz['hx_GBps_algorithmic']:.0f} GB/s", file=sys.stderr, flush=True)
+    if not args.no_circuit:
+        line["gate_level"] = circuit_leg(z2h, torch, args.circuit_4x4)
+        g3 = line["gate_level"]["3x3_c128"]
+        print(f"gate level 3x3: {g3['gate_by_gate_ms_per_step']:.2f} / {g3['fused_gates_ms_per_step']:.2f} ms per step "
+              f"(Trotter path {g3['trotter_path_ms_per_step']:.3f})", file=sys.stderr, flush=True)
     if not args.no_protocol:
         line["paper_protocol"] = paper_protocol(z2h, torch)
         print(f"paper protocol: {line['paper_protocol']['trotter_steps_per_s']:.0f} steps/s", file=sys.stderr, flush=True)

@@ -391,6 +391,84 @@ z2h_status z2h_tridiag_lowest(int32_t m, const double *alpha, const double *beta
 z2h_status z2h_tridiag_expv(int32_t m, const double *alpha, const double *beta, double tau, double *out_re,
                             double *out_im);
 
+/* ------------------------------------------------------------------ gate-level circuits */
+
+/*
+ * Gate-level emulation of the paper's circuits (Sec. III; state preparation
+ * Eqs. (ini1), (ini2)) on n + 1 qubits: the n links in library bit order and
+ * one ancilla at bit n.  These run the circuit as written, gate by gate, as
+ * a check of the circuit itself: the Trotter path above applies the same
+ * operator through fused diagonal phases and needs no ancilla.
+ *
+ * Gate kinds (rotation convention R_a(theta) = exp(-i theta sigma^a / 2)):
+ *   Z2H_GATE_H      Hadamard on q0
+ *   Z2H_GATE_RX     R_x(theta) on q0
+ *   Z2H_GATE_RZ     R_z(theta) on q0
+ *   Z2H_GATE_CNOT   control q0, target q1
+ *   Z2H_GATE_PROJ0  projection of q0 on |0> (not renormalised)
+ *   Z2H_GATE_NORM   rescale the state to unit norm (q0 unused)
+ */
+#define Z2H_GATE_H 0
+#define Z2H_GATE_RX 1
+#define Z2H_GATE_RZ 2
+#define Z2H_GATE_CNOT 3
+#define Z2H_GATE_PROJ0 4
+#define Z2H_GATE_NORM 5
+typedef struct {
+    int32_t kind;
+    int32_t q0, q1;
+    int32_t reserved; /* 0 */
+    double theta;
+} z2h_gate;
+
+/*
+ * The gates of one Trotter step of Sec. III for the couplings cx (used by
+ * the x-type terms: JA, hx) and cz (z-type: JB, hz), duration dt, in time
+ * order (the first gate acts first).  order 0 (x-z-x):
+ *   R_x(-hx dt) on every link; the half stabilizer layer; R_z(-2 hz dt) on
+ *   every link; the half stabilizer layer; R_x(-hx dt) on every link.
+ * The half stabilizer layer realises exp(i JB B_p dt/2) per plaquette as
+ * CNOTs from its links to the ancilla, R_z(-JB dt) on the ancilla, the same
+ * CNOTs; then exp(i JA A_v dt/2) per star as Hadamards on its links, the
+ * same CNOT / R_z(-JA dt) / CNOT gadget, Hadamards.  The ancilla starts and
+ * ends in |0>.  order 1 (z-x-z) swaps the field layers (R_z(-hz dt) halves,
+ * R_x(-2 hx dt) in the middle).  At 3x3: 522 gates.
+ * out: host array of cap gates; *count receives the number written (and is
+ * set even when cap is too small, which returns Z2H_ERR_WORKSPACE).  Host only.
+ */
+z2h_status z2h_circuit_step(int32_t Lx, int32_t Ly, const z2h_couplings *cx, const z2h_couplings *cz, double dt,
+                            int32_t order, z2h_gate *out, int32_t cap, int32_t *count);
+
+/* The preparation circuit of Eq. (ini1) (which = Z2H_INIT_PSI1: Hadamards
+ * on every link, then per plaquette CNOTs to the ancilla, projection of the
+ * ancilla on |0>, CNOTs) or Eq. (ini2) (Z2H_INIT_PSI1P: per star Hadamards
+ * on its links, CNOTs, projection, CNOTs, Hadamards), from |0...0>, followed
+ * by one NORM gate.  Host only; out / cap / count as above. */
+z2h_status z2h_circuit_prep(int32_t Lx, int32_t Ly, int32_t which, z2h_gate *out, int32_t cap, int32_t *count);
+
+/*
+ * Apply gates[0..ngates) (host array, time order) to the state of nq qubits
+ * (2^nq complex elements of dtype at d_state, 256-byte aligned; nq in
+ * [2, 34]).  fuse 0: one kernel launch per gate (each a pass over the
+ * state).  fuse 1: consecutive gates whose qubits fit one tile are applied
+ * together in LDS, one pass per group; a tile always holds the four lowest
+ * qubits (coalesced rows) and up to 8 (complex128) or 9 (complex64) others.
+ * NORM gates end a group; NORM leaves a zero state zero.  Results agree
+ * with fuse 0 to rounding.  d_ws: z2h_gates_ws_bytes bytes (norm partials).
+ * Errors: Z2H_ERR_INVALID (qubit out of range, q0 == q1 for CNOT, unknown
+ * kind, nq out of range, bad buffers), Z2H_ERR_WORKSPACE.
+ */
+size_t z2h_gates_ws_bytes(int32_t nq);
+z2h_status z2h_gates_run(int32_t nq, z2h_dtype dtype, void *d_state, void *d_ws, size_t ws_bytes,
+                         const z2h_gate *gates, int32_t ngates, int32_t fuse, void *stream);
+
+/* The adiabatic ramp of the schedule at gate level: for each step
+ * k_begin <= k < k_end, the circuit of z2h_circuit_step with the step's
+ * couplings (x-type at sX[k] or s_k, z-type at sZ[k] or s_k), applied by
+ * z2h_gates_run on the n + 1 qubit state d_state.  renorm is ignored. */
+z2h_status z2h_circuit_evolve(int32_t Lx, int32_t Ly, z2h_dtype dtype, void *d_state, void *d_ws, size_t ws_bytes,
+                              const z2h_schedule *sched, int32_t fuse, void *stream);
+
 /* ------------------------------------------------------------------ tuning */
 
 /*

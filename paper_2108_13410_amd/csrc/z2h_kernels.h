@@ -209,6 +209,33 @@ hipError_t launch_vec(bool c128, const VecArgs &a, unsigned blocks, hipStream_t 
 hipError_t launch_scalar(const ScalarArgs &a, hipStream_t s);
 hipError_t launch_combine(bool c128, const CombineArgs &a, unsigned blocks, hipStream_t s);
 
+// ---- gate-level circuit emulation
+
+// One gate on device: kind as in the public header; m = the 2x2 matrix of a
+// one-qubit gate (row-major, re/im interleaved), computed on the host in FP64.
+struct GateDev {
+    int32_t kind, q0, q1, pad;
+    double m[8];
+};
+
+constexpr int kFuseMaxGates = 40;   // gates applied by one fused tile pass
+constexpr int kGateBlocksMax = 4096;
+
+// One fused pass: the tile holds the m qubits lq[0..m) (ascending; the
+// gates' qubits are local indices into it) and the tile number supplies the
+// other qubits cq[0..nq-m) in ascending order.
+struct FusedArgs {
+    void *state;
+    int32_t nq, m, ngates, pad;
+    int32_t lq[16];
+    int32_t cq[40];
+    GateDev gates[kFuseMaxGates];
+};
+
+hipError_t launch_gate(bool c128, void *state, int nq, const GateDev &g, hipStream_t s);
+hipError_t launch_fused(bool c128, const FusedArgs &a, hipStream_t s);
+hipError_t launch_normalize(bool c128, void *state, int nq, double *part, int nparts, hipStream_t s);
+
 LevelOp level_op_host(int lev, int K, int S, int k0, int order);
 
 // Register-window shapes (R, NL) with a compiled straight-line kernel.

@@ -63,6 +63,14 @@ class z2h_path(ctypes.Structure):
                 ("renorm", ctypes.c_int32), ("trace_every", ctypes.c_int32)]
 
 
+class z2h_gate(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("q0", ctypes.c_int32), ("q1", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("theta", ctypes.c_double)]
+
+
+Z2H_GATE_H, Z2H_GATE_RX, Z2H_GATE_RZ, Z2H_GATE_CNOT, Z2H_GATE_PROJ0, Z2H_GATE_NORM = range(6)
+
+
 class z2h_obs(ctypes.Structure):
     _fields_ = [("norm", ctypes.c_double), ("energy", ctypes.c_double),
                 ("sumA", ctypes.c_double), ("sumB", ctypes.c_double),
@@ -115,6 +123,12 @@ SIGNATURES = {
     "z2h_exact_evolve": (_i32, [_P, _P, _P, _sz, ctypes.POINTER(z2h_schedule), _i32, ctypes.POINTER(_dbl), _P]),
     "z2h_tridiag_lowest": (_i32, [_i32, _P, _P, ctypes.POINTER(_dbl)]),
     "z2h_tridiag_expv": (_i32, [_i32, _P, _P, _dbl, _P, _P]),
+    "z2h_circuit_step": (_i32, [_i32, _i32, ctypes.POINTER(z2h_couplings), ctypes.POINTER(z2h_couplings), _dbl, _i32,
+                                 _P, _i32, ctypes.POINTER(_i32)]),
+    "z2h_circuit_prep": (_i32, [_i32, _i32, _i32, _P, _i32, ctypes.POINTER(_i32)]),
+    "z2h_gates_ws_bytes": (_sz, [_i32]),
+    "z2h_gates_run": (_i32, [_i32, _i32, _P, _P, _sz, _P, _i32, _i32, _P]),
+    "z2h_circuit_evolve": (_i32, [_i32, _i32, _i32, _P, _P, _sz, ctypes.POINTER(z2h_schedule), _i32, _P]),
     "z2h_timing_enable": (_i32, [_i32]),
     "z2h_timing_read": (_i32, [_P, _P]),
     "z2h_version": (ctypes.c_char_p, []),
@@ -400,6 +414,48 @@ def z2h_tridiag_expv(alpha, beta, tau):
     _check(lib().z2h_tridiag_expv(len(a), a.ctypes.data_as(_P), b.ctypes.data_as(_P) if len(b) else None,
                                   float(tau), re.ctypes.data_as(_P), im.ctypes.data_as(_P)))
     return re + 1j * im
+
+
+# ------------------------------------------------------------------ gate-level circuits
+
+def _gate_list(fn, *args):
+    cnt = ctypes.c_int32()
+    code = fn(*args, None, 0, ctypes.byref(cnt))
+    if code not in (Z2H_OK, -6):
+        _check(code)
+    arr = (z2h_gate * max(cnt.value, 1))()
+    _check(fn(*args, arr, cnt.value, ctypes.byref(cnt)))
+    return arr, cnt.value
+
+
+def z2h_circuit_step(Lx, Ly, cx, cz, dt, order=0):
+    """The gates of one Trotter step (ctypes array, count)."""
+    cxs = cx if isinstance(cx, z2h_couplings) else couplings(*cx)
+    czs = cz if isinstance(cz, z2h_couplings) else couplings(*cz)
+    return _gate_list(lib().z2h_circuit_step, int(Lx), int(Ly), ctypes.byref(cxs), ctypes.byref(czs), float(dt),
+                      int(order))
+
+
+def z2h_circuit_prep(Lx, Ly, which=Z2H_INIT_PSI1):
+    return _gate_list(lib().z2h_circuit_prep, int(Lx), int(Ly), int(which))
+
+
+def gates_to_list(arr, n):
+    return [(g.kind, g.q0, g.q1, g.theta) for g in arr[:n]]
+
+
+def z2h_gates_ws_bytes(nq):
+    return int(lib().z2h_gates_ws_bytes(int(nq)))
+
+
+def z2h_gates_run(nq, dtype, state, ws, gates, ngates, fuse=1, stream=None):
+    _check(lib().z2h_gates_run(int(nq), int(dtype), _ptr(state), _ptr(ws), ws.numel() * ws.element_size(),
+                               gates, int(ngates), int(fuse), _stream(stream)))
+
+
+def z2h_circuit_evolve(Lx, Ly, dtype, state, ws, sched, fuse=1, stream=None):
+    _check(lib().z2h_circuit_evolve(int(Lx), int(Ly), int(dtype), _ptr(state), _ptr(ws),
+                                    ws.numel() * ws.element_size(), ctypes.byref(sched), int(fuse), _stream(stream)))
 
 
 class Batch:

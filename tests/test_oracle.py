@@ -443,3 +443,69 @@ def test_trotter_bound_table():
     e10 = bound.closed_form(p, r, rows[0][1], rows[0][2])
     e800 = bound.closed_form(p, r, rows[3][1], rows[3][2])
     assert abs(e10 / e800 - 6400) < 1e-6
+
+
+# ------------------------------------------------------------------ gate-level circuits (Sec. III)
+
+from oracle import circuit  # noqa: E402
+
+
+def test_circuit_gates_against_expm():
+    """Each gate's matrix and the ancilla gadget against scipy's expm: on
+    links with the ancilla in |0>, CNOTs - R_z(theta) - CNOTs equals
+    exp(-i theta/2 Z_links) and returns the ancilla to |0>."""
+    n = 5
+    rng = np.random.default_rng(21)
+    x = _rand_state(n, 22)
+    for name, M in (("RX", lambda t: sla.expm(-0.5j * t * SX)), ("RZ", lambda t: sla.expm(-0.5j * t * SZ))):
+        th = rng.uniform(-2, 2)
+        got = circuit.apply(x, [(name, (2,), th)])
+        ref = np.einsum("ij,ajb->aib", M(th), x.reshape(1 << (n - 3), 2, 4)).reshape(-1)
+        assert np.abs(got - ref).max() < 1e-14
+    links, anc, th = [0, 2, 3], 4, 0.83
+    y = circuit.apply(x[: 1 << 4].copy().tolist() + [0] * (1 << 4), circuit._gadget(anc, links, th))
+    zs = np.ones(1 << 4)
+    for i in range(1 << 4):
+        zs[i] = (-1) ** sum((i >> l) & 1 for l in links)
+    ref = np.exp(-0.5j * th * zs) * x[: 1 << 4]
+    assert np.abs(y[: 1 << 4] - ref).max() < 1e-14
+    assert np.abs(y[1 << 4:]).max() < 1e-15
+
+
+@pytest.mark.parametrize("Lx,Ly", [(2, 2), (2, 3)])
+@pytest.mark.parametrize("order", [0, 1])
+def test_circuit_step_equals_algebraic_step(Lx, Ly, order):
+    """Sec. III: one gate-level step with the ancilla in |0> equals the
+    oracle's Trotter step (Pauli-string exponentials, pinned above) on the
+    links, and leaves the ancilla in |0>."""
+    n = 2 * Lx * Ly
+    x = _rand_state(n, 30 + order)
+    cx, cz = (0.7, 0.4, 0.3, 0.2), (0.6, 0.9, 0.1, 0.45)
+    got = circuit.apply(circuit.with_ancilla(x), circuit.step_gates(Lx, Ly, cx, cz, 0.37, order))
+    ref = x.copy()
+    oracle.trotter_step(Lx, Ly, ref, cx, cz, 0.37, order)
+    assert np.abs(got[: 1 << n] - ref).max() < 1e-13
+    assert np.abs(got[1 << n:]).max() < 1e-14
+
+
+@pytest.mark.parametrize("Lx,Ly", [(2, 2), (2, 3)])
+def test_preparation_circuits(Lx, Ly):
+    """Eqs. (ini1) and (ini2) at gate level give psi_1 and psi_1'."""
+    n = 2 * Lx * Ly
+    zero = np.zeros(1 << (n + 1), complex)
+    zero[0] = 1
+    p1 = circuit.apply(zero, circuit.prep_gates(Lx, Ly, "psi1"))
+    p2 = circuit.apply(zero, circuit.prep_gates(Lx, Ly, "psi1p"))
+    assert np.abs(p1[: 1 << n] - oracle.init_psi1(Lx, Ly)).max() < 1e-14
+    assert np.abs(p2[: 1 << n] - oracle.init_psi1p(Lx, Ly)).max() < 1e-14
+    assert np.abs(p1[1 << n:]).max() == 0 and np.abs(p2[1 << n:]).max() == 0
+
+
+def test_circuit_gate_count():
+    """Per step: n rotations in each of the three field layers, and in each
+    of the two stabilizer halves 4 + 1 + 4 gates per plaquette gadget and
+    4 + 9 + 4 per star gadget: 3n + 2 (9 Np + 17 Ns) = 522 at 3x3."""
+    for Lx, Ly in ((2, 2), (3, 3), (4, 4)):
+        n, nv = 2 * Lx * Ly, Lx * Ly
+        assert len(circuit.step_gates(Lx, Ly, (1, 1, 0.1, 0.1), (1, 1, 0.1, 0.1), 0.1)) == 3 * n + 2 * 26 * nv
+    assert 3 * 18 + 2 * 26 * 9 == 522
