@@ -288,6 +288,59 @@ def paper_protocol(z2h, torch):
             "traces": "observables every 100 steps (every 1e-3 in g)"}
 
 
+def refinement_leg(z2h, torch, ns=(10, 200, 500, 800)):
+    """Table contrast_tab (Sec. VI): the red path to R(0.5, 0.05) and on to
+    R'(0, 0.05) with dg = 1e-4/n and dt = 0.2/n per step, n = 10 (the
+    protocol), 200, 500, 800; E_n(g) on the last leg at the n = 10 grid
+    (every 1e-5 in g, 50001 points); delta_n = sum |E_10 - E_n|, alpha_n =
+    max.  3x3, complex128; the four paths run concurrently, one stream each."""
+    import threading
+    import numpy as np
+    from paper_2108_13410_amd import protocols as pr
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C128)
+    sz = z2h.z2h_plan_sizes(plan)
+    runs = {}
+
+    def one(n):
+        init, verts, steps, dt = pr.refined_red_path(0.5, 0.05, n)
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            psi = z2h.alloc_state(plan)
+            ws = z2h.alloc_bytes(max(sz["ws_evolve"], sz["ws_observe"]))
+            z2h.z2h_state_init(plan, psi, z2h.Z2H_INIT_PSI1, stream=stream.cuda_stream)
+            t0 = time.perf_counter()
+            E = {}
+            for i in range(3):
+                # one leg per call; energies every 1e-5 in g on the two legs that vary g
+                every = n // 10 if i != 1 else 0
+                tr = z2h.z2h_path_evolve(plan, psi, ws, z2h.make_path(verts[i:i + 2], steps[i:i + 1], dt, sampling=1,
+                                                                      every=every), stream=stream.cuda_stream)
+                stream.synchronize()
+                E[i] = tr[:, 1].cpu().numpy()
+                print(f"refinement n={n}: leg {i + 1} of 3 done ({steps[i]} steps) after "
+                      f"{time.perf_counter() - t0:.0f} s", file=sys.stderr, flush=True)
+            runs[n] = (E[0], E[2], sum(steps), time.perf_counter() - t0)
+
+    threads = [threading.Thread(target=one, args=(n,)) for n in ns]
+    t0 = time.perf_counter()
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    wall = time.perf_counter() - t0
+    paper = {200: (0.03982, 4.79e-5), 500: (0.04009, 4.99e-5), 800: (0.04075, 4.98e-5)}
+    rows = []
+    for n in ns:
+        d1, a1 = pr.refinement_metrics(runs[ns[0]][0], runs[n][0])
+        d3, a3 = pr.refinement_metrics(runs[ns[0]][1], runs[n][1])
+        rows.append({"n": n, "steps": runs[n][2], "seconds": runs[n][3],
+                     "delta_n": d3, "alpha_n": a3, "delta_n_g_axis": d1, "alpha_n_g_axis": a1,
+                     "paper_delta_n": paper.get(n, (0.0, 0.0))[0], "paper_alpha_n": paper.get(n, (0.0, 0.0))[1]})
+    return {"rows": rows, "wall_seconds": wall, "grid_points": int(len(runs[ns[0]][1])),
+            "reading": "delta_n, alpha_n: E_n(g) on the leg R(0.5, 0.05) -> R'(0, 0.05); *_g_axis: on the leg "
+                       "O(0, 0) -> P(0.5, 0); every leg refined; 50001 points every 1e-5 in g"}
+
+
 def adjoint_leg(z2h, torch):
     """Gradient of the final energy (3x3, complex128, M = 200, T = 20, loss at
     (1, 1, 0.3, 0.3)) with respect to the 400 per-step schedule values, by
@@ -486,6 +539,8 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint and mixed-batch legs")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact-solver leg (Lanczos, Krylov)")
     ap.add_argument("--no-circuit", action="store_true", help="skip the gate-level circuit leg")
+    ap.add_argument("--refinement", action="store_true",
+                    help="add Table contrast_tab's refinement study (1.6e7 Trotter steps, a few minutes)")
     ap.add_argument("--circuit-4x4", action="store_true", help="add the 33-qubit gate-level step (about 10 s)")
     ap.add_argument("--tune-cache", default=None,
                     help="schedule cache: loaded if it has the needed entries, else written by the autotuner "
@@ -636,6 +691,12 @@ def main():
     if not args.no_protocol:
         line["paper_protocol"] = paper_protocol(z2h, torch)
         print(f"paper protocol: {line['paper_protocol']['trotter_steps_per_s']:.0f} steps/s", file=sys.stderr, flush=True)
+    if args.refinement:
+        line["refinement"] = refinement_leg(z2h, torch)
+        for r in line["refinement"]["rows"]:
+            print(f"refinement n={r['n']}: R->R' delta {r['delta_n']:.5f} alpha {r['alpha_n']:.3g}; "
+                  f"O->P delta {r['delta_n_g_axis']:.5f} alpha {r['alpha_n_g_axis']:.3g} "
+                  f"(paper {r['paper_delta_n']}, {r['paper_alpha_n']}), {r['seconds']:.0f} s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(15)
     line["paper_context"] = {"rtx3090_c128_19q": ">= 0.8e7-1.8e7 link-amplitude-updates/s (derived "

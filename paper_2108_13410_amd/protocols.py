@@ -13,6 +13,9 @@ taken at the end of each step.
                       R(p, r), then along lambda = r to R'(0, r).
   dual_path(q)        Fig. dual_evo: psi_1' along the lambda axis to (0, q),
                       across to (q, q), then down the dual line to O.
+  refined_red_path    the red path with n times finer steps (Sec. VI,
+                      Table contrast_tab), and refinement_metrics for the
+                      table's delta_n and alpha_n.
 """
 from __future__ import annotations
 
@@ -51,6 +54,26 @@ def red_path(p, r):
 
 def dual_path(q=0.5):
     return ("psi1p", *path([(0, 0), (0, q), (q, q), (0, 0)]))
+
+
+def refined_red_path(p, r, n):
+    """The red path with the step refinement of Sec. VI: dg = 1e-4 / n and
+    dt = 0.2 / n per step on every leg (n = 10 is the protocol above).
+    Returns (init, vertices, steps, dt)."""
+    dg = 1e-4 / n
+    verts = [pt(0, 0), pt(p, 0), pt(p, r), pt(0, r)]
+    steps = []
+    for a, b in zip(verts[:-1], verts[1:]):
+        d = max(abs(b[2] - a[2]), abs(b[3] - a[3]))
+        steps.append(int(round(d / dg)))
+    return "psi1", verts, steps, 0.2 / n
+
+
+def refinement_metrics(E_ref, E_n):
+    """Table contrast_tab: delta_n = sum over the grid of |E_n0(g) - E_n(g)|
+    (1-norm), alpha_n = its maximum."""
+    d = np.abs(np.asarray(E_ref, float) - np.asarray(E_n, float))
+    return float(d.sum()), float(d.max())
 
 
 def second_derivative(x, E, w=10):

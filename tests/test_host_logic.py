@@ -386,3 +386,69 @@ def test_exact_solver_sizes_and_argument_checks():
         z2h._check(code)
     with pytest.raises(z2h.Z2HError):
         z2h._check(z2h.lib().z2h_tridiag_expv(33, None, None, 0.1, None, None))
+
+
+# ------------------------------------------------------------------ gate-level circuits (host parts)
+
+@pytest.mark.parametrize("Lx,Ly", [(2, 2), (2, 3), (3, 3), (3, 4), (4, 4)])
+def test_circuit_step_structure(Lx, Ly):
+    """The library's step circuit: 3n field rotations and, in each of the two
+    stabilizer halves, a CNOT-R_z-CNOT gadget per plaquette and the same
+    inside Hadamards per star (3n + 52 Ns gates; 522 at 3x3).  Every CNOT
+    targets the ancilla (qubit n), every R_z on the ancilla carries the
+    coupling's angle, and the layers come in the order of Eq. (decom)."""
+    n, nv = 2 * Lx * Ly, Lx * Ly
+    cx, cz, dt = (0.7, 0.4, 0.3, 0.2), (0.6, 0.9, 0.1, 0.45), 0.37
+    arr, cnt = z2h.z2h_circuit_step(Lx, Ly, cx, cz, dt, 0)
+    g = z2h.gates_to_list(arr, cnt)
+    assert cnt == 3 * n + 52 * nv
+    if (Lx, Ly) == (3, 3):
+        assert cnt == 522
+    assert [k for k, *_ in g[:n]] == [z2h.Z2H_GATE_RX] * n
+    assert all(abs(t - (-cx[2] * dt)) < 1e-15 for _, _, _, t in g[:n])
+    assert all(q1 == n for k, q0, q1, _ in g if k == z2h.Z2H_GATE_CNOT)
+    anc_rz = [t for k, q0, _, t in g if k == z2h.Z2H_GATE_RZ and q0 == n]
+    assert sorted(set(round(t, 15) for t in anc_rz)) == sorted({round(-cz[1] * dt, 15), round(-cx[0] * dt, 15)})
+    assert len(anc_rz) == 2 * 2 * nv
+    link_rz = [t for k, q0, _, t in g if k == z2h.Z2H_GATE_RZ and q0 < n]
+    assert len(link_rz) == n and all(abs(t + 2 * cz[3] * dt) < 1e-15 for t in link_rz)
+    st, pl = z2h.z2h_masks(Lx, Ly)
+    # the first gadget belongs to plaquette 0: CNOTs from exactly its links
+    first = g[n:n + 4]
+    assert sum(1 << q0 for _, q0, _, _ in first) == int(pl[0])
+
+
+def test_circuit_prep_structure():
+    arr, cnt = z2h.z2h_circuit_prep(3, 3, z2h.Z2H_INIT_PSI1)
+    g = z2h.gates_to_list(arr, cnt)
+    assert cnt == 18 + 9 * 9 + 1
+    assert g[-1][0] == z2h.Z2H_GATE_NORM
+    assert sum(1 for k, *_ in g if k == z2h.Z2H_GATE_PROJ0) == 9
+    arr, cnt = z2h.z2h_circuit_prep(3, 3, z2h.Z2H_INIT_PSI1P)
+    assert cnt == 9 * (4 + 4 + 1 + 4 + 4) + 1
+    with pytest.raises(z2h.Z2HError):
+        z2h.z2h_circuit_prep(3, 3, z2h.Z2H_INIT_PLUS)
+
+
+def test_gate_list_validation():
+    """Rejections that happen before any device work."""
+    G = z2h.z2h_gate
+    ws = np.zeros(4096, np.uint8)
+
+    def run(nq, gates, fuse=0):
+        arr = (G * len(gates))(*[G(*g) for g in gates])
+        code = z2h.lib().z2h_gates_run(nq, z2h.Z2H_C128, ctypes.c_void_p(256), ws.ctypes.data_as(ctypes.c_void_p),
+                                       ws.nbytes, arr, len(gates), fuse, None)
+        return code
+
+    assert run(5, [(z2h.Z2H_GATE_H, 5, 0, 0, 0.0)]) == -1          # qubit out of range
+    assert run(5, [(z2h.Z2H_GATE_CNOT, 1, 1, 0, 0.0)]) == -1       # control == target
+    assert run(5, [(9, 0, 0, 0, 0.0)]) == -1                       # unknown kind
+    assert run(1, [(z2h.Z2H_GATE_H, 0, 0, 0, 0.0)]) == -1          # nq too small
+    assert run(35, [(z2h.Z2H_GATE_H, 0, 0, 0, 0.0)]) == -1         # nq too large
+    assert run(5, [(z2h.Z2H_GATE_RX, 0, 0, 0, float("nan"))]) == -1
+    assert z2h.z2h_gates_ws_bytes(1) == 0 and z2h.z2h_gates_ws_bytes(19) >= 8 * 2048
+    cnt = ctypes.c_int32()
+    code = z2h.lib().z2h_circuit_step(3, 3, ctypes.byref(z2h.couplings()), ctypes.byref(z2h.couplings()), 0.1, 0,
+                                      None, 0, ctypes.byref(cnt))
+    assert code == -6 and cnt.value == 522
