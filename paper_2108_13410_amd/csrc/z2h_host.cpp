@@ -360,9 +360,11 @@ static z2h_status apply_split(Plan &P, const GroupChoice *ch, int K) {
         if (ch[j].np != 1 && ch[j].np != 2) return fail(Z2H_ERR_INVALID, "group %d: %d tiles per block", j, ch[j].np);
         if (ch[j].np == 2) {
             // the block's two tiles differ in the lowest tile bit, which must
-            // sit right above the carried bits for the pair to be contiguous
-            if (j == 0 || g.b0 - g.c < 1 || g.tiles_log2 < 1)
-                return fail(Z2H_ERR_INVALID, "group %d: two-tile blocks need a strided group with tile bits below it", j);
+            // sit right above the carried bits (strided group) or right above
+            // the tile (group 0: two adjacent chunks) for the pair to be
+            // contiguous
+            if ((j > 0 && g.b0 - g.c < 1) || g.tiles_log2 < 1)
+                return fail(Z2H_ERR_INVALID, "group %d: two-tile blocks need tile bits next to the tile", j);
             if (!g.full || !pair_level_ok(P.c128, g.R, g.full))
                 return fail(Z2H_ERR_UNSUPPORTED, "group %d: no two-tile kernel for window %d x %d", j, g.R, g.full);
             g.pair = 2;
@@ -548,12 +550,15 @@ static std::vector<TileOpt> group_tiles(const Plan &P, int j, int b0, int G, int
         return lds_bytes(P, g, R) <= (size_t)kMaxLdsBytes;
     };
     const int c_lo = P.c128 ? 2 : 3;
+    const bool pair = (G % R == 0) && pair_level_ok(P.c128, R, G / R);
     if (j == 0) {
         for (int m = G; m <= std::min(m_hi, P.n); ++m)
-            if (m - R >= 6 && m - R <= 9 && lds_ok(m)) out.push_back({m, 0, 1});
+            if (m - R >= 6 && m - R <= 9 && lds_ok(m)) {
+                out.push_back({m, 0, 1});
+                if (pair && m == G && P.n - m >= 1) out.push_back({m, 0, 2});
+            }
         return out;
     }
-    const bool pair = (G % R == 0) && pair_level_ok(P.c128, R, G / R);
     for (int c = c_lo; c <= b0; ++c) {
         const int m = c + G;
         if (m > m_hi) break;

@@ -134,7 +134,7 @@ def test_autotuner_candidates_are_valid_plans(Lx, Ly, dt):
 
 def test_schedule_strings_rejected():
     for bad in ("split=10:5:13:0", "split=10:5:13:1/8:4:13:5", "split=10:5:13:0/8:4:19:11", "split=10:5:16:0/8:4:13:5",
-                "split=10:5:11:0:2/8:4:13:5", "split=10:5:11:0/8:4:13:5:3", "nonsense"):
+                "split=10:5:11:0/8:4:13:5:3", "split=18:3:18:0:2", "nonsense"):
         with pytest.raises(z2h.Z2HError):
             z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C64, bad)
     # two-tile blocks exist for complex64 only
@@ -143,6 +143,10 @@ def test_schedule_strings_rejected():
     ok = z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C64, "split=10:5:11:0/8:4:12:4:2")
     assert z2h.z2h_plan_describe(ok)["groups"][1]["pair"] == 2
     check_geometry(ok)
+    # group 0 in two-tile blocks (two adjacent chunks)
+    ok0 = z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C64, "split=12:4:12:0:2/6:3:11:5:2")
+    assert [g["pair"] for g in z2h.z2h_plan_describe(ok0)["groups"]] == [2, 2]
+    check_geometry(ok0)
 
 
 def check_full_lds(g, n, esize):
@@ -233,12 +237,15 @@ def check_geometry(plan):
         if g["full"] and K > 1:
             check_full_lds(g, n, 16 if d["c128"] else 8)
         if g.get("pair", 1) == 2:
-            # two-tile blocks: tiles 2u and 2u + 1 differ only in global bit c,
-            # so a block's rows are 2^(c+1) contiguous amplitudes
-            assert gi > 0 and g["tiles_log2"] >= 1 and b0 - c >= 1 and g["full"]
+            # two-tile blocks: tiles 2u and 2u + 1 differ only in global bit c
+            # (a strided group's rows become 2^(c+1) contiguous amplitudes) or,
+            # in group 0, in bit m (two adjacent chunks of 2^m amplitudes)
+            assert g["tiles_log2"] >= 1 and g["full"]
+            assert (gi > 0 and b0 - c >= 1) or (gi == 0 and c == 0)
+            step = 1 << c if gi > 0 else 1 << m
             e = np.arange(1 << m)
             for u in (0, (1 << (g["tiles_log2"] - 1)) - 1):
-                assert np.array_equal(glob(g, 2 * u + 1, e) - glob(g, 2 * u, e), np.full(e.size, 1 << c))
+                assert np.array_equal(glob(g, 2 * u + 1, e) - glob(g, 2 * u, e), np.full(e.size, step))
         if n <= 18:
             # all tiles together cover the state exactly once
             e = np.arange(1 << m)
