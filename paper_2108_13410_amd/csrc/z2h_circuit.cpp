@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "z2h_runtime.h"
+#include "z2h_solvers.h"
 
 using namespace z2h;
 using namespace z2h::rt;

@@ -8,6 +8,7 @@
 #include "../../include/z2h.h"
 #include "z2h_internal.h"
 #include "z2h_kernels.h"
+#include "z2h_solvers.h"
 #include "z2h_tile.h"
 
 namespace z2h {
