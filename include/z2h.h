@@ -258,6 +258,35 @@ z2h_status z2h_path_evolve(const z2h_plan *plan, void *d_state, void *d_ws, size
                            const uint64_t *xmasks, int32_t nx, double *d_trace, int64_t trace_cap,
                            int64_t *n_samples, void *stream);
 
+/*
+ * Many paths on one lattice at once (the paper's protocols batched over the
+ * paths' parameters, e.g. the red paths for several r, Secs. IV-V).  The
+ * npaths states lie contiguously at d_states (state j at element offset
+ * j * 2^n; initialise them with z2h_state_init), and all paths must have the
+ * same number of vertices, trace_every and step order; vertices, step
+ * counts, dt, sampling and renorm may differ per path.  Leg i runs for all
+ * paths together in segments of trace_every steps of the longest leg i (one
+ * segment if trace_every is 0); after each segment every path is observed
+ * with the couplings of the point it reached (a path whose leg is shorter
+ * repeats its end state; a leg of zero steps is observed at its end
+ * vertex).  Segment boundaries are those of z2h_path_evolve, so a path whose
+ * legs all have the longest length gets exactly z2h_path_evolve's samples.
+ * One pass launch serves every path.
+ *
+ * z2h_paths_sizes: samples (1 + the segments of every leg) and the workspace
+ * (norm partials, one transformed copy per path, observable records, segment
+ * records).  z2h_paths_evolve: d_trace (device) receives samples * npaths
+ * records of Z2H_OBS_DOUBLES doubles, sample-major (record of path j in
+ * sample s at (s * npaths + j) * Z2H_OBS_DOUBLES).  Loop masks as in
+ * z2h_observe.  Synchronizes the stream once per leg.  Errors:
+ * Z2H_ERR_INVALID (paths, masks, buffers), Z2H_ERR_WORKSPACE.
+ */
+z2h_status z2h_paths_sizes(const z2h_plan *plan, int32_t npaths, const z2h_path *paths, int64_t *n_samples,
+                           size_t *ws_bytes);
+z2h_status z2h_paths_evolve(const z2h_plan *plan, int32_t npaths, void *d_states, void *d_ws, size_t ws_bytes,
+                            const z2h_path *paths, const uint64_t *zmasks, int32_t nz, const uint64_t *xmasks,
+                            int32_t nx, double *d_trace, void *stream);
+
 /* ------------------------------------------------------------------ batches */
 
 /*

@@ -129,6 +129,8 @@ SIGNATURES = {
     "z2h_gates_ws_bytes": (_sz, [_i32]),
     "z2h_gates_run": (_i32, [_i32, _i32, _P, _P, _sz, _P, _i32, _i32, _P]),
     "z2h_circuit_evolve": (_i32, [_i32, _i32, _i32, _P, _P, _sz, ctypes.POINTER(z2h_schedule), _i32, _P]),
+    "z2h_paths_sizes": (_i32, [_P, _i32, _P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_sz)]),
+    "z2h_paths_evolve": (_i32, [_P, _i32, _P, _P, _sz, _P, _P, _i32, _P, _i32, _P, _P]),
     "z2h_timing_enable": (_i32, [_i32]),
     "z2h_timing_read": (_i32, [_P, _P]),
     "z2h_version": (ctypes.c_char_p, []),
@@ -456,6 +458,34 @@ def z2h_gates_run(nq, dtype, state, ws, gates, ngates, fuse=1, stream=None):
 def z2h_circuit_evolve(Lx, Ly, dtype, state, ws, sched, fuse=1, stream=None):
     _check(lib().z2h_circuit_evolve(int(Lx), int(Ly), int(dtype), _ptr(state), _ptr(ws),
                                     ws.numel() * ws.element_size(), ctypes.byref(sched), int(fuse), _stream(stream)))
+
+
+def z2h_paths_evolve(plan, paths, states=None, inits=None, zmasks=None, xmasks=None, stream=None):
+    """Run several paths of one lattice together.  paths: list of make_path
+    objects; states: device tensor of len(paths) * 2^n complex elements (or
+    None: allocated and initialised from inits, Z2H_INIT_* per path).
+    Returns (states, trace) with trace shaped (samples, len(paths), 56)."""
+    import torch
+    n = plan.n
+    npaths = len(paths)
+    arr = (z2h_path * npaths)(*paths)
+    ns = ctypes.c_int64()
+    wsb = ctypes.c_size_t()
+    L = lib()
+    _check(L.z2h_paths_sizes(plan.handle, npaths, arr, ctypes.byref(ns), ctypes.byref(wsb)))
+    if states is None:
+        dt = torch.complex128 if plan.dtype == Z2H_C128 else torch.complex64
+        states = torch.empty(npaths << n, dtype=dt, device="cuda")
+        for j in range(npaths):
+            z2h_state_init(plan, states[j << n:(j + 1) << n], (inits or [Z2H_INIT_PSI1] * npaths)[j], stream=stream)
+    ws = alloc_bytes(wsb.value, device=states.device)
+    trace = torch.empty((ns.value, npaths, Z2H_OBS_DOUBLES), dtype=torch.float64, device=states.device)
+    zp, nz, za = _masks_arg(zmasks)
+    xp, nx, xa = _masks_arg(xmasks)
+    _check(L.z2h_paths_evolve(plan.handle, npaths, _ptr(states), _ptr(ws), wsb.value, arr, zp, nz, xp, nx,
+                              _ptr(trace), _stream(stream)))
+    del za, xa, arr
+    return states, trace
 
 
 class Batch:

@@ -5,6 +5,7 @@ Legs are emulated on the oracle with explicit per-step schedule values, so
 the oracle runs exactly the steps the path prescribes."""
 import numpy as np
 import pytest
+import torch
 
 import oracle
 from helpers import compare_observables, oracle_observables, standard_loops_lib, to_oracle_order
@@ -93,3 +94,59 @@ def test_untraced_path_equals_ramps():
         z2h.z2h_evolve(plan, b, ws, z2h.schedule(verts[i], verts[i + 1], M, 0.05, sampling=1, renorm=1))
     torch.cuda.synchronize()
     assert torch.equal(torch.view_as_real(a), torch.view_as_real(b))
+
+
+def _single_path_trace(plan, path, init):
+    psi = z2h.alloc_state(plan)
+    z2h.z2h_state_init(plan, psi, init)
+    sz = z2h.z2h_plan_sizes(plan)
+    ws = z2h.alloc_bytes(max(sz["ws_evolve"], sz["ws_observe"]))
+    tr = z2h.z2h_path_evolve(plan, psi, ws, path)
+    torch.cuda.synchronize()
+    return psi, tr.cpu().numpy()
+
+
+@pytest.mark.parametrize("dtype", [z2h.Z2H_C128, z2h.Z2H_C64])
+def test_paths_batched_equal_single(dtype):
+    """z2h_paths_evolve on three 3x3 paths (different couplings and initial
+    states, equal leg lengths) gives, path by path, exactly the samples and
+    final states of separate z2h_path_evolve calls."""
+    plan = z2h.z2h_plan_create(3, 3, dtype)
+    renorm = 1 if dtype == z2h.Z2H_C64 else 0
+    paths, inits = [], []
+    for j, g in enumerate((0.2, 0.3, 0.45)):
+        verts = [(0.5, 0.5, 0.0, 0.0), (0.5, 0.5, g, 0.0), (0.5, 0.5, g, 0.1), (0.5, 0.5, 0.0, 0.1)]
+        paths.append(z2h.make_path(verts, [30, 10, 30], 0.05, sampling=1, renorm=renorm, every=10))
+        inits.append(z2h.Z2H_INIT_PSI1 if j != 1 else z2h.Z2H_INIT_PSI1P)
+    print(f"case batched paths dtype={dtype}", flush=True)
+    states, trace = z2h.z2h_paths_evolve(plan, paths, inits=inits)
+    torch.cuda.synchronize()
+    tr = trace.cpu().numpy()
+    n = 18
+    for j, path in enumerate(paths):
+        psi, ref = _single_path_trace(plan, path, inits[j])
+        assert tr.shape[0] == ref.shape[0] == 1 + 3 + 1 + 3
+        assert np.array_equal(tr[:, j, :], ref), (j, np.abs(tr[:, j, :] - ref).max())
+        assert torch.equal(states[j << n:(j + 1) << n], psi)
+
+
+def test_paths_batched_ragged_legs():
+    """Legs of different length (the red paths' rise to lambda = r): the
+    shorter path repeats its leg-end sample while the longer one runs on, and
+    otherwise matches its own single-path trace bitwise."""
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C128)
+    mk = lambda r, m: z2h.make_path([(0.5, 0.5, 0.0, 0.0), (0.5, 0.5, 0.3, 0.0), (0.5, 0.5, 0.3, r),
+                                     (0.5, 0.5, 0.0, r)], [20, m, 20], 0.05, sampling=1, every=10)
+    short, long_ = mk(0.05, 5), mk(0.15, 15)
+    print("case batched paths, ragged legs", flush=True)
+    states, trace = z2h.z2h_paths_evolve(plan, [short, long_])
+    torch.cuda.synchronize()
+    tr = trace.cpu().numpy()
+    _, ref_s = _single_path_trace(plan, short, z2h.Z2H_INIT_PSI1)
+    _, ref_l = _single_path_trace(plan, long_, z2h.Z2H_INIT_PSI1)
+    assert tr.shape[0] == 1 + 2 + 2 + 2 and ref_l.shape[0] == 7 and ref_s.shape[0] == 6
+    assert np.array_equal(tr[:, 1, :], ref_l)
+    # short path: samples 0-2 (start, leg 1), leg 2 end twice, then leg 3
+    assert np.array_equal(tr[:4, 0, :], ref_s[:4])
+    assert np.array_equal(tr[4, 0, :], ref_s[3])
+    assert np.array_equal(tr[5:, 0, :], ref_s[4:])
