@@ -246,11 +246,78 @@ z2h_status run_fused(int nq, bool c128, void *st, double *parts, const z2h_gate 
     return flush();
 }
 
+// Register groups: consecutive gates on at most kRegBits qubits, applied by
+// one pass in which every thread holds the amplitudes that differ in those
+// qubits.  The group's qubit set is padded with the highest remaining qubits
+// so that the 256 threads of a block cover the lowest ones (coalesced
+// access).  States of fewer than kRegBits + 6 qubits use LDS groups instead.
+z2h_status run_reg(int nq, bool c128, void *st, double *parts, const z2h_gate *g, int ng, hipStream_t s) {
+    if (nq < kRegBits + 6) return run_fused(nq, c128, st, parts, g, ng, s);
+    const int nt = std::min(8, nq - kRegBits);
+    std::vector<int> U, group;
+    auto has = [&](int q) { return std::find(U.begin(), U.end(), q) != U.end(); };
+    auto flush = [&]() -> z2h_status {
+        if (group.empty()) return Z2H_OK;
+        std::vector<char> in(nq, 0);
+        for (int q : U) in[q] = 1;
+        for (int q = nq - 1; (int)U.size() < kRegBits; --q)
+            if (!in[q]) {
+                in[q] = 1;
+                U.push_back(q);
+            }
+        RegArgs a;
+        memset(&a, 0, sizeof a);
+        a.state = st;
+        a.nq = nq;
+        a.nt = nt;
+        a.ngates = (int)group.size();
+        int loc[kMaxCircuitQubits];
+        for (int i = 0; i < kRegBits; ++i) {
+            a.rq[i] = U[i];
+            loc[U[i]] = i;
+        }
+        int k = 0, c = 0;
+        for (int q = 0; q < nq; ++q) {
+            if (in[q]) continue;
+            if (k < nt)
+                a.tq[k++] = q;
+            else
+                a.cq[c++] = q;
+        }
+        for (int i = 0; i < a.ngates; ++i) {
+            const z2h_gate &x = g[group[i]];
+            a.gates[i] = device_gate(x, loc[x.q0], x.kind == Z2H_GATE_CNOT ? loc[x.q1] : 0);
+        }
+        hipError_t e = launch_reg(c128, a, s);
+        if (e != hipSuccess) return fail(Z2H_ERR_HIP, "register gate pass failed: %s", hipGetErrorString(e));
+        U.clear();
+        group.clear();
+        return Z2H_OK;
+    };
+    for (int i = 0; i < ng; ++i) {
+        z2h_status st_;
+        if (g[i].kind == Z2H_GATE_NORM) {
+            if ((st_ = flush())) return st_;
+            hipError_t e = launch_normalize(c128, st, nq, parts, gate_parts(nq), s);
+            if (e != hipSuccess) return fail(Z2H_ERR_HIP, "normalisation failed: %s", hipGetErrorString(e));
+            continue;
+        }
+        const bool cn = g[i].kind == Z2H_GATE_CNOT;
+        const int add = !has(g[i].q0) + (cn && !has(g[i].q1));
+        if ((int)U.size() + add > kRegBits || (int)group.size() == kFuseMaxGates)
+            if ((st_ = flush())) return st_;
+        if (!has(g[i].q0)) U.push_back(g[i].q0);
+        if (cn && !has(g[i].q1)) U.push_back(g[i].q1);
+        group.push_back(i);
+    }
+    return flush();
+}
+
 z2h_status run_gates(int nq, z2h_dtype dtype, void *d_state, void *d_ws, size_t ws_bytes, const z2h_gate *gates,
                      int ng, int fuse, hipStream_t s) {
     if (nq < 2 || nq > kMaxCircuitQubits) return fail(Z2H_ERR_INVALID, "nq = %d outside [2, %d]", nq, kMaxCircuitQubits);
     if (dtype != Z2H_C64 && dtype != Z2H_C128) return fail(Z2H_ERR_INVALID, "unknown dtype %d", dtype);
-    if (fuse != 0 && fuse != 1) return fail(Z2H_ERR_INVALID, "fuse must be 0 or 1");
+    if (fuse < 0 || fuse > 2) return fail(Z2H_ERR_INVALID, "fuse must be 0, 1 or 2");
     if (ng < 0 || (ng > 0 && !gates)) return fail(Z2H_ERR_INVALID, "gate list");
     z2h_status st = validate_state_ptr(d_state, "d_state");
     if (st) return st;
@@ -260,6 +327,7 @@ z2h_status run_gates(int nq, z2h_dtype dtype, void *d_state, void *d_ws, size_t 
                     sizeof(double) * (size_t)gate_parts(nq));
     if ((st = check_gates(nq, gates, ng))) return st;
     const bool c128 = dtype == Z2H_C128;
+    if (fuse == 2) return run_reg(nq, c128, d_state, (double *)d_ws, gates, ng, s);
     return fuse ? run_fused(nq, c128, d_state, (double *)d_ws, gates, ng, s)
                 : run_unfused(nq, c128, d_state, (double *)d_ws, gates, ng, s);
 }

@@ -149,6 +149,117 @@ __global__ void __launch_bounds__(256) fused_kernel(FusedArgs a) {
     }
 }
 
+// Gates on register bits: every one-qubit gate, CNOT and projection acts
+// on pairs of a thread's own registers, with the bit positions fixed at
+// compile time (a runtime switch picks the instantiation).
+template <typename Real, int B>
+__device__ __forceinline__ void reg_1q(Cx<Real> (&v)[1 << kRegBits], const double *m) {
+#pragma unroll
+    for (int k = 0; k < (1 << kRegBits); ++k)
+        if (!(k & (1 << B))) apply_2x2<Real>(v[k], v[k | (1 << B)], m);
+}
+
+template <typename Real, int B>
+__device__ __forceinline__ void reg_proj0(Cx<Real> (&v)[1 << kRegBits]) {
+#pragma unroll
+    for (int k = 0; k < (1 << kRegBits); ++k)
+        if (k & (1 << B)) v[k] = Cx<Real>{(Real)0, (Real)0};
+}
+
+template <typename Real, int C, int T>
+__device__ __forceinline__ void reg_cnot(Cx<Real> (&v)[1 << kRegBits]) {
+    if constexpr (C != T) {
+#pragma unroll
+        for (int k = 0; k < (1 << kRegBits); ++k)
+            if ((k & (1 << C)) && !(k & (1 << T))) {
+                const Cx<Real> x = v[k];
+                v[k] = v[k | (1 << T)];
+                v[k | (1 << T)] = x;
+            }
+    }
+}
+
+template <typename Real, int C>
+__device__ __forceinline__ void reg_cnot_t(Cx<Real> (&v)[1 << kRegBits], int t) {
+    switch (t) {
+        case 0: reg_cnot<Real, C, 0>(v); break;
+        case 1: reg_cnot<Real, C, 1>(v); break;
+        case 2: reg_cnot<Real, C, 2>(v); break;
+        case 3: reg_cnot<Real, C, 3>(v); break;
+        default: reg_cnot<Real, C, 4>(v); break;
+    }
+}
+
+template <typename Real>
+__device__ __forceinline__ void reg_gate(Cx<Real> (&v)[1 << kRegBits], const GateDev &g) {
+    static_assert(kRegBits == 5, "the switches below cover five register bits");
+    if (g.kind == Z2H_GATE_CNOT) {
+        switch (g.q0) {
+            case 0: reg_cnot_t<Real, 0>(v, g.q1); break;
+            case 1: reg_cnot_t<Real, 1>(v, g.q1); break;
+            case 2: reg_cnot_t<Real, 2>(v, g.q1); break;
+            case 3: reg_cnot_t<Real, 3>(v, g.q1); break;
+            default: reg_cnot_t<Real, 4>(v, g.q1); break;
+        }
+    } else if (g.kind == Z2H_GATE_PROJ0) {
+        switch (g.q0) {
+            case 0: reg_proj0<Real, 0>(v); break;
+            case 1: reg_proj0<Real, 1>(v); break;
+            case 2: reg_proj0<Real, 2>(v); break;
+            case 3: reg_proj0<Real, 3>(v); break;
+            default: reg_proj0<Real, 4>(v); break;
+        }
+    } else {
+        switch (g.q0) {
+            case 0: reg_1q<Real, 0>(v, g.m); break;
+            case 1: reg_1q<Real, 1>(v, g.m); break;
+            case 2: reg_1q<Real, 2>(v, g.m); break;
+            case 3: reg_1q<Real, 3>(v, g.m); break;
+            default: reg_1q<Real, 4>(v, g.m); break;
+        }
+    }
+}
+
+// A group of gates on at most five qubits, applied in registers: load the
+// thread's 32 amplitudes, apply every gate, store.  No LDS and no barriers.
+template <typename Real>
+__global__ void __launch_bounds__(256) reg_kernel(RegArgs a) {
+    Cx<Real> *st = reinterpret_cast<Cx<Real> *>(a.state);
+    const uint32_t t = threadIdx.x;
+    uint64_t tpart = 0;
+    for (int j = 0; j < a.nt; ++j) tpart |= (uint64_t)((t >> j) & 1u) << a.tq[j];
+    uint64_t roff[kRegBits];
+#pragma unroll
+    for (int i = 0; i < kRegBits; ++i) roff[i] = 1ull << a.rq[i];
+    const int ncq = a.nq - kRegBits - a.nt;
+    const uint64_t tiles = 1ull << ncq;
+    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        uint64_t base = tpart;
+        for (int j = 0; j < ncq; ++j) base |= ((tile >> j) & 1ull) << a.cq[j];
+        Cx<Real> v[1 << kRegBits];
+#pragma unroll
+        for (int k = 0; k < (1 << kRegBits); ++k) {
+            uint64_t i = base;
+#pragma unroll
+            for (int b = 0; b < kRegBits; ++b)
+                if (k & (1 << b)) i |= roff[b];
+            v[k] = st[i];
+        }
+        for (int g = 0; g < a.ngates; ++g) reg_gate<Real>(v, a.gates[g]);
+        // recompute the store addresses rather than keep the 32 load
+        // addresses alive through the gates (two registers each)
+        asm volatile("" : "+v"(base));
+#pragma unroll
+        for (int k = 0; k < (1 << kRegBits); ++k) {
+            uint64_t i = base;
+#pragma unroll
+            for (int b = 0; b < kRegBits; ++b)
+                if (k & (1 << b)) i |= roff[b];
+            st[i] = v[k];
+        }
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 
 static unsigned blocks_for(uint64_t work) {
@@ -174,6 +285,16 @@ hipError_t launch_fused(bool c128, const FusedArgs &a, hipStream_t s) {
         hipLaunchKernelGGL(fused_kernel<double>, dim3(nb), dim3(256), lds, s, a);
     else
         hipLaunchKernelGGL(fused_kernel<float>, dim3(nb), dim3(256), lds, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_reg(bool c128, const RegArgs &a, hipStream_t s) {
+    const uint64_t tiles = 1ull << (a.nq - kRegBits - a.nt);
+    const unsigned nb = (unsigned)(tiles < (uint64_t)kGateBlocksMax ? tiles : (uint64_t)kGateBlocksMax);
+    if (c128)
+        hipLaunchKernelGGL(reg_kernel<double>, dim3(nb), dim3(1u << a.nt), 0, s, a);
+    else
+        hipLaunchKernelGGL(reg_kernel<float>, dim3(nb), dim3(1u << a.nt), 0, s, a);
     return hipGetLastError();
 }
 

@@ -119,7 +119,22 @@ struct FusedArgs {
     GateDev gates[kFuseMaxGates];
 };
 
+// One register-group pass: each thread holds the 2^kRegBits amplitudes that
+// differ in the group's qubits rq[] (its register bits); the 2^nt threads of
+// a block differ in qubits tq[]; the block's tile number supplies the other
+// qubits cq[].  Gate qubits are register-bit indices.
+constexpr int kRegBits = 5;
+struct RegArgs {
+    void *state;
+    int32_t nq, nt, ngates, pad;
+    int32_t rq[kRegBits], pad2[3];
+    int32_t tq[8];
+    int32_t cq[40];
+    GateDev gates[kFuseMaxGates];
+};
+
 hipError_t launch_gate(bool c128, void *state, int nq, const GateDev &g, hipStream_t s);
+hipError_t launch_reg(bool c128, const RegArgs &a, hipStream_t s);
 hipError_t launch_fused(bool c128, const FusedArgs &a, hipStream_t s);
 hipError_t launch_normalize(bool c128, void *state, int nq, double *part, int nparts, hipStream_t s);
 

@@ -47,7 +47,7 @@ def run(nq, dtype, psi, gates, ngates, fuse):
 
 
 @pytest.mark.parametrize("Lx,Ly", [(2, 2), (2, 3), (3, 3)])
-@pytest.mark.parametrize("fuse", [0, 1])
+@pytest.mark.parametrize("fuse", [0, 1, 2])
 @pytest.mark.parametrize("dtype,order", [(z2h.Z2H_C128, 0), (z2h.Z2H_C128, 1), (z2h.Z2H_C64, 0)])
 def test_circuit_step_against_oracle_circuit(Lx, Ly, fuse, dtype, order):
     n = 2 * Lx * Ly
@@ -70,7 +70,7 @@ def test_circuit_step_against_oracle_circuit(Lx, Ly, fuse, dtype, order):
 
 @pytest.mark.parametrize("Lx,Ly", [(2, 3), (3, 3)])
 @pytest.mark.parametrize("which", [z2h.Z2H_INIT_PSI1, z2h.Z2H_INIT_PSI1P])
-@pytest.mark.parametrize("fuse", [0, 1])
+@pytest.mark.parametrize("fuse", [0, 1, 2])
 def test_preparation_circuits(Lx, Ly, which, fuse):
     n = 2 * Lx * Ly
     print(f"case prep {Lx}x{Ly} which={which} fuse={fuse}", flush=True)
@@ -84,7 +84,7 @@ def test_preparation_circuits(Lx, Ly, which, fuse):
     assert np.abs(got[1 << n:]).max() == 0
 
 
-@pytest.mark.parametrize("fuse", [0, 1])
+@pytest.mark.parametrize("fuse", [0, 1, 2])
 def test_gate_level_ramp_equals_fused_trotter_path(fuse):
     """3x3, 12 steps of the ramp from psi_1 (prepared by the circuit of
     Eq. (ini1)): the gate-level run, the library's fused Trotter path and the
@@ -114,13 +114,14 @@ def test_gate_level_ramp_equals_fused_trotter_path(fuse):
 
 
 @pytest.mark.slow
-def test_gate_level_4x4_with_ancilla():
-    """33 qubits in complex64 (64 GiB), fused passes: two steps of the 4x4
-    ramp from psi_1 against the Trotter path (complex64) on 2^16 sampled
-    link amplitudes and the ancilla half on 2^16 samples."""
+@pytest.mark.parametrize("fuse", [1, 2])
+def test_gate_level_4x4_with_ancilla(fuse):
+    """33 qubits in complex64 (64 GiB), LDS or register gate groups: two
+    steps of the 4x4 ramp from psi_1 against the Trotter path (complex64) on
+    2^16 sampled link amplitudes and the ancilla half on 2^16 samples."""
     Lx, Ly, n, M, dt = 4, 4, 32, 200, 0.1
     c0, c1 = (0.5, 0.5, 0.0, 0.0), (0.5, 0.5, 0.4, 0.3)
-    print("case gate-level 4x4 + ancilla c64", flush=True)
+    print(f"case gate-level 4x4 + ancilla c64 fuse={fuse}", flush=True)
     torch.cuda.empty_cache()
     plan = z2h.z2h_plan_create(Lx, Ly, z2h.Z2H_C64)
     phi = z2h.alloc_state(plan)
@@ -128,7 +129,7 @@ def test_gate_level_4x4_with_ancilla():
     psi = torch.zeros(1 << (n + 1), dtype=torch.complex64, device="cuda")
     psi[: 1 << n].copy_(phi)
     ws = z2h.alloc_bytes(z2h.z2h_gates_ws_bytes(n + 1))
-    z2h.z2h_circuit_evolve(Lx, Ly, z2h.Z2H_C64, psi, ws, z2h.schedule(c0, c1, M, dt, k_end=2), fuse=1)
+    z2h.z2h_circuit_evolve(Lx, Ly, z2h.Z2H_C64, psi, ws, z2h.schedule(c0, c1, M, dt, k_end=2), fuse=fuse)
     sz = z2h.z2h_plan_sizes(plan)
     z2h.z2h_evolve(plan, phi, z2h.alloc_bytes(sz["ws_evolve"]), z2h.schedule(c0, c1, M, dt, k_end=2))
     torch.cuda.synchronize()
