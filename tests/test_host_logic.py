@@ -459,3 +459,27 @@ def test_gate_list_validation():
     code = z2h.lib().z2h_circuit_step(3, 3, ctypes.byref(z2h.couplings()), ctypes.byref(z2h.couplings()), 0.1, 0,
                                       None, 0, ctypes.byref(cnt))
     assert code == -6 and cnt.value == 522
+
+
+def test_exact_solver_workspace_checks():
+    """Lanczos and the Krylov evolution reject a workspace below the stated
+    size, and overlapping buffers, before any device work."""
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C128)
+    L = z2h.lib()
+    need = z2h.z2h_lanczos_sizes(plan, 40)
+    it, e0 = ctypes.c_int32(), ctypes.c_double()
+    H = z2h.couplings(0.5, 0.5, 0.2, 0.1)
+    v, ws = ctypes.c_void_p(1 << 40), ctypes.c_void_p((1 << 40) + (1 << 30))
+    code = L.z2h_lanczos_ground(plan.handle, v, ws, need - 256, ctypes.byref(H), 40, 1e-10, None, None,
+                                ctypes.byref(it), ctypes.byref(e0), None)
+    assert code == -6
+    code = L.z2h_lanczos_ground(plan.handle, v, ctypes.c_void_p((1 << 40) + 4096), need, ctypes.byref(H), 40, 1e-10,
+                                None, None, ctypes.byref(it), ctypes.byref(e0), None)
+    assert code == -1 and b"overlap" in L.z2h_last_error()
+    sched = z2h.schedule((0.5, 0.5, 0, 0), (0.5, 0.5, 0.3, 0.2), 10, 0.1)
+    err = ctypes.c_double()
+    need = z2h.z2h_exact_sizes(plan, 12)
+    code = L.z2h_exact_evolve(plan.handle, v, ws, need - 256, ctypes.byref(sched), 12, ctypes.byref(err), None)
+    assert code == -6
+    code = L.z2h_hamiltonian_apply(plan.handle, v, ctypes.c_void_p((1 << 40) + 256), ctypes.byref(H), None)
+    assert code == -1 and b"overlap" in L.z2h_last_error()
