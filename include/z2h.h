@@ -412,6 +412,28 @@ z2h_status z2h_exact_sizes(const z2h_plan *plan, int32_t krylov_dim, size_t *ws_
 z2h_status z2h_exact_evolve(const z2h_plan *plan, void *d_state, void *d_ws, size_t ws_bytes,
                             const z2h_schedule *sched, int32_t krylov_dim, double *err_est, void *stream);
 
+/*
+ * Ground-state vector from a finished z2h_lanczos_ground run: d_v must hold
+ * the same start vector that run began from (the recurrence is repeated with
+ * the same kernels, so it reproduces the same Lanczos vectors), and receives
+ * the unit-norm Ritz vector of the lowest eigenvalue of T, i.e.
+ * sum_k s_k v_k with s the eigenvector of T (inverse iteration on the host).
+ * h_alpha, h_beta, iters: that run's outputs.  energy (may be NULL) gets the
+ * Rayleigh quotient <v|H|v>, residual (may be NULL) the norm |H v - E v|;
+ * either costs one more application of H.  d_ws: z2h_lanczos_vector_sizes
+ * bytes (three state-sized vectors plus coefficients).  Synchronizes.
+ * Errors as z2h_lanczos_ground.
+ */
+z2h_status z2h_lanczos_vector_sizes(const z2h_plan *plan, int32_t iters, size_t *ws_bytes);
+z2h_status z2h_lanczos_vector(const z2h_plan *plan, void *d_v, void *d_ws, size_t ws_bytes, const z2h_couplings *H,
+                              const double *h_alpha, const double *h_beta, int32_t iters, double *energy,
+                              double *residual, void *stream);
+
+/* <a|b> of two states of the plan (FP64 reduction); d_ws: at least 32768
+ * bytes of device scratch.  Synchronizes. */
+z2h_status z2h_overlap(const z2h_plan *plan, const void *d_a, const void *d_b, void *d_ws, size_t ws_bytes,
+                       double *re, double *im, void *stream);
+
 /* Host-only helpers of the two solvers above, for a symmetric tridiagonal
  * matrix with diagonal alpha[0..m) and off-diagonal beta[0..m-1):
  * z2h_tridiag_lowest: its lowest eigenvalue (Sturm bisection);

@@ -111,6 +111,15 @@ def ground(Lx, Ly, c, k=1):
     return np.sort(vals)
 
 
+def ground_state(Lx, Ly, c):
+    """(E0, unit ground-state vector) by scipy's Lanczos (eigsh), for a
+    non-degenerate ground state; the vector's global phase is arbitrary."""
+    H = hamiltonian(Lx, Ly, c)
+    vals, vecs = spla.eigsh(H, k=1, which="SA", tol=1e-13)
+    v = vecs[:, 0].astype(np.complex128)
+    return float(vals[0]), v / np.linalg.norm(v)
+
+
 def exact_stepwise(Lx, Ly, psi0, c0, c1, M, dt, sampling=0):
     """prod_k expm(-i dt H(c(s_k))) psi0: the evolution the Trotter steps
     approximate, with the same per-step parameter values s_k (dense expm,

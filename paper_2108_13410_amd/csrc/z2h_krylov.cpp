@@ -76,7 +76,7 @@ size_t lanczos_carve(const Plan &P, int nvec, int ncoef, char *base, LanczosWs *
     LanczosWs tmp;
     memset(&tmp, 0, sizeof tmp);
     for (int i = 0; i < nvec; ++i) tmp.vec[i] = c.take(state_bytes(P));
-    tmp.apart = (double *)c.take(sizeof(double) * kHamWorkersMax);
+    tmp.apart = (double *)c.take(sizeof(double) * 2 * kVecBlocks);  // also the dot kernel's (Re, Im) pairs
     tmp.apart_x = (double *)c.take(sizeof(double) * kHamWorkersMax);
     tmp.wpart = (double *)c.take(sizeof(double) * kVecBlocks);
     tmp.coef = (LanczosCoef *)c.take(sizeof(LanczosCoef) * (size_t)ncoef);
@@ -241,11 +241,12 @@ double tridiag_lowest(const double *a, const double *b, int m) {
     return 0.5 * (lo + hi);
 }
 
-// exp(-i tau T) e_1 for the symmetric tridiagonal T (m <= kKrylovMax): cyclic
-// Jacobi rotations diagonalise T = Q diag(l) Q^T, then the result is
-// Q diag(exp(-i tau l)) Q^T e_1.
-void tridiag_expv(const double *a, const double *b, int m, double tau, std::complex<double> *out) {
-    std::vector<double> A((size_t)m * m, 0.0), Q((size_t)m * m, 0.0);
+// Eigen-decomposition of the symmetric tridiagonal T (diagonal a[0..m),
+// off-diagonal b[1..m)) by cyclic Jacobi rotations: T = Q diag(lam) Q^T,
+// Q row-major (column l is the eigenvector of lam[l]).
+void tridiag_eigs(const double *a, const double *b, int m, std::vector<double> &lam, std::vector<double> &Q) {
+    std::vector<double> A((size_t)m * m, 0.0);
+    Q.assign((size_t)m * m, 0.0);
     for (int i = 0; i < m; ++i) {
         A[(size_t)i * m + i] = a[i];
         if (i > 0) A[(size_t)i * m + i - 1] = A[(size_t)(i - 1) * m + i] = b[i];
@@ -286,13 +287,74 @@ void tridiag_expv(const double *a, const double *b, int m, double tau, std::comp
                 }
             }
     }
+    lam.resize((size_t)m);
+    for (int l = 0; l < m; ++l) lam[l] = A[(size_t)l * m + l];
+}
+
+// Eigenvector of the lowest eigenvalue theta of T (diagonal a[0..m),
+// off-diagonal b[1..m)) by inverse iteration: with the shift theta - delta
+// just below the spectrum, T - shift is positive definite, so each solve is
+// a stable LDL^T (Thomas) elimination.  The result has unit norm.
+void tridiag_lowest_vector(const double *a, const double *b, int m, double theta, std::vector<double> &x) {
+    double scale = 0.0;
+    for (int i = 0; i < m; ++i) scale = std::max(scale, std::fabs(a[i]) + (i > 0 ? std::fabs(b[i]) : 0.0));
+    const double shift = theta - 1e-10 * std::max(1.0, scale);
+    x.assign((size_t)m, 1.0 / std::sqrt((double)m));
+    std::vector<double> d((size_t)m), l((size_t)m), z((size_t)m);
+    for (int it = 0; it < 4; ++it) {
+        // factor (T - shift) = L D L^T and solve L D L^T x' = x
+        d[0] = a[0] - shift;
+        z[0] = x[0];
+        for (int i = 1; i < m; ++i) {
+            l[i] = b[i] / d[i - 1];
+            d[i] = a[i] - shift - l[i] * b[i];
+            z[i] = x[i] - l[i] * z[i - 1];
+        }
+        x[m - 1] = z[m - 1] / d[m - 1];
+        for (int i = m - 2; i >= 0; --i) x[i] = z[i] / d[i] - l[i + 1] * x[i + 1];
+        double nrm = 0.0;
+        for (int i = 0; i < m; ++i) nrm += x[i] * x[i];
+        nrm = std::sqrt(nrm);
+        for (int i = 0; i < m; ++i) x[i] /= nrm;
+    }
+}
+
+// exp(-i tau T) e_1 = Q diag(exp(-i tau lam)) Q^T e_1 (m <= kKrylovMax).
+void tridiag_expv(const double *a, const double *b, int m, double tau, std::complex<double> *out) {
+    std::vector<double> lam, Q;
+    tridiag_eigs(a, b, m, lam, Q);
     for (int j = 0; j < m; ++j) out[j] = 0.0;
     for (int l = 0; l < m; ++l) {
-        const double lam = A[(size_t)l * m + l];
-        const std::complex<double> ph(std::cos(tau * lam), -std::sin(tau * lam));
+        const std::complex<double> ph(std::cos(tau * lam[l]), -std::sin(tau * lam[l]));
         const double w = Q[(size_t)0 * m + l];
         for (int j = 0; j < m; ++j) out[j] += Q[(size_t)j * m + l] * w * ph;
     }
+}
+
+// Sum of the dot kernel's per-block partials (fixed order): (Re, Im) in
+// mode 0, the squared norm in mode 1.
+z2h_status dot_host(const Plan &P, const void *x, const void *y, double theta, int mode, double *part, double out[2],
+                    hipStream_t s) {
+    DotArgs d;
+    memset(&d, 0, sizeof d);
+    d.a = x;
+    d.b = y;
+    d.theta = theta;
+    d.mode = mode;
+    d.nelem = 1ull << P.n;
+    d.part = part;
+    const unsigned nb = vec_blocks(P);
+    hipError_t e = launch_dot(P.c128, d, nb, s);
+    if (e != hipSuccess) return fail(Z2H_ERR_HIP, "dot kernel failed: %s", hipGetErrorString(e));
+    std::vector<double> h(2 * (size_t)nb);
+    HIP_TRY(hipMemcpyAsync(h.data(), part, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    out[0] = out[1] = 0.0;
+    for (unsigned i = 0; i < nb; ++i) {
+        out[0] += h[2 * i];
+        out[1] += h[2 * i + 1];
+    }
+    return Z2H_OK;
 }
 
 double sched_s_host(const z2h_schedule &S, int64_t k) {
@@ -476,6 +538,112 @@ z2h_status z2h_exact_evolve(const z2h_plan *plan, void *d_state, void *d_ws, siz
         return Z2H_OK;
     } catch (...) {
         return fail(Z2H_ERR_OOM, "exception in z2h_exact_evolve");
+    }
+}
+
+z2h_status z2h_lanczos_vector_sizes(const z2h_plan *plan, int32_t iters, size_t *ws_bytes) {
+    if (!plan || !ws_bytes) return fail(Z2H_ERR_INVALID, "plan or ws_bytes is NULL");
+    if (iters < 1 || iters > 4096) return fail(Z2H_ERR_INVALID, "iters %d out of [1, 4096]", iters);
+    *ws_bytes = lanczos_carve(plan->P, 3, iters + 2, nullptr, nullptr);
+    return Z2H_OK;
+}
+
+z2h_status z2h_lanczos_vector(const z2h_plan *plan, void *d_v, void *d_ws, size_t ws_bytes, const z2h_couplings *H,
+                              const double *h_alpha, const double *h_beta, int32_t iters, double *energy,
+                              double *residual, void *stream) {
+    try {
+        if (!plan) return fail(Z2H_ERR_INVALID, "plan is NULL");
+        const Plan &P = plan->P;
+        if (!H || !finite4(*H)) return fail(Z2H_ERR_INVALID, "couplings NULL or not finite");
+        if (iters < 1 || iters > 4096) return fail(Z2H_ERR_INVALID, "iters %d out of [1, 4096]", iters);
+        if (!h_alpha || (iters > 1 && !h_beta)) return fail(Z2H_ERR_INVALID, "alpha or beta is NULL");
+        z2h_status st = validate_state_ptr(d_v, "d_v");
+        if (st) return st;
+        if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(Z2H_ERR_INVALID, "d_ws NULL or not 256-byte aligned");
+        const size_t need = lanczos_carve(P, 3, iters + 2, nullptr, nullptr);
+        if (ws_bytes < need) return fail(Z2H_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+        if ((st = check_pair(d_v, state_bytes(P), d_ws, ws_bytes, "d_v", "d_ws"))) return st;
+        for (int i = 0; i < iters; ++i)
+            if (!std::isfinite(h_alpha[i]) || (i + 1 < iters && !std::isfinite(h_beta[i])))
+                return fail(Z2H_ERR_INVALID, "coefficient %d not finite", i);
+        if ((st = check_device_(P))) return st;
+        // lowest eigenpair of T
+        std::vector<double> b((size_t)iters + 1, 0.0), sv;
+        for (int i = 1; i < iters; ++i) b[i] = h_beta[i - 1];
+        const double theta = tridiag_lowest(h_alpha, b.data(), iters);
+        tridiag_lowest_vector(h_alpha, b.data(), iters, theta, sv);
+        hipStream_t s = (hipStream_t)stream;
+        LanczosWs L;
+        lanczos_carve(P, 3, iters + 2, (char *)d_ws, &L);
+        void *u = d_v, *p = L.vec[0], *y = L.vec[1], *g = L.vec[2];
+        // the same recurrence again (same kernels, so the same vectors),
+        // accumulating g = sum_k s_k v_k
+        if ((st = norm_start(P, u, L, s))) return st;
+        const unsigned nb = vec_blocks(P);
+        for (int k = 0; k < iters; ++k) {
+            AccArgs a;
+            memset(&a, 0, sizeof a);
+            a.g = g;
+            a.u = u;
+            a.coef = L.coef;
+            a.s = sv[k];
+            a.k = k;
+            a.first = k == 0;
+            a.nelem = 1ull << P.n;
+            hipError_t e = launch_acc(P.c128, a, nb, s);
+            if (e != hipSuccess) return fail(Z2H_ERR_HIP, "Ritz accumulation failed: %s", hipGetErrorString(e));
+            if (k + 1 < iters) {
+                if ((st = lanczos_iter(P, *H, k, u, p, p, y, L, s))) return st;
+                std::swap(u, p);
+            }
+        }
+        double nn[2];
+        if ((st = dot_host(P, g, g, 0.0, 0, L.apart, nn, s))) return st;
+        if (!(nn[0] > 0.0) || !std::isfinite(nn[0])) return fail(Z2H_ERR_NUMERIC, "Ritz vector norm %g", nn[0]);
+        CombineArgs c;
+        memset(&c, 0, sizeof c);
+        c.psi = d_v;
+        c.u[0] = g;
+        c.cre[0] = 1.0 / std::sqrt(nn[0]);
+        c.m = 1;
+        c.nelem = 1ull << P.n;
+        hipError_t e = launch_combine(P.c128, c, nb, s);
+        if (e != hipSuccess) return fail(Z2H_ERR_HIP, "normalisation failed: %s", hipGetErrorString(e));
+        double rq = theta;
+        if (energy || residual) {
+            if ((st = ham_passes(P, d_v, y, *H, nullptr, nullptr, s))) return st;
+            double hv[2], rr[2];
+            if ((st = dot_host(P, d_v, y, 0.0, 0, L.apart, hv, s))) return st;
+            rq = hv[0];
+            if ((st = dot_host(P, y, d_v, rq, 1, L.apart, rr, s))) return st;
+            if (residual) *residual = std::sqrt(rr[0]);
+        }
+        if (energy) *energy = rq;
+        return Z2H_OK;
+    } catch (...) {
+        return fail(Z2H_ERR_OOM, "exception in z2h_lanczos_vector");
+    }
+}
+
+z2h_status z2h_overlap(const z2h_plan *plan, const void *d_a, const void *d_b, void *d_ws, size_t ws_bytes,
+                       double *re, double *im, void *stream) {
+    try {
+        if (!plan) return fail(Z2H_ERR_INVALID, "plan is NULL");
+        if (!re || !im) return fail(Z2H_ERR_INVALID, "re or im is NULL");
+        z2h_status st = validate_state_ptr(d_a, "d_a");
+        if (!st) st = validate_state_ptr(d_b, "d_b");
+        if (st) return st;
+        if (!d_ws || ((uintptr_t)d_ws & 255)) return fail(Z2H_ERR_INVALID, "d_ws NULL or not 256-byte aligned");
+        if (ws_bytes < sizeof(double) * 2 * kVecBlocks)
+            return fail(Z2H_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, sizeof(double) * 2 * kVecBlocks);
+        if ((st = check_device_(plan->P))) return st;
+        double o[2];
+        if ((st = dot_host(plan->P, d_a, d_b, 0.0, 0, (double *)d_ws, o, (hipStream_t)stream))) return st;
+        *re = o[0];
+        *im = o[1];
+        return Z2H_OK;
+    } catch (...) {
+        return fail(Z2H_ERR_OOM, "exception in z2h_overlap");
     }
 }
 

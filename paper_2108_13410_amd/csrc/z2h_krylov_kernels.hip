@@ -319,6 +319,49 @@ __global__ void __launch_bounds__(256) combine_kernel(CombineArgs a) {
     }
 }
 
+template <typename Real>
+__global__ void __launch_bounds__(256) acc_kernel(AccArgs a) {
+    Cx<Real> *g = reinterpret_cast<Cx<Real> *>(a.g);
+    const Cx<Real> *u = reinterpret_cast<const Cx<Real> *>(a.u);
+    const double c = a.s * a.coef[a.k].sigma;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.nelem; i += stride) {
+        const Cx<Real> e = u[i];
+        double re = c * (double)e.x, im = c * (double)e.y;
+        if (!a.first) {
+            const Cx<Real> o = g[i];
+            re += (double)o.x;
+            im += (double)o.y;
+        }
+        g[i] = Cx<Real>{(Real)re, (Real)im};
+    }
+}
+
+template <typename Real>
+__global__ void __launch_bounds__(256) dot_kernel(DotArgs a) {
+    __shared__ double red[8];
+    const Cx<Real> *x = reinterpret_cast<const Cx<Real> *>(a.a);
+    const Cx<Real> *y = reinterpret_cast<const Cx<Real> *>(a.b);
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    double s0 = 0.0, s1 = 0.0;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.nelem; i += stride) {
+        const Cx<Real> p = x[i], q = y[i];
+        if (a.mode == 0) {  // conj(p) q
+            s0 += (double)p.x * (double)q.x + (double)p.y * (double)q.y;
+            s1 += (double)p.x * (double)q.y - (double)p.y * (double)q.x;
+        } else {
+            const double dr = (double)p.x - a.theta * (double)q.x, di = (double)p.y - a.theta * (double)q.y;
+            s0 += dr * dr + di * di;
+        }
+    }
+    const double r0 = block_sum(s0, red);
+    const double r1 = block_sum(s1, red);
+    if (threadIdx.x == 0) {
+        a.part[2 * blockIdx.x] = r0;
+        a.part[2 * blockIdx.x + 1] = r1;
+    }
+}
+
 // ---------------------------------------------------------------- launchers
 
 static std::mutex g_krylov_lds_mu;
@@ -381,6 +424,22 @@ hipError_t launch_vec(bool c128, const VecArgs &a, unsigned blocks, hipStream_t 
 
 hipError_t launch_scalar(const ScalarArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(scalar_kernel, dim3(1), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_acc(bool c128, const AccArgs &a, unsigned blocks, hipStream_t s) {
+    if (c128)
+        hipLaunchKernelGGL(acc_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(acc_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dot(bool c128, const DotArgs &a, unsigned blocks, hipStream_t s) {
+    if (c128)
+        hipLaunchKernelGGL(dot_kernel<double>, dim3(blocks), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(dot_kernel<float>, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

@@ -88,6 +88,26 @@ struct CombineArgs {
     uint64_t nelem;
 };
 
+// Ritz-vector accumulation: g = (first ? 0 : g) + s * coef[k].sigma * u.
+struct AccArgs {
+    void *g;
+    const void *u;
+    const LanczosCoef *coef;
+    double s;
+    int32_t k, first;
+    uint64_t nelem;
+};
+
+// Per-block partials of either Re<a, b> and Im<a, b> (mode 0; two doubles
+// per block) or |a - theta b|^2 (mode 1).
+struct DotArgs {
+    const void *a, *b;
+    double theta;
+    int32_t mode, pad;
+    uint64_t nelem;
+    double *part;
+};
+
 constexpr int kVecBlocks = 2048;   // blocks of the elementwise Lanczos kernels
 constexpr int kHamWorkersMax = 2048;
 
@@ -95,6 +115,8 @@ hipError_t launch_ham(bool c128, int R, const HamArgs &a, unsigned workers, size
 hipError_t launch_vec(bool c128, const VecArgs &a, unsigned blocks, hipStream_t s);
 hipError_t launch_scalar(const ScalarArgs &a, hipStream_t s);
 hipError_t launch_combine(bool c128, const CombineArgs &a, unsigned blocks, hipStream_t s);
+hipError_t launch_acc(bool c128, const AccArgs &a, unsigned blocks, hipStream_t s);
+hipError_t launch_dot(bool c128, const DotArgs &a, unsigned blocks, hipStream_t s);
 
 // ---- gate-level circuit emulation
 

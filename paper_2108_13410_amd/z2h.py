@@ -121,6 +121,10 @@ SIGNATURES = {
                                   ctypes.POINTER(_i32), ctypes.POINTER(_dbl), _P]),
     "z2h_exact_sizes": (_i32, [_P, _i32, ctypes.POINTER(_sz)]),
     "z2h_exact_evolve": (_i32, [_P, _P, _P, _sz, ctypes.POINTER(z2h_schedule), _i32, ctypes.POINTER(_dbl), _P]),
+    "z2h_lanczos_vector_sizes": (_i32, [_P, _i32, ctypes.POINTER(_sz)]),
+    "z2h_lanczos_vector": (_i32, [_P, _P, _P, _sz, ctypes.POINTER(z2h_couplings), _P, _P, _i32,
+                                  ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _P]),
+    "z2h_overlap": (_i32, [_P, _P, _P, _P, _sz, ctypes.POINTER(_dbl), ctypes.POINTER(_dbl), _P]),
     "z2h_tridiag_lowest": (_i32, [_i32, _P, _P, ctypes.POINTER(_dbl)]),
     "z2h_tridiag_expv": (_i32, [_i32, _P, _P, _dbl, _P, _P]),
     "z2h_circuit_step": (_i32, [_i32, _i32, ctypes.POINTER(z2h_couplings), ctypes.POINTER(z2h_couplings), _dbl, _i32,
@@ -380,6 +384,33 @@ def z2h_lanczos_ground(plan, v, ws, H, max_iter=300, tol=1e-13, stream=None):
                                     ctypes.byref(Hc), int(max_iter), float(tol), a.ctypes.data_as(_P),
                                     b.ctypes.data_as(_P), ctypes.byref(it), ctypes.byref(e0), _stream(stream)))
     return e0.value, it.value, a[:it.value].copy(), b[:it.value].copy()
+
+
+def z2h_lanczos_vector(plan, v, H, alpha, beta, stream=None):
+    """Ground-state vector into v (which must hold the start vector of the
+    z2h_lanczos_ground run that produced alpha, beta).  Returns (energy,
+    residual)."""
+    import numpy as np
+    Hc = H if isinstance(H, z2h_couplings) else couplings(*H)
+    a = np.ascontiguousarray(alpha, dtype=np.float64)
+    b = np.ascontiguousarray(beta, dtype=np.float64)
+    n = ctypes.c_size_t()
+    _check(lib().z2h_lanczos_vector_sizes(plan.handle, len(a), ctypes.byref(n)))
+    ws = alloc_bytes(n.value, device=v.device)
+    e, r = ctypes.c_double(), ctypes.c_double()
+    _check(lib().z2h_lanczos_vector(plan.handle, _ptr(v), _ptr(ws), n.value, ctypes.byref(Hc), a.ctypes.data_as(_P),
+                                    b.ctypes.data_as(_P), len(a), ctypes.byref(e), ctypes.byref(r), _stream(stream)))
+    del ws
+    return e.value, r.value
+
+
+def z2h_overlap(plan, a, b, stream=None):
+    """<a|b> as a Python complex."""
+    ws = alloc_bytes(32768, device=a.device)
+    re, im = ctypes.c_double(), ctypes.c_double()
+    _check(lib().z2h_overlap(plan.handle, _ptr(a), _ptr(b), _ptr(ws), 32768, ctypes.byref(re), ctypes.byref(im),
+                             _stream(stream)))
+    return complex(re.value, im.value)
 
 
 def z2h_exact_sizes(plan, krylov_dim):

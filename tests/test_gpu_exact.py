@@ -232,3 +232,90 @@ def test_trotter_distance_to_exact_is_second_order():
     print("Trotter distance to exact at M = 20, 40, 80:", dist, flush=True)
     assert 3.7 < dist[0] / dist[1] < 4.3
     assert 3.85 < dist[1] / dist[2] < 4.15
+
+
+def test_lanczos_vector_against_ed():
+    """3x3 ground state at a gapped point (0.5, 0.5, 0.3, 0.2): the repeated
+    recurrence's Ritz vector against the oracle's eigenvector (fidelity
+    1 - 1e-10), its Rayleigh quotient against the ED energy (1e-10) and its
+    residual |Hv - Ev|; z2h_overlap of the vector with itself is 1."""
+    c = (0.5, 0.5, 0.3, 0.2)
+    print("case Lanczos vector 3x3", flush=True)
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C128)
+    v = z2h.alloc_state(plan)
+    z2h.z2h_state_init(plan, v, z2h.Z2H_INIT_PLUS)
+    ws = z2h.alloc_bytes(z2h.z2h_lanczos_sizes(plan, 300))
+    e0, it, a, b = z2h.z2h_lanczos_ground(plan, v, ws, c, max_iter=300, tol=1e-13)
+    del ws
+    z2h.z2h_state_init(plan, v, z2h.Z2H_INIT_PLUS)
+    E, res = z2h.z2h_lanczos_vector(plan, v, c, a, b)
+    E_or, g_or = ed.ground_state(3, 3, c)
+    g = to_oracle_order(3, 3, v.cpu().numpy())
+    fid = abs(np.vdot(g_or, g)) ** 2
+    print(f"3x3 E {E:.12f} (ED {E_or:.12f}), residual {res:.2e}, fidelity 1 - {1 - fid:.2e}, {it} it", flush=True)
+    assert abs(E - E_or) < 1e-10 and abs(e0 - E_or) < 1e-9
+    assert res < 1e-6
+    assert fid > 1 - 1e-10
+    assert abs(z2h.z2h_overlap(plan, v, v) - 1) < 1e-12
+
+
+def test_adiabatic_fidelity_3x3():
+    """psi_1 ramped to (0.5, 0.5, 0.3, 0.2) (T = 20, M = 1000, complex128):
+    the fidelity |<g|psi_T>|^2 with the ground state there, all on the GPU
+    (Trotter path, Lanczos vector, overlap), equals the oracle's (Trotter
+    evolution, ED eigenvector) within 1e-9."""
+    c0, c1, M, T = (0.5, 0.5, 0.0, 0.0), (0.5, 0.5, 0.3, 0.2), 1000, 20.0
+    print("case adiabatic fidelity 3x3", flush=True)
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C128)
+    g = z2h.alloc_state(plan)
+    z2h.z2h_state_init(plan, g, z2h.Z2H_INIT_PLUS)
+    ws = z2h.alloc_bytes(z2h.z2h_lanczos_sizes(plan, 300))
+    _, _, a, b = z2h.z2h_lanczos_ground(plan, g, ws, c1, max_iter=300, tol=1e-13)
+    z2h.z2h_state_init(plan, g, z2h.Z2H_INIT_PLUS)
+    z2h.z2h_lanczos_vector(plan, g, c1, a, b)
+    psi = z2h.alloc_state(plan)
+    z2h.z2h_state_init(plan, psi, z2h.Z2H_INIT_PSI1)
+    sz = z2h.z2h_plan_sizes(plan)
+    z2h.z2h_evolve(plan, psi, z2h.alloc_bytes(sz["ws_evolve"]), z2h.schedule(c0, c1, M, T / M))
+    F = abs(z2h.z2h_overlap(plan, g, psi)) ** 2
+    ref = oracle.init_psi1(3, 3)
+    oracle.evolve(3, 3, ref, c0, c1, M, T / M)
+    _, g_or = ed.ground_state(3, 3, c1)
+    F_or = abs(np.vdot(g_or, ref)) ** 2
+    print(f"3x3 adiabatic fidelity {F:.12f} (oracle {F_or:.12f})", flush=True)
+    assert abs(F - F_or) < 1e-9
+
+
+@pytest.mark.slow
+def test_lanczos_vector_4x4_and_adiabatic_fidelity():
+    """4x4, complex64 (start vector plus three work vectors: 128 GiB): the
+    ground state at the 4x4 ramp's end point (1, 1, 0.25, 0.25); its
+    residual and Rayleigh quotient, then the fidelity of the Trotterized
+    ramp (T = 20, M = 200, psi_1) with it."""
+    from paper_2108_13410_amd import workloads
+    job = workloads.point_4x4()
+    c1 = job["c1"]
+    print("case Lanczos vector 4x4 c64", flush=True)
+    torch.cuda.empty_cache()
+    plan = z2h.z2h_plan_create(4, 4, z2h.Z2H_C64)
+    g = z2h.alloc_state(plan)
+    z2h.z2h_state_init(plan, g, z2h.Z2H_INIT_PLUS)
+    ws = z2h.alloc_bytes(z2h.z2h_lanczos_sizes(plan, 160))
+    e0, it, a, b = z2h.z2h_lanczos_ground(plan, g, ws, c1, max_iter=160, tol=1e-9)
+    del ws
+    torch.cuda.empty_cache()
+    z2h.z2h_state_init(plan, g, z2h.Z2H_INIT_PLUS)
+    E, res = z2h.z2h_lanczos_vector(plan, g, c1, a, b)
+    torch.cuda.empty_cache()
+    psi = z2h.alloc_state(plan)
+    z2h.z2h_state_init(plan, psi, z2h.Z2H_INIT_PSI1)
+    sz = z2h.z2h_plan_sizes(plan)
+    z2h.z2h_evolve(plan, psi, z2h.alloc_bytes(sz["ws_evolve"]),
+                   z2h.schedule(job["c0"], c1, job["M"], job["T"] / job["M"], renorm=1))
+    F = abs(z2h.z2h_overlap(plan, g, psi)) ** 2
+    print(f"4x4 E0 {e0:.8f} ({it} it), Ritz {E:.8f}, residual {res:.2e}, adiabatic fidelity {F:.8f}", flush=True)
+    assert abs(E - e0) < 1e-5 * abs(e0)
+    assert res < 1e-3
+    assert 0.0 < F <= 1.0 + 1e-5
+    del g, psi
+    torch.cuda.empty_cache()

@@ -314,6 +314,20 @@ def test_hamiltonian_rows_equal_sparse_matrix():
         assert np.abs(got - ref).max() < 1e-13
 
 
+def test_ground_state_vector_product_form():
+    """JA = JB = 0: the ground state is the product over links of the lowest
+    eigenvector of -hx X - hz Z (amplitudes alpha^(n-w) beta^w)."""
+    Lx, Ly, n = 2, 3, 12
+    hx, hz = 0.3, 0.4
+    E0, v = ed.ground_state(Lx, Ly, (0.0, 0.0, hx, hz))
+    w1, u1 = np.linalg.eigh(-hx * SX.real - hz * SZ.real)
+    assert abs(E0 - n * w1[0]) < 1e-10
+    a, b = u1[:, 0]
+    w = np.array([bin(i).count("1") for i in range(1 << n)])
+    ref = a ** (n - w) * b ** w
+    assert abs(abs(np.vdot(ref, v)) - 1) < 1e-10
+
+
 def test_sparse_exact_stepwise_equals_dense():
     """The sparse exact evolution (expm_multiply) and the dense one (expm)
     are two algorithms for the same product of exponentials."""
