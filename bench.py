@@ -287,6 +287,26 @@ def paper_protocol(z2h, torch):
             "traces": "observables every 100 steps (every 1e-3 in g)"}
 
 
+def dos_leg(z2h, torch):
+    """Figs. dos_sec and dos_dual (Sec. V) on the 3x3 torus, complex128, paper
+    protocol: the distribution of |psi|^2 over Ztilde = 2w - n on the red
+    paths (r = 0.01 .. 0.19, run together) at g = 0.19, and on the dual line
+    at g = 0.65 and 0.30, with the maxima of each (peaks of at least 1 % of
+    the largest bin; "interior" leaves out the ends of the occupied range)."""
+    from paper_2108_13410_amd import protocols as pr
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C128)
+    t0 = time.perf_counter()
+    red, dual = pr.dos_study(z2h, plan)
+    el = time.perf_counter() - t0
+    n = plan.n
+    row = lambda d: {"maxima_at_Ztilde": pr.dos_maxima(d, n), "interior_maxima": pr.dos_maxima(d, n, True),
+                     "dos": [round(float(x), 6) for x in d]}
+    return {"seconds": el, "red_g0.19": {str(r): row(d) for r, d in red.items()},
+            "dual_line": {str(g): row(d) for g, d in dual.items()},
+            "paper": "single maximum for r < 0.16 (Fig. dos_sec); on the dual line two maxima at g = 0.30 with "
+                     "one at Ztilde = -10, one maximum at g = 0.65 (Fig. dos_dual)"}
+
+
 def refinement_leg(z2h, torch, ns=(10, 200, 500, 800)):
     """Table contrast_tab (Sec. VI): the red path to R(0.5, 0.05) and on to
     R'(0, 0.05) with dg = 1e-4/n and dt = 0.2/n per step, n = 10 (the
@@ -541,6 +561,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint and mixed-batch legs")
     ap.add_argument("--no-exact", action="store_true", help="skip the exact-solver leg (Lanczos, Krylov)")
     ap.add_argument("--no-circuit", action="store_true", help="skip the gate-level circuit leg")
+    ap.add_argument("--dos", action="store_true", help="add the Ztilde distributions of Figs. dos_sec, dos_dual")
     ap.add_argument("--refinement", action="store_true",
                     help="add Table contrast_tab's refinement study (1.6e7 Trotter steps, a few minutes)")
     ap.add_argument("--circuit-4x4", action="store_true", help="add the 33-qubit gate-level step (about 10 s)")
@@ -694,6 +715,13 @@ def main():
     if not args.no_protocol:
         line["paper_protocol"] = paper_protocol(z2h, torch)
         print(f"paper protocol: {line['paper_protocol']['trotter_steps_per_s']:.0f} steps/s", file=sys.stderr, flush=True)
+    if args.dos:
+        line["dos"] = dos_leg(z2h, torch)
+        for r, v in line["dos"]["red_g0.19"].items():
+            print(f"dos red r={r} g=0.19: maxima at Ztilde {v['maxima_at_Ztilde']} (interior {v['interior_maxima']})",
+                  file=sys.stderr, flush=True)
+        for g, v in line["dos"]["dual_line"].items():
+            print(f"dos dual line g={g}: maxima at Ztilde {v['maxima_at_Ztilde']}", file=sys.stderr, flush=True)
     if args.refinement:
         line["refinement"] = refinement_leg(z2h, torch)
         for r in line["refinement"]["rows"]:

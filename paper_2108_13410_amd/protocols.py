@@ -16,6 +16,8 @@ taken at the end of each step.
   refined_red_path    the red path with n times finer steps (Sec. VI,
                       Table contrast_tab), and refinement_metrics for the
                       table's delta_n and alpha_n.
+  dos_study           the Ztilde distributions of Figs. dos_sec and
+                      dos_dual, and dos_maxima to count their maxima.
 """
 from __future__ import annotations
 
@@ -74,6 +76,52 @@ def refinement_metrics(E_ref, E_n):
     (1-norm), alpha_n = its maximum."""
     d = np.abs(np.asarray(E_ref, float) - np.asarray(E_n, float))
     return float(d.sum()), float(d.max())
+
+
+def dos_maxima(dos, n, interior=False, rel=0.01):
+    """Ztilde = 2w - n of the local maxima of a weight distribution dos[w]
+    (w = 0..n) over the weights it occupies, counting only peaks of at least
+    rel times the largest entry; interior=True leaves out the two end points
+    of the occupied range."""
+    d = [float(x) for x in dos[: n + 1]]
+    top = max(d)
+    occ = [w for w in range(n + 1) if d[w] > 1e-12]
+    out = []
+    for i, w in enumerate(occ):
+        left = d[occ[i - 1]] if i > 0 else -1.0
+        right = d[occ[i + 1]] if i + 1 < len(occ) else -1.0
+        if d[w] > left and d[w] > right and d[w] >= rel * top:
+            if interior and (i == 0 or i == len(occ) - 1):
+                continue
+            out.append(2 * w - n)
+    return out
+
+
+def dos_study(z2h, plan, rs=None, dual_q=0.7, dual_g=(0.65, 0.30), every=1000):
+    """Figs. dos_sec and dos_dual (Sec. V) on the plan's lattice: red paths
+    P(0.5, 0) -> R(0.5, r) -> R'(0, r) for each r, run together and read at
+    g = 0.19 on the last leg; the dual line (0, 0) -> (0, q) -> (q, q) -> O
+    read at the g values given.  Returns ({r: dos}, {g: dos}), dos[w] = weight
+    of Hamming weight w (Ztilde = 2w - n)."""
+    n = plan.n
+    rs = rs or [round(0.01 * k, 2) for k in range(1, 20)]
+    paths = []
+    for r in rs:
+        _, verts, steps = red_path(0.5, r)
+        paths.append(z2h.make_path(verts, steps, DT, sampling=1, every=every))
+    _, tr = z2h.z2h_paths_evolve(plan, paths)
+    tr = tr.cpu().numpy()
+    per = int(round(0.01 / DG)) // every if every else 0   # samples per 0.01 in g
+    last = steps[-1] // every                              # samples on the last leg (g from 0.5 to 0)
+    k = int(round((0.5 - 0.19) / 0.01)) * per - 1
+    red = {r: tr[-last + k, j, 22:23 + n] for j, r in enumerate(rs)}
+    _, dverts, dsteps = dual_path(dual_q)
+    _, dtr = z2h.z2h_paths_evolve(plan, [z2h.make_path(dverts, dsteps, DT, sampling=1, every=every)],
+                                  inits=[z2h.Z2H_INIT_PSI1P])
+    dtr = dtr.cpu().numpy()
+    dlast = dsteps[-1] // every
+    dual = {g: dtr[-dlast + int(round((dual_q - g) / 0.01)) * per - 1, 0, 22:23 + n] for g in dual_g}
+    return red, dual
 
 
 def second_derivative(x, E, w=10):

@@ -105,3 +105,33 @@ def test_topo_energies(engine):
     assert abs(res[(0.5, "E'")][1] - G["topo_p050_Eprime"]) < 3e-4
     print("blue paths:", {f"{k[0]} {k[1]}": (round(v[0], 6), round(v[1], 6)) for k, v in res.items()},
           "paper E' at p=0.12:", G["topo_p012_Eprime"], flush=True)
+
+
+@pytest.mark.slow
+def test_dos_maxima():
+    """Figs. dos_sec and dos_dual (tests/golden/dos_claims.txt): on the red
+    paths at g = 0.19 the Ztilde distribution has a single interior maximum
+    for r < 0.16 and more from r = 0.16 on; on the dual line it has two
+    maxima at g = 0.30 (one at Ztilde = -10) and one at g = 0.65 (peaks of
+    at least 1 % of the largest bin)."""
+    claims = {}
+    for line in open(os.path.join(HERE, "golden", "dos_claims.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, v = line.split()
+            claims[k] = float(v)
+    print("case DOS of Ztilde, red paths and dual line", flush=True)
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C128)
+    red, dual = pr.dos_study(plan=plan, z2h=z2h, dual_g=(claims["dual_g2"], claims["dual_g1"]))
+    n = plan.n
+    for r, d in red.items():
+        k = len(pr.dos_maxima(d, n, interior=True))
+        print(f"r = {r}: interior maxima at {pr.dos_maxima(d, n, interior=True)}", flush=True)
+        if r < claims["red_single_max_below_r"] - 1e-9:
+            assert k == 1, (r, k)
+        else:
+            assert k >= 2, (r, k)
+    g1 = pr.dos_maxima(dual[claims["dual_g1"]], n)
+    g2 = pr.dos_maxima(dual[claims["dual_g2"]], n)
+    print(f"dual line: g = {claims['dual_g1']}: {g1}; g = {claims['dual_g2']}: {g2}", flush=True)
+    assert len(g1) == claims["dual_g1_maxima"] and int(claims["dual_g1_max_at"]) in g1
+    assert len(g2) == claims["dual_g2_maxima"]
