@@ -307,6 +307,34 @@ def dos_leg(z2h, torch):
                      "one at Ztilde = -10, one maximum at g = 0.65 (Fig. dos_dual)"}
 
 
+def blue_leg(z2h, torch, ps=(0.36, 0.32, 0.28, 0.24)):
+    """Fig. 3maxima (Sec. V): psi_1 along the g axis to P(p, 0), then the blue
+    line to P'(0, p), for four p, run together (3x3, complex128, paper
+    protocol, energies every 100 steps).  On the blue leg, d2E/dg2 from
+    local quadratic fits; its largest and smallest values and all its local
+    extrema, beside the dual point lambda = p/2."""
+    import numpy as np
+    from paper_2108_13410_amd import protocols as pr
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C128)
+    paths = []
+    for p in ps:
+        _, verts, steps = pr.topo_paths(p)["E"]
+        paths.append(z2h.make_path(verts, steps, pr.DT, sampling=1, every=100))
+    t0 = time.perf_counter()
+    _, tr = z2h.z2h_paths_evolve(plan, paths)
+    tr = tr.cpu().numpy()
+    el = time.perf_counter() - t0
+    out = {}
+    for j, p in enumerate(ps):
+        nb = paths[j].steps[1] // 100
+        lam = np.linspace(0, p, nb + 1)
+        x, d2 = pr.second_derivative(lam, tr[-nb - 1:, j, 1], 10)
+        ext = [round(float(x[i]), 3) for i in range(1, len(d2) - 1) if (d2[i] - d2[i - 1]) * (d2[i + 1] - d2[i]) < 0]
+        out[str(p)] = {"dual_point_lambda": p / 2, "d2_max_at": float(x[np.argmax(d2)]),
+                       "d2_min_at": float(x[np.argmin(d2)]), "local_extrema_at": ext}
+    return {"seconds": el, "paths": out}
+
+
 def refinement_leg(z2h, torch, ns=(10, 200, 500, 800)):
     """Table contrast_tab (Sec. VI): the red path to R(0.5, 0.05) and on to
     R'(0, 0.05) with dg = 1e-4/n and dt = 0.2/n per step, n = 10 (the
@@ -562,6 +590,7 @@ def main():
     ap.add_argument("--no-exact", action="store_true", help="skip the exact-solver leg (Lanczos, Krylov)")
     ap.add_argument("--no-circuit", action="store_true", help="skip the gate-level circuit leg")
     ap.add_argument("--dos", action="store_true", help="add the Ztilde distributions of Figs. dos_sec, dos_dual")
+    ap.add_argument("--blue", action="store_true", help="add the blue paths of Fig. 3maxima")
     ap.add_argument("--refinement", action="store_true",
                     help="add Table contrast_tab's refinement study (1.6e7 Trotter steps, a few minutes)")
     ap.add_argument("--circuit-4x4", action="store_true", help="add the 33-qubit gate-level step (about 10 s)")
@@ -722,6 +751,11 @@ def main():
                   file=sys.stderr, flush=True)
         for g, v in line["dos"]["dual_line"].items():
             print(f"dos dual line g={g}: maxima at Ztilde {v['maxima_at_Ztilde']}", file=sys.stderr, flush=True)
+    if args.blue:
+        line["blue_paths"] = blue_leg(z2h, torch)
+        for p, v in line["blue_paths"]["paths"].items():
+            print(f"blue p={p}: d2E max at {v['d2_max_at']:.3f}, min at {v['d2_min_at']:.3f}, dual point "
+                  f"{v['dual_point_lambda']:.3f}", file=sys.stderr, flush=True)
     if args.refinement:
         line["refinement"] = refinement_leg(z2h, torch)
         for r in line["refinement"]["rows"]:
