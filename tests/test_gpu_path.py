@@ -150,3 +150,22 @@ def test_paths_batched_ragged_legs():
     assert np.array_equal(tr[:4, 0, :], ref_s[:4])
     assert np.array_equal(tr[4, 0, :], ref_s[3])
     assert np.array_equal(tr[5:, 0, :], ref_s[4:])
+
+
+@pytest.mark.parametrize("Lx,Ly,every", [(2, 2, 7), (2, 3, 0)])
+def test_paths_batched_small_lattices(Lx, Ly, every):
+    """Batched paths on one-group plans (2x2: the LDS-resident kernel) and
+    without intermediate samples (every = 0: one segment per leg) equal the
+    single-path runs bitwise."""
+    plan = z2h.z2h_plan_create(Lx, Ly, z2h.Z2H_C128)
+    paths = [z2h.make_path([(1.0, 1.0, 0.0, 0.0), (1.0, 1.0, g, 0.1), (0.8, 1.0, g, 0.3)], [21, 14], 0.07,
+                           sampling=0, every=every) for g in (0.2, 0.5)]
+    print(f"case batched paths {Lx}x{Ly} every={every}", flush=True)
+    states, trace = z2h.z2h_paths_evolve(plan, paths)
+    torch.cuda.synchronize()
+    tr = trace.cpu().numpy()
+    n = 2 * Lx * Ly
+    for j, path in enumerate(paths):
+        psi, ref = _single_path_trace(plan, path, z2h.Z2H_INIT_PSI1)
+        assert np.array_equal(tr[:, j, :], ref)
+        assert torch.equal(states[j << n:(j + 1) << n], psi)
