@@ -503,7 +503,7 @@ def exact_leg(z2h, torch):
 def circuit_leg(z2h, torch, with_4x4=False):
     """The paper's circuit at gate level (Sec. III; n links + 1 ancilla) beside
     the fused Trotter path, per Trotter step: 3x3 in complex128 gate by gate
-    (522 launches) and in fused LDS passes; optionally 4x4 (33 qubits,
+    (522 launches), in tile groups and in register groups; optionally 4x4 (33 qubits,
     complex64, 64 GiB) in fused passes."""
     out = {}
     c0, c1, M, dt = (0.5, 0.5, 0.0, 0.0), (0.5, 0.5, 0.3, 0.2), 100, 0.02

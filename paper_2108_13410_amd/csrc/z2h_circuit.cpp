@@ -179,7 +179,12 @@ z2h_status run_unfused(int nq, bool c128, void *st, double *parts, const z2h_gat
 
 // Greedy grouping: consecutive gates join the current group while the union
 // of their qubits and the always-local low qubits fits the tile width.
+// Within a group, consecutive gates form a phase while the union of their
+// local bits fits the kRegBits register bits; a phase's layout is padded
+// with the highest local bits, so a phase on the top local bits needs no
+// change of layout.
 z2h_status run_fused(int nq, bool c128, void *st, double *parts, const z2h_gate *g, int ng, hipStream_t s) {
+    if (nq < kRegBits + 1) return run_unfused(nq, c128, st, parts, g, ng, s);
     const int mloc = std::min(nq, c128 ? 12 : 13);
     const int nbase = std::min(4, mloc);
     std::vector<char> in(nq, 0);
@@ -214,10 +219,37 @@ z2h_status run_fused(int nq, bool c128, void *st, double *parts, const z2h_gate 
             }
         }
         a.ngates = (int)group.size();
+        std::vector<int> bits;
+        int first = 0;
+        auto close = [&](int end) {
+            std::vector<int> lay = bits;
+            for (int b = mloc - 1; (int)lay.size() < kRegBits; --b)
+                if (std::find(lay.begin(), lay.end(), b) == lay.end()) lay.push_back(b);
+            std::sort(lay.begin(), lay.end());
+            uint32_t code = 0;
+            int rb[16];
+            for (int b = 0; b < kRegBits; ++b) {
+                code |= (uint32_t)lay[b] << (4 * b);
+                rb[lay[b]] = b;
+            }
+            a.phase[a.nphase++] = code | (uint32_t)end << 24;
+            for (int i = first; i < end; ++i) {
+                const z2h_gate &x = g[group[i]];
+                a.gates[i] = device_gate(x, rb[loc[x.q0]], x.kind == Z2H_GATE_CNOT ? rb[loc[x.q1]] : 0);
+            }
+            first = end;
+            bits.clear();
+        };
         for (int i = 0; i < a.ngates; ++i) {
             const z2h_gate &x = g[group[i]];
-            a.gates[i] = device_gate(x, loc[x.q0], x.kind == Z2H_GATE_CNOT ? loc[x.q1] : 0);
+            const int b0 = loc[x.q0], b1 = x.kind == Z2H_GATE_CNOT ? loc[x.q1] : b0;
+            const bool h0 = std::find(bits.begin(), bits.end(), b0) != bits.end();
+            const bool h1 = b1 == b0 || std::find(bits.begin(), bits.end(), b1) != bits.end();
+            if ((int)bits.size() + !h0 + !h1 > kRegBits) close(i);
+            if (std::find(bits.begin(), bits.end(), b0) == bits.end()) bits.push_back(b0);
+            if (std::find(bits.begin(), bits.end(), b1) == bits.end()) bits.push_back(b1);
         }
+        close(a.ngates);
         hipError_t e = launch_fused(c128, a, s);
         if (e != hipSuccess) return fail(Z2H_ERR_HIP, "fused gate pass failed: %s", hipGetErrorString(e));
         reset();

@@ -1,7 +1,8 @@
 // Gate kernels for the gate-level emulation of the paper's circuits
 // (Sec. III; Eqs. (ini1), (ini2)): one-qubit gates given as 2x2 matrices,
-// CNOT, projection on |0>, renormalisation, and a fused pass that applies a
-// group of gates to tiles held in LDS.
+// CNOT, projection on |0>, renormalisation, and two fused passes that keep
+// a thread's amplitudes in registers: gate groups on the qubits of an LDS
+// tile, applied in register phases, and gate groups on five qubits.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -90,97 +91,95 @@ __global__ void __launch_bounds__(256) scale_kernel(Cx<Real> *st, uint64_t n, co
     }
 }
 
-// Global index of a tile's element: local bit j sits at qubit lq[j], tile
-// bit j at qubit cq[j].
-__device__ __forceinline__ uint64_t local_offset(const FusedArgs &a, uint32_t e) {
-    uint64_t g = 0;
-    for (int j = 0; j < a.m; ++j) g |= (uint64_t)((e >> j) & 1u) << a.lq[j];
-    return g;
-}
+// ------------------------------------------------------------ register file
 
-__device__ __forceinline__ uint64_t tile_base(const FusedArgs &a, uint64_t tile) {
-    uint64_t g = 0;
-    for (int j = 0; j < a.nq - a.m; ++j) g |= ((tile >> j) & 1ull) << a.cq[j];
-    return g;
-}
-
-// A group of gates on the qubits of one tile: load the 2^m amplitudes of a
-// tile (the four lowest qubits are always local, so each row is 16
-// contiguous amplitudes), apply the gates one after another in LDS, store.
+// The 2^kRegBits amplitudes a thread holds, real and imaginary parts
+// interleaved in one vector value.  The gates below touch it only through
+// compile-time element indices, and a runtime switch picks the
+// instantiation for a gate's register bits.  (With an array, merged switch
+// cases address the elements through pointer selects, and the array is
+// then kept in scratch memory.)
 template <typename Real>
-__global__ void __launch_bounds__(256) fused_kernel(FusedArgs a) {
-    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
-    Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
-    Cx<Real> *st = reinterpret_cast<Cx<Real> *>(a.state);
-    const uint32_t T = 1u << a.m, t = threadIdx.x, nt = blockDim.x;
-    const uint64_t tiles = 1ull << (a.nq - a.m);
-    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        const uint64_t base = tile_base(a, tile);
-        for (uint32_t e = t; e < T; e += nt) lds[e] = st[base | local_offset(a, e)];
-        __syncthreads();
-        for (int k = 0; k < a.ngates; ++k) {
-            const GateDev &g = a.gates[k];
-            if (g.kind == Z2H_GATE_CNOT) {
-                const int lo = g.q0 < g.q1 ? g.q0 : g.q1, hi = g.q0 < g.q1 ? g.q1 : g.q0;
-                for (uint32_t p = t; p < (T >> 2); p += nt) {
-                    const uint32_t i = (uint32_t)insert0(insert0(p, lo), hi) | (1u << g.q0);
-                    const uint32_t j = i | (1u << g.q1);
-                    const Cx<Real> x = lds[i];
-                    lds[i] = lds[j];
-                    lds[j] = x;
-                }
-            } else {
-                for (uint32_t p = t; p < (T >> 1); p += nt) {
-                    const uint32_t i = (uint32_t)insert0(p, g.q0), j = i | (1u << g.q0);
-                    if (g.kind == Z2H_GATE_PROJ0) {
-                        lds[j] = Cx<Real>{(Real)0, (Real)0};
-                    } else {
-                        Cx<Real> x = lds[i], y = lds[j];
-                        apply_2x2<Real>(x, y, g.m);
-                        lds[i] = x;
-                        lds[j] = y;
-                    }
-                }
-            }
-            __syncthreads();
+struct RegFile {
+    typedef Real type __attribute__((ext_vector_type(2 << kRegBits)));
+};
+template <typename Real>
+using Regs = typename RegFile<Real>::type;
+
+// The one-qubit gates in the forms their matrices have (the host builds
+// them so): H = r [[1, 1], [1, -1]]; R_x = [[c, i w], [i w, c]]; R_z =
+// diag(d0, d1).  Eight real operations per amplitude pair instead of the
+// sixteen of a general complex 2x2 matrix.
+template <typename Real, int B>
+__device__ __forceinline__ void reg_h(Regs<Real> &v, const double *m) {
+    const Real r = (Real)m[0];
+#pragma unroll
+    for (int k = 0; k < (1 << kRegBits); ++k)
+        if (!(k & (1 << B))) {
+            const int j = k | (1 << B);
+            const Real xr = v[2 * k], xi = v[2 * k + 1], yr = v[2 * j], yi = v[2 * j + 1];
+            v[2 * k] = r * (xr + yr);
+            v[2 * k + 1] = r * (xi + yi);
+            v[2 * j] = r * (xr - yr);
+            v[2 * j + 1] = r * (xi - yi);
         }
-        for (uint32_t e = t; e < T; e += nt) st[base | local_offset(a, e)] = lds[e];
-        __syncthreads();
+}
+
+template <typename Real, int B>
+__device__ __forceinline__ void reg_rx(Regs<Real> &v, const double *m) {
+    const Real c = (Real)m[0], w = (Real)m[3];
+#pragma unroll
+    for (int k = 0; k < (1 << kRegBits); ++k)
+        if (!(k & (1 << B))) {
+            const int j = k | (1 << B);
+            const Real xr = v[2 * k], xi = v[2 * k + 1], yr = v[2 * j], yi = v[2 * j + 1];
+            v[2 * k] = c * xr - w * yi;
+            v[2 * k + 1] = c * xi + w * yr;
+            v[2 * j] = c * yr - w * xi;
+            v[2 * j + 1] = c * yi + w * xr;
+        }
+}
+
+template <typename Real, int B>
+__device__ __forceinline__ void reg_rz(Regs<Real> &v, const double *m) {
+    const Cx<Real> d0{(Real)m[0], (Real)m[1]}, d1{(Real)m[6], (Real)m[7]};
+#pragma unroll
+    for (int k = 0; k < (1 << kRegBits); ++k) {
+        const Cx<Real> d = (k & (1 << B)) ? d1 : d0;
+        const Cx<Real> p = cmul(d, Cx<Real>{v[2 * k], v[2 * k + 1]});
+        v[2 * k] = p.x;
+        v[2 * k + 1] = p.y;
     }
 }
 
-// Gates on register bits: every one-qubit gate, CNOT and projection acts
-// on pairs of a thread's own registers, with the bit positions fixed at
-// compile time (a runtime switch picks the instantiation).
 template <typename Real, int B>
-__device__ __forceinline__ void reg_1q(Cx<Real> (&v)[1 << kRegBits], const double *m) {
+__device__ __forceinline__ void reg_proj0(Regs<Real> &v) {
 #pragma unroll
     for (int k = 0; k < (1 << kRegBits); ++k)
-        if (!(k & (1 << B))) apply_2x2<Real>(v[k], v[k | (1 << B)], m);
-}
-
-template <typename Real, int B>
-__device__ __forceinline__ void reg_proj0(Cx<Real> (&v)[1 << kRegBits]) {
-#pragma unroll
-    for (int k = 0; k < (1 << kRegBits); ++k)
-        if (k & (1 << B)) v[k] = Cx<Real>{(Real)0, (Real)0};
+        if (k & (1 << B)) {
+            v[2 * k] = (Real)0;
+            v[2 * k + 1] = (Real)0;
+        }
 }
 
 template <typename Real, int C, int T>
-__device__ __forceinline__ void reg_cnot(Cx<Real> (&v)[1 << kRegBits]) {
+__device__ __forceinline__ void reg_cnot(Regs<Real> &v) {
     if constexpr (C != T) {
 #pragma unroll
         for (int k = 0; k < (1 << kRegBits); ++k)
             if ((k & (1 << C)) && !(k & (1 << T))) {
-                const Cx<Real> x = v[k];
-                v[k] = v[k | (1 << T)];
-                v[k | (1 << T)] = x;
+                const int j = k | (1 << T);
+                const Real x = v[2 * k], y = v[2 * k + 1];
+                v[2 * k] = v[2 * j];
+                v[2 * k + 1] = v[2 * j + 1];
+                v[2 * j] = x;
+                v[2 * j + 1] = y;
             }
     }
 }
 
 template <typename Real, int C>
-__device__ __forceinline__ void reg_cnot_t(Cx<Real> (&v)[1 << kRegBits], int t) {
+__device__ __forceinline__ void reg_cnot_t(Regs<Real> &v, int t) {
     switch (t) {
         case 0: reg_cnot<Real, C, 0>(v); break;
         case 1: reg_cnot<Real, C, 1>(v); break;
@@ -191,7 +190,7 @@ __device__ __forceinline__ void reg_cnot_t(Cx<Real> (&v)[1 << kRegBits], int t) 
 }
 
 template <typename Real>
-__device__ __forceinline__ void reg_gate(Cx<Real> (&v)[1 << kRegBits], const GateDev &g) {
+__device__ __forceinline__ void reg_gate(Regs<Real> &v, const GateDev &g) {
     static_assert(kRegBits == 5, "the switches below cover five register bits");
     if (g.kind == Z2H_GATE_CNOT) {
         switch (g.q0) {
@@ -209,14 +208,170 @@ __device__ __forceinline__ void reg_gate(Cx<Real> (&v)[1 << kRegBits], const Gat
             case 3: reg_proj0<Real, 3>(v); break;
             default: reg_proj0<Real, 4>(v); break;
         }
+    } else if (g.kind == Z2H_GATE_H) {
+        switch (g.q0) {
+            case 0: reg_h<Real, 0>(v, g.m); break;
+            case 1: reg_h<Real, 1>(v, g.m); break;
+            case 2: reg_h<Real, 2>(v, g.m); break;
+            case 3: reg_h<Real, 3>(v, g.m); break;
+            default: reg_h<Real, 4>(v, g.m); break;
+        }
+    } else if (g.kind == Z2H_GATE_RX) {
+        switch (g.q0) {
+            case 0: reg_rx<Real, 0>(v, g.m); break;
+            case 1: reg_rx<Real, 1>(v, g.m); break;
+            case 2: reg_rx<Real, 2>(v, g.m); break;
+            case 3: reg_rx<Real, 3>(v, g.m); break;
+            default: reg_rx<Real, 4>(v, g.m); break;
+        }
     } else {
         switch (g.q0) {
-            case 0: reg_1q<Real, 0>(v, g.m); break;
-            case 1: reg_1q<Real, 1>(v, g.m); break;
-            case 2: reg_1q<Real, 2>(v, g.m); break;
-            case 3: reg_1q<Real, 3>(v, g.m); break;
-            default: reg_1q<Real, 4>(v, g.m); break;
+            case 0: reg_rz<Real, 0>(v, g.m); break;
+            case 1: reg_rz<Real, 1>(v, g.m); break;
+            case 2: reg_rz<Real, 2>(v, g.m); break;
+            case 3: reg_rz<Real, 3>(v, g.m); break;
+            default: reg_rz<Real, 4>(v, g.m); break;
         }
+    }
+}
+
+// Register k of a thread whose base index is `base`: the bits of k select
+// the offsets off[0..kRegBits).
+template <typename Real>
+__device__ __forceinline__ void load_regs(Regs<Real> &v, const Cx<Real> *st, uint64_t base,
+                                          const uint64_t (&off)[kRegBits]) {
+#pragma unroll
+    for (int k = 0; k < (1 << kRegBits); ++k) {
+        uint64_t i = base;
+#pragma unroll
+        for (int b = 0; b < kRegBits; ++b)
+            if (k & (1 << b)) i |= off[b];
+        const Cx<Real> e = st[i];
+        v[2 * k] = e.x;
+        v[2 * k + 1] = e.y;
+    }
+}
+
+template <typename Real>
+__device__ __forceinline__ void store_regs(const Regs<Real> &v, Cx<Real> *st, uint64_t base,
+                                           const uint64_t (&off)[kRegBits]) {
+#pragma unroll
+    for (int k = 0; k < (1 << kRegBits); ++k) {
+        uint64_t i = base;
+#pragma unroll
+        for (int b = 0; b < kRegBits; ++b)
+            if (k & (1 << b)) i |= off[b];
+        st[i] = Cx<Real>{v[2 * k], v[2 * k + 1]};
+    }
+}
+
+// The bits of x deposited, lowest first, at the qubits q[0..n).
+__device__ __forceinline__ uint64_t deposit(uint64_t x, const int32_t *q, int n) {
+    uint64_t g = 0;
+    for (int j = 0; j < n; ++j) g |= ((x >> j) & 1ull) << q[j];
+    return g;
+}
+
+// ------------------------------------------------------------- tile phases
+
+// Local index of register 0 of thread t in the layout with register bits
+// S[0] < ... < S[kRegBits-1]: t's bits fill the other local bits in order.
+__device__ __forceinline__ uint32_t spread(uint32_t t, const int (&S)[kRegBits]) {
+    uint32_t x = t;
+#pragma unroll
+    for (int b = 0; b < kRegBits; ++b) x = ((x >> S[b]) << (S[b] + 1)) | (x & ((1u << S[b]) - 1u));
+    return x;
+}
+
+// LDS slot of local index i: the bits above a 256-byte row are folded into
+// the offset within the row, so threads whose indices differ only in higher
+// bits reach different banks.  A bijection of [0, 2^m) for every m.
+template <typename Real>
+__device__ __forceinline__ uint32_t lds_slot(uint32_t i) {
+    constexpr int w = sizeof(Real) == 8 ? 4 : 5;
+    return i ^ ((i >> w) & ((1u << w) - 1u));
+}
+
+__device__ __forceinline__ void unpack_layout(uint32_t code, int (&S)[kRegBits]) {
+#pragma unroll
+    for (int b = 0; b < kRegBits; ++b) S[b] = (int)((code >> (4 * b)) & 15u);
+}
+
+// Move the tile from layout `from` to layout `to` through LDS.
+template <typename Real>
+__device__ __forceinline__ void relayout(Regs<Real> &v, Cx<Real> *lds, uint32_t t, uint32_t from, uint32_t to) {
+    int S[kRegBits];
+    unpack_layout(from, S);
+    uint32_t base = spread(t, S);
+    __syncthreads();  // every thread is done with the previous contents
+#pragma unroll
+    for (int k = 0; k < (1 << kRegBits); ++k) {
+        uint32_t i = base;
+#pragma unroll
+        for (int b = 0; b < kRegBits; ++b)
+            if (k & (1 << b)) i |= 1u << S[b];
+        lds[lds_slot<Real>(i)] = Cx<Real>{v[2 * k], v[2 * k + 1]};
+    }
+    __syncthreads();
+    unpack_layout(to, S);
+    base = spread(t, S);
+#pragma unroll
+    for (int k = 0; k < (1 << kRegBits); ++k) {
+        uint32_t i = base;
+#pragma unroll
+        for (int b = 0; b < kRegBits; ++b)
+            if (k & (1 << b)) i |= 1u << S[b];
+        const Cx<Real> e = lds[lds_slot<Real>(i)];
+        v[2 * k] = e.x;
+        v[2 * k + 1] = e.y;
+    }
+}
+
+// A group of gates on the qubits of one tile of 2^m amplitudes.  Each
+// thread loads its 2^kRegBits amplitudes in the home layout (its own bits
+// are the tile's lowest qubits, which keeps the loads coalesced), applies
+// the gates phase by phase in registers, changing layout through LDS
+// between phases whose register bits differ, and stores in the home layout.
+// Two 64 KiB complex64 tiles fit a CU's LDS; the register budget is set
+// for the two waves per SIMD that this allows.
+template <typename Real>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 2 : 1)))
+fused_kernel(FusedArgs a) {
+    extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
+    Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
+    Cx<Real> *st = reinterpret_cast<Cx<Real> *>(a.state);
+    const uint32_t t = threadIdx.x;
+    const int lt = a.m - kRegBits, nc = a.nq - a.m;
+    uint32_t home = 0;
+#pragma unroll
+    for (int b = 0; b < kRegBits; ++b) home |= (uint32_t)(lt + b) << (4 * b);
+    uint64_t off[kRegBits];
+#pragma unroll
+    for (int b = 0; b < kRegBits; ++b) off[b] = 1ull << a.lq[lt + b];
+    const uint64_t toff = deposit(t, a.lq, lt);
+    // tile numbers deposited at the qubits cq[]: advanced by a masked add
+    const uint64_t mask = deposit(~0ull, a.cq, nc), step = deposit(gridDim.x, a.cq, nc);
+    uint64_t tb = deposit(blockIdx.x, a.cq, nc);
+    const uint64_t tiles = 1ull << nc;
+    for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
+        Regs<Real> v;
+        load_regs<Real>(v, st, tb | toff, off);
+        uint32_t cur = home;
+        int g = 0;
+        for (int p = 0; p < a.nphase; ++p) {
+            const uint32_t lay = a.phase[p] & 0xFFFFFu;
+            if (lay != cur) {
+                relayout<Real>(v, lds, t, cur, lay);
+                cur = lay;
+            }
+            for (const int end = (int)(a.phase[p] >> 24); g < end; ++g) reg_gate<Real>(v, a.gates[g]);
+        }
+        if (cur != home) relayout<Real>(v, lds, t, cur, home);
+        uint64_t base = tb | toff;
+        // keeps the 32 store addresses from being computed before the gates
+        asm volatile("" : "+v"(base));
+        store_regs<Real>(v, st, base, off);
+        tb = ((tb | ~mask) + step) & mask;
     }
 }
 
@@ -225,38 +380,22 @@ __device__ __forceinline__ void reg_gate(Cx<Real> (&v)[1 << kRegBits], const Gat
 template <typename Real>
 __global__ void __launch_bounds__(256) reg_kernel(RegArgs a) {
     Cx<Real> *st = reinterpret_cast<Cx<Real> *>(a.state);
-    const uint32_t t = threadIdx.x;
-    uint64_t tpart = 0;
-    for (int j = 0; j < a.nt; ++j) tpart |= (uint64_t)((t >> j) & 1u) << a.tq[j];
-    uint64_t roff[kRegBits];
+    const uint64_t tpart = deposit(threadIdx.x, a.tq, a.nt);
+    uint64_t off[kRegBits];
 #pragma unroll
-    for (int i = 0; i < kRegBits; ++i) roff[i] = 1ull << a.rq[i];
+    for (int i = 0; i < kRegBits; ++i) off[i] = 1ull << a.rq[i];
     const int ncq = a.nq - kRegBits - a.nt;
+    const uint64_t mask = deposit(~0ull, a.cq, ncq), step = deposit(gridDim.x, a.cq, ncq);
+    uint64_t tb = deposit(blockIdx.x, a.cq, ncq);
     const uint64_t tiles = 1ull << ncq;
     for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
-        uint64_t base = tpart;
-        for (int j = 0; j < ncq; ++j) base |= ((tile >> j) & 1ull) << a.cq[j];
-        Cx<Real> v[1 << kRegBits];
-#pragma unroll
-        for (int k = 0; k < (1 << kRegBits); ++k) {
-            uint64_t i = base;
-#pragma unroll
-            for (int b = 0; b < kRegBits; ++b)
-                if (k & (1 << b)) i |= roff[b];
-            v[k] = st[i];
-        }
+        Regs<Real> v;
+        load_regs<Real>(v, st, tb | tpart, off);
         for (int g = 0; g < a.ngates; ++g) reg_gate<Real>(v, a.gates[g]);
-        // recompute the store addresses rather than keep the 32 load
-        // addresses alive through the gates (two registers each)
+        uint64_t base = tb | tpart;
         asm volatile("" : "+v"(base));
-#pragma unroll
-        for (int k = 0; k < (1 << kRegBits); ++k) {
-            uint64_t i = base;
-#pragma unroll
-            for (int b = 0; b < kRegBits; ++b)
-                if (k & (1 << b)) i |= roff[b];
-            st[i] = v[k];
-        }
+        store_regs<Real>(v, st, base, off);
+        tb = ((tb | ~mask) + step) & mask;
     }
 }
 
@@ -277,14 +416,16 @@ hipError_t launch_gate(bool c128, void *state, int nq, const GateDev &g, hipStre
 }
 
 hipError_t launch_fused(bool c128, const FusedArgs &a, hipStream_t s) {
+    if (a.m < kRegBits + 1 || a.m > 13 || a.nq - a.m > 40) return hipErrorInvalidValue;
     const uint64_t tiles = 1ull << (a.nq - a.m);
     const unsigned nb = (unsigned)(tiles < (uint64_t)kGateBlocksMax ? tiles : (uint64_t)kGateBlocksMax);
+    const unsigned nt = 1u << (a.m - kRegBits);
     const size_t lds = (size_t)(c128 ? 16 : 8) << a.m;
-    if (lds > 65536) return hipErrorInvalidValue;
+    if (lds > 65536 || nt > 256) return hipErrorInvalidValue;
     if (c128)
-        hipLaunchKernelGGL(fused_kernel<double>, dim3(nb), dim3(256), lds, s, a);
+        hipLaunchKernelGGL(fused_kernel<double>, dim3(nb), dim3(nt), lds, s, a);
     else
-        hipLaunchKernelGGL(fused_kernel<float>, dim3(nb), dim3(256), lds, s, a);
+        hipLaunchKernelGGL(fused_kernel<float>, dim3(nb), dim3(nt), lds, s, a);
     return hipGetLastError();
 }
 

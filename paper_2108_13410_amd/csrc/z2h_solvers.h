@@ -129,23 +129,32 @@ struct GateDev {
 
 constexpr int kFuseMaxGates = 40;   // gates applied by one fused tile pass
 constexpr int kGateBlocksMax = 4096;
+constexpr int kRegBits = 5;         // qubits held in a thread's registers
 
-// One fused pass: the tile holds the m qubits lq[0..m) (ascending; the
-// gates' qubits are local indices into it) and the tile number supplies the
-// other qubits cq[0..nq-m) in ascending order.
+// One fused pass over tiles of m qubits lq[0..m) (ascending); the tile
+// number supplies the other qubits cq[0..nq-m) in ascending order.  Local
+// bit j of the tile index is qubit lq[j].  Each thread holds 2^kRegBits
+// amplitudes of a tile, which differ in kRegBits local bits (the layout);
+// the 2^(m-kRegBits) threads of a block differ in the other local bits.
+// The gates run in phases: phase p has the layout whose local bits are
+// packed 4 bits each, ascending, in bits 0..19 of phase[p], and applies the
+// gates up to index phase[p] >> 24 (exclusive).  Gate qubits are register
+// bit indices into the layout of their phase.  Loads and stores use the
+// home layout, the top kRegBits local bits.
 struct FusedArgs {
     void *state;
-    int32_t nq, m, ngates, pad;
+    int32_t nq, m, ngates, nphase;
     int32_t lq[16];
     int32_t cq[40];
+    uint32_t phase[kFuseMaxGates];
     GateDev gates[kFuseMaxGates];
 };
+static_assert(sizeof(FusedArgs) <= 4096, "kernel argument block");
 
 // One register-group pass: each thread holds the 2^kRegBits amplitudes that
 // differ in the group's qubits rq[] (its register bits); the 2^nt threads of
 // a block differ in qubits tq[]; the block's tile number supplies the other
 // qubits cq[].  Gate qubits are register-bit indices.
-constexpr int kRegBits = 5;
 struct RegArgs {
     void *state;
     int32_t nq, nt, ngates, pad;

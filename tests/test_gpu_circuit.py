@@ -1,8 +1,9 @@
 """GPU parity of the gate-level circuits (Sec. III with the ancilla; Eqs.
 (ini1), (ini2)) through the C ABI.
 
-- One Trotter step as the library's gate list, run gate by gate and in fused
-  LDS passes, against the oracle's own gate-level circuit (paper numbering),
+- One Trotter step as the library's gate list, run gate by gate, in tile
+  groups (register phases, layout changes through LDS) and in register
+  groups, against the oracle's own gate-level circuit (paper numbering),
   from a random link state with the ancilla in |0>.
 - The preparation circuits against psi_1 and psi_1'.
 - A gate-level ramp against the fused Trotter path of the library and the
