@@ -145,3 +145,52 @@ def test_gate_level_4x4_with_ancilla(fuse):
     assert np.abs(anc).max() < 3e-5 * scale
     del psi, phi
     torch.cuda.empty_cache()
+
+
+def random_gates(rng, nq, count):
+    """A random gate list (oracle tuples and the library's array): one-qubit
+    rotations, Hadamards, CNOTs both ways, a projection and a renormalisation
+    in the middle, on qubits drawn from a few clusters so that consecutive
+    gates share qubits and the fused executors form real groups."""
+    clusters = [rng.choice(nq, size=min(nq, 6), replace=False) for _ in range(4)]
+    ora, lib = [], []
+    for i in range(count):
+        cl = clusters[(i // 15) % len(clusters)]
+        r = rng.random()
+        if i == count // 2:
+            q = int(rng.choice(cl))
+            ora += [("P0", (q,)), ("NORM", ())]
+            lib += [(z2h.Z2H_GATE_PROJ0, q, 0, 0.0), (z2h.Z2H_GATE_NORM, 0, 0, 0.0)]
+        elif r < 0.35:
+            c, t = (int(x) for x in rng.choice(cl, size=2, replace=False))
+            ora.append(("CNOT", (c, t)))
+            lib.append((z2h.Z2H_GATE_CNOT, c, t, 0.0))
+        else:
+            q, th = int(rng.choice(cl)), float(rng.uniform(-3, 3))
+            kind = ("H", "RX", "RZ")[int(rng.integers(3))]
+            ora.append((kind, (q,)) if kind == "H" else (kind, (q,), th))
+            lib.append(({"H": z2h.Z2H_GATE_H, "RX": z2h.Z2H_GATE_RX, "RZ": z2h.Z2H_GATE_RZ}[kind], q, 0, th))
+    arr = (z2h.z2h_gate * len(lib))()
+    for a, (k, q0, q1, th) in zip(arr, lib):
+        a.kind, a.q0, a.q1, a.theta = k, q0, q1, th
+    return ora, arr, len(lib)
+
+
+@pytest.mark.parametrize("nq", [5, 6, 9, 12, 14, 16])
+@pytest.mark.parametrize("fuse", [0, 1, 2])
+@pytest.mark.parametrize("dtype", [z2h.Z2H_C128, z2h.Z2H_C64])
+def test_random_gate_lists(nq, fuse, dtype):
+    """Random gate lists against the oracle's gate-by-gate application: every
+    executor, layouts on low and high qubits, tiles smaller than a wave
+    (fewer than 11 qubits) and the gate-by-gate fallback (5 qubits)."""
+    rng = np.random.default_rng(1000 * nq + 10 * fuse + dtype)
+    print(f"case random gates nq={nq} fuse={fuse} dtype={dtype}", flush=True)
+    x = rng.normal(size=1 << nq) + 1j * rng.normal(size=1 << nq)
+    x /= np.linalg.norm(x)
+    ora, arr, ng = random_gates(rng, nq, 150)
+    ref = circuit.apply(x, ora)
+    psi = torch.tensor(x, dtype=CDT[dtype], device="cuda")
+    run(nq, dtype, psi, arr, ng, fuse)
+    got = psi.cpu().numpy().astype(np.complex128)
+    tol = 1e-12 if dtype == z2h.Z2H_C128 else 5e-6
+    assert np.abs(got - ref).max() < tol
