@@ -282,7 +282,7 @@ z2h_status run_fused(int nq, bool c128, void *st, double *parts, const z2h_gate 
 // one pass in which every thread holds the amplitudes that differ in those
 // qubits.  The group's qubit set is padded with the highest remaining qubits
 // so that the 256 threads of a block cover the lowest ones (coalesced
-// access).  States of fewer than kRegBits + 6 qubits use LDS groups instead.
+// access).  States of fewer than kRegBits + 6 qubits use tile groups instead.
 z2h_status run_reg(int nq, bool c128, void *st, double *parts, const z2h_gate *g, int ng, hipStream_t s) {
     if (nq < kRegBits + 6) return run_fused(nq, c128, st, parts, g, ng, s);
     const int nt = std::min(8, nq - kRegBits);
