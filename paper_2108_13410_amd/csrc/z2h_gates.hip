@@ -6,6 +6,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <set>
+
 #include "../../include/z2h.h"
 #include "z2h_internal.h"
 #include "z2h_kernels.h"
@@ -283,13 +286,22 @@ __device__ __forceinline__ uint32_t spread(uint32_t t, const int (&S)[kRegBits])
     return x;
 }
 
-// LDS slot of local index i: the bits above a 256-byte row are folded into
-// the offset within the row, so threads whose indices differ only in higher
-// bits reach different banks.  A bijection of [0, 2^m) for every m.
+// LDS slot of local index i: one pad element after every 256-byte row, so
+// threads whose indices differ only in higher bits reach different banks.
+// For indices with disjoint bits the slot is additive, slot(a | b) =
+// slot(a) + slot(b) (the low parts of a and b add without a carry), so a
+// register's slot is the thread's slot plus a block-uniform offset.
+template <typename Real>
+constexpr int kPadShift = sizeof(Real) == 8 ? 4 : 5;
+
 template <typename Real>
 __device__ __forceinline__ uint32_t lds_slot(uint32_t i) {
-    constexpr int w = sizeof(Real) == 8 ? 4 : 5;
-    return i ^ ((i >> w) & ((1u << w) - 1u));
+    return i + (i >> kPadShift<Real>);
+}
+
+template <typename Real>
+constexpr size_t tile_lds_bytes(int m) {
+    return (((size_t)1 << m) + ((size_t)1 << m >> kPadShift<Real>)) * sizeof(Cx<Real>);
 }
 
 __device__ __forceinline__ void unpack_layout(uint32_t code, int (&S)[kRegBits]) {
@@ -301,27 +313,32 @@ __device__ __forceinline__ void unpack_layout(uint32_t code, int (&S)[kRegBits])
 template <typename Real>
 __device__ __forceinline__ void relayout(Regs<Real> &v, Cx<Real> *lds, uint32_t t, uint32_t from, uint32_t to) {
     int S[kRegBits];
+    uint32_t so[kRegBits];
     unpack_layout(from, S);
-    uint32_t base = spread(t, S);
+    uint32_t base = lds_slot<Real>(spread(t, S));
+#pragma unroll
+    for (int b = 0; b < kRegBits; ++b) so[b] = lds_slot<Real>(1u << S[b]);
     __syncthreads();  // every thread is done with the previous contents
 #pragma unroll
     for (int k = 0; k < (1 << kRegBits); ++k) {
-        uint32_t i = base;
+        uint32_t o = 0;
 #pragma unroll
         for (int b = 0; b < kRegBits; ++b)
-            if (k & (1 << b)) i |= 1u << S[b];
-        lds[lds_slot<Real>(i)] = Cx<Real>{v[2 * k], v[2 * k + 1]};
+            if (k & (1 << b)) o += so[b];
+        lds[base + o] = Cx<Real>{v[2 * k], v[2 * k + 1]};
     }
     __syncthreads();
     unpack_layout(to, S);
-    base = spread(t, S);
+    base = lds_slot<Real>(spread(t, S));
+#pragma unroll
+    for (int b = 0; b < kRegBits; ++b) so[b] = lds_slot<Real>(1u << S[b]);
 #pragma unroll
     for (int k = 0; k < (1 << kRegBits); ++k) {
-        uint32_t i = base;
+        uint32_t o = 0;
 #pragma unroll
         for (int b = 0; b < kRegBits; ++b)
-            if (k & (1 << b)) i |= 1u << S[b];
-        const Cx<Real> e = lds[lds_slot<Real>(i)];
+            if (k & (1 << b)) o += so[b];
+        const Cx<Real> e = lds[base + o];
         v[2 * k] = e.x;
         v[2 * k + 1] = e.y;
     }
@@ -332,8 +349,8 @@ __device__ __forceinline__ void relayout(Regs<Real> &v, Cx<Real> *lds, uint32_t 
 // are the tile's lowest qubits, which keeps the loads coalesced), applies
 // the gates phase by phase in registers, changing layout through LDS
 // between phases whose register bits differ, and stores in the home layout.
-// Two 64 KiB complex64 tiles fit a CU's LDS; the register budget is set
-// for the two waves per SIMD that this allows.
+// Two padded complex64 tiles (66 KiB each) fit a CU's LDS; the register
+// budget is set for the two waves per SIMD that this allows.
 template <typename Real>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 2 : 1)))
 fused_kernel(FusedArgs a) {
@@ -401,6 +418,10 @@ __global__ void __launch_bounds__(256) reg_kernel(RegArgs a) {
 
 // ---------------------------------------------------------------- launchers
 
+// Largest padded tile: 2^13 complex64 or 2^12 complex128 amplitudes.
+constexpr size_t kTileLdsMax = 69632;
+static_assert(tile_lds_bytes<float>(13) <= kTileLdsMax && tile_lds_bytes<double>(12) <= kTileLdsMax, "tile LDS");
+
 static unsigned blocks_for(uint64_t work) {
     const uint64_t b = (work + 255) / 256;
     return (unsigned)(b < (uint64_t)kGateBlocksMax ? (b ? b : 1) : (uint64_t)kGateBlocksMax);
@@ -415,13 +436,30 @@ hipError_t launch_gate(bool c128, void *state, int nq, const GateDev &g, hipStre
     return hipGetLastError();
 }
 
+static std::mutex g_lds_mu;
+static std::set<const void *> g_lds_done;
+
+// Raise a kernel's dynamic-LDS limit once (tiles above 64 KiB).
+static hipError_t allow_lds(const void *fn, size_t lds) {
+    if (lds <= 65536) return hipSuccess;
+    std::lock_guard<std::mutex> lk(g_lds_mu);
+    if (g_lds_done.count(fn)) return hipSuccess;
+    hipError_t e = hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)kTileLdsMax);
+    if (e == hipSuccess) g_lds_done.insert(fn);
+    return e;
+}
+
 hipError_t launch_fused(bool c128, const FusedArgs &a, hipStream_t s) {
     if (a.m < kRegBits + 1 || a.m > 13 || a.nq - a.m > 40) return hipErrorInvalidValue;
     const uint64_t tiles = 1ull << (a.nq - a.m);
     const unsigned nb = (unsigned)(tiles < (uint64_t)kGateBlocksMax ? tiles : (uint64_t)kGateBlocksMax);
     const unsigned nt = 1u << (a.m - kRegBits);
-    const size_t lds = (size_t)(c128 ? 16 : 8) << a.m;
-    if (lds > 65536 || nt > 256) return hipErrorInvalidValue;
+    const size_t lds = c128 ? tile_lds_bytes<double>(a.m) : tile_lds_bytes<float>(a.m);
+    if (lds > kTileLdsMax || nt > 256) return hipErrorInvalidValue;
+    const void *fn = c128 ? reinterpret_cast<const void *>(&fused_kernel<double>)
+                          : reinterpret_cast<const void *>(&fused_kernel<float>);
+    hipError_t e = allow_lds(fn, lds);
+    if (e != hipSuccess) return e;
     if (c128)
         hipLaunchKernelGGL(fused_kernel<double>, dim3(nb), dim3(nt), lds, s, a);
     else
