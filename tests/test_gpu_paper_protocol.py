@@ -135,3 +135,38 @@ def test_dos_maxima():
     print(f"dual line: g = {claims['dual_g1']}: {g1}; g = {claims['dual_g2']}: {g2}", flush=True)
     assert len(g1) == claims["dual_g1_maxima"] and int(claims["dual_g1_max_at"]) in g1
     assert len(g2) == claims["dual_g2_maxima"]
+
+
+@pytest.mark.parametrize("p", [0.12, 0.5])
+def test_blue_path_forward_reverse_curves(engine, p):
+    """Fig. topo, forward against reverse along the blue path: E(lambda) for
+    the state prepared at P and driven to P', E'(lambda) for the state
+    prepared at P' and driven back to P (energies every 100 steps).
+
+    - Self-duality: the reverse process at each path time has the energy of
+      the forward one (to the step-ordering error), so E'(lambda) =
+      E(p - lambda): the curves are mirror images and meet at the centre.
+    - p = 0.12 (deconfined): E is strongly asymmetric, so the two curves
+      cross, as the figure shows.
+    - p = 0.5: the curves nearly coincide and E is symmetric about the
+      centre."""
+    every = 100
+    tr = {}
+    for name, (init, verts, steps) in pr.topo_paths(p).items():
+        print(f"case blue path curves p={p} {name}", flush=True)
+        n = steps[-1] // every
+        tr[name] = engine(init, verts, steps, every)[-n - 1:, 1]
+    EF, ER = tr["E"], tr["E'"]
+    mirror = float(np.abs(ER - EF).max())
+    D = EF - ER[::-1]               # E(lambda_j) - E'(lambda_j)
+    half = len(D) // 2
+    print(f"blue p={p}: duality mirror {mirror:.2e}; E(0) - E'(0) = {D[0]:.6f}, "
+          f"max |E - E'| = {np.abs(D).max():.2e}, sign changes {int((np.diff(np.sign(D)) != 0).sum())}",
+          flush=True)
+    assert mirror < (1e-6 if p < 0.3 else 1e-5)
+    if p < 0.3:
+        assert abs(D[0]) > 0.01 and np.sign(D[0]) == -np.sign(D[-1])
+        assert np.all(np.sign(D[: half - 1]) == np.sign(D[0]))
+        assert np.all(np.sign(D[-half + 1:]) == np.sign(D[-1]))
+    else:
+        assert np.abs(D).max() < 1e-4
