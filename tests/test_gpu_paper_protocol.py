@@ -170,3 +170,62 @@ def test_blue_path_forward_reverse_curves(engine, p):
         assert np.all(np.sign(D[-half + 1:]) == np.sign(D[-1]))
     else:
         assert np.abs(D).max() < 1e-4
+
+
+def _ed_energies(Lx, Ly, pts):
+    from oracle import ed
+    return np.array([ed.ground(Lx, Ly, (pr.J, pr.J, g, lam))[0] for g, lam in pts])
+
+
+def test_2x2_against_ed():
+    """Sec. VII on the 2x2 torus (Figs. 2by2_OP, blue_example,
+    blue_example2), with the protocol's dg = 1e-5 and dt = 0.02:
+    - O -> P(0.5, 0): the second derivatives of the simulated energy and of
+      the ED ground energy along g are close;
+    - blue path at p = 0.4: the simulated curve is nearly symmetric, like
+      ED's (ED is exactly symmetric by self-duality);
+    - blue path at p = 0.1 (deconfined): the simulated curve is clearly
+      asymmetric, its ends differ, and forward and reverse curves cross."""
+    plan = z2h.z2h_plan_create(2, 2, z2h.Z2H_C128)
+    sz = z2h.z2h_plan_sizes(plan)
+    psi = z2h.alloc_state(plan)
+    ws = z2h.alloc_bytes(max(sz["ws_evolve"], sz["ws_observe"]))
+    every = 100
+
+    def run(init, verts, steps):
+        z2h.z2h_state_init(plan, psi, {"psi1": z2h.Z2H_INIT_PSI1, "psi1p": z2h.Z2H_INIT_PSI1P}[init])
+        p = z2h.make_path(verts, steps, pr.DT, sampling=1, every=every)
+        n = steps[-1] // every
+        return z2h.z2h_path_evolve(plan, psi, ws, p).cpu().numpy()[-n - 1:, 1]
+
+    print("case 2x2 O -> P(0.5, 0) against ED", flush=True)
+    init, (verts, steps) = "psi1", pr.path([(0, 0), (0.5, 0)])
+    E = run(init, verts, steps)
+    g = np.linspace(0, 0.5, len(E))
+    Eed = _ed_energies(2, 2, [(x, 0.0) for x in g])
+    x, d2 = pr.second_derivative(g, E, 10)
+    _, d2ed = pr.second_derivative(g, Eed, 10)
+    scale = np.abs(d2ed).max()
+    diff = np.abs(d2 - d2ed).max() / scale
+    print(f"2x2 O->P: max |E - E_ED| = {np.abs(E - Eed).max():.2e}; d2 minima at g = {x[np.argmin(d2)]:.3f} "
+          f"(ED {x[np.argmin(d2ed)]:.3f}); max |d2 - d2_ED| / max |d2_ED| = {diff:.3f}", flush=True)
+    assert diff < 0.02
+    assert abs(x[np.argmin(d2)] - x[np.argmin(d2ed)]) < 0.005
+    asym = {}
+    for p in (0.4, 0.1):
+        print(f"case 2x2 blue path p={p}", flush=True)
+        curves = {name: run(init, verts, steps) for name, (init, verts, steps) in pr.topo_paths(p).items()}
+        lam = np.linspace(0, p, len(curves["E"]))
+        Eed = _ed_energies(2, 2, [(p - l, l) for l in lam])
+        EF, ER = curves["E"], curves["E'"][::-1]   # both against lambda
+        asym[p] = abs(EF[-1] - EF[0])
+        D = EF - ER
+        print(f"2x2 blue p={p}: E(0) = {EF[0]:.6f}, E(p) = {EF[-1]:.6f}, asymmetry {asym[p]:.2e}; "
+              f"ED ends {Eed[0]:.6f} {Eed[-1]:.6f}; max |E - E'| = {np.abs(D).max():.2e}, "
+              f"sign changes {int((np.diff(np.sign(D)) != 0).sum())}", flush=True)
+        assert abs(Eed[0] - Eed[-1]) < 1e-9
+        if p < 0.3:
+            assert asym[p] > 0.01 and int((np.diff(np.sign(D)) != 0).sum()) == 1
+        else:
+            assert np.abs(D).max() < 1e-4 and np.abs(EF - Eed).max() < 5e-4
+    assert asym[0.1] > 100 * asym[0.4]
