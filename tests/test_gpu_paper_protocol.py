@@ -229,3 +229,32 @@ def test_2x2_against_ed():
         else:
             assert np.abs(D).max() < 1e-4 and np.abs(EF - Eed).max() < 5e-4
     assert asym[0.1] > 100 * asym[0.4]
+
+
+def test_critical_lines_from_red_paths():
+    """Sec. V: on the red paths (p = 0.5) the minimum of d2E/dg2 along the
+    last leg stays at g_c ~ 0.19 while r < 0.19 and follows g_c ~ r above
+    (tests/golden/paper_protocol.txt); seven paths run as one batch."""
+    G = golden()
+    rs = [0.03, 0.09, 0.13, 0.17, 0.22, 0.25, 0.28]
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C128)
+    every = 100
+    paths = []
+    for r in rs:
+        init, verts, steps = pr.red_path(0.5, r)
+        paths.append(z2h.make_path(verts, steps, pr.DT, sampling=1, every=every))
+    n = steps[-1] // every
+    print(f"case red-path sweep r = {rs}, {len(rs)} paths batched", flush=True)
+    _, tr = z2h.z2h_paths_evolve(plan, paths)
+    tr = tr.cpu().numpy()
+    found = []
+    for j, r in enumerate(rs):
+        g, E = last_leg_curve(tr[:, j, :], [n * every], every, 0.5)
+        x, d2 = pr.second_derivative(g, E, 10)
+        gc, _ = pr.extremum_in(x, d2, 0.05, 0.45, "min")
+        found.append(gc)
+        target = G["critical_g_low_r"] if r < G["critical_r_split"] else r
+        print(f"red path r={r}: minimum of d2E/dg2 at g = {gc:.4f} (expected about {target})", flush=True)
+    for r, gc in zip(rs, found):
+        target = G["critical_g_low_r"] if r < G["critical_r_split"] else r
+        assert abs(gc - target) < 0.01, (r, gc)
