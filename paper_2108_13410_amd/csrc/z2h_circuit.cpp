@@ -146,6 +146,34 @@ GateDev device_gate(const z2h_gate &g, int q0, int q1) {
     return d;
 }
 
+// Append gate x, acting on register bits b0 (and b1, a CNOT's target), in
+// the register kernels' form.  A CNOT right after another with the same
+// target (both at index >= from, i.e. in one phase) is composed into it:
+// the target flips with the parity of the XOR of their control masks, and
+// a mask that cancels to zero drops the gate.  Hadamards are counted for
+// the group's final scale.
+static void append_reg_gate(GateDev *out, int &n, int from, const z2h_gate &x, int b0, int b1, int &nh) {
+    if (x.kind == Z2H_GATE_CNOT) {
+        if (n > from && out[n - 1].kind == Z2H_GATE_CNOT && out[n - 1].q1 == b1) {
+            out[n - 1].q0 ^= 1 << b0;
+            if (out[n - 1].q0 == 0) --n;
+            return;
+        }
+        GateDev d;
+        memset(&d, 0, sizeof d);
+        d.kind = Z2H_GATE_CNOT;
+        d.q0 = 1 << b0;
+        d.q1 = b1;
+        out[n++] = d;
+        return;
+    }
+    if (x.kind == Z2H_GATE_H) ++nh;
+    out[n++] = device_gate(x, b0, 0);
+}
+
+// 2^(-h/2): the factor that the unscaled Hadamard butterflies leave out.
+static double hadamard_scale(int nh) { return std::ldexp(nh % 2 ? 1.0 / std::sqrt(2.0) : 1.0, -(nh / 2)); }
+
 z2h_status check_gates(int nq, const z2h_gate *g, int ng) {
     for (int i = 0; i < ng; ++i) {
         const int k = g[i].kind;
@@ -218,9 +246,9 @@ z2h_status run_fused(int nq, bool c128, void *st, double *parts, const z2h_gate 
                 a.cq[nc++] = q;
             }
         }
-        a.ngates = (int)group.size();
+        const int ng_src = (int)group.size();
         std::vector<int> bits;
-        int first = 0;
+        int first = 0, nd = 0, nh = 0;
         auto close = [&](int end) {
             std::vector<int> lay = bits;
             for (int b = mloc - 1; (int)lay.size() < kRegBits; --b)
@@ -232,15 +260,16 @@ z2h_status run_fused(int nq, bool c128, void *st, double *parts, const z2h_gate 
                 code |= (uint32_t)lay[b] << (4 * b);
                 rb[lay[b]] = b;
             }
-            a.phase[a.nphase++] = code | (uint32_t)end << 24;
+            const int from = nd;
             for (int i = first; i < end; ++i) {
                 const z2h_gate &x = g[group[i]];
-                a.gates[i] = device_gate(x, rb[loc[x.q0]], x.kind == Z2H_GATE_CNOT ? rb[loc[x.q1]] : 0);
+                append_reg_gate(a.gates, nd, from, x, rb[loc[x.q0]], x.kind == Z2H_GATE_CNOT ? rb[loc[x.q1]] : 0, nh);
             }
+            if (nd > from) a.phase[a.nphase++] = code | (uint32_t)nd << 24;
             first = end;
             bits.clear();
         };
-        for (int i = 0; i < a.ngates; ++i) {
+        for (int i = 0; i < ng_src; ++i) {
             const z2h_gate &x = g[group[i]];
             const int b0 = loc[x.q0], b1 = x.kind == Z2H_GATE_CNOT ? loc[x.q1] : b0;
             const bool h0 = std::find(bits.begin(), bits.end(), b0) != bits.end();
@@ -249,8 +278,10 @@ z2h_status run_fused(int nq, bool c128, void *st, double *parts, const z2h_gate 
             if (std::find(bits.begin(), bits.end(), b0) == bits.end()) bits.push_back(b0);
             if (std::find(bits.begin(), bits.end(), b1) == bits.end()) bits.push_back(b1);
         }
-        close(a.ngates);
-        hipError_t e = launch_fused(c128, a, s);
+        close(ng_src);
+        a.ngates = nd;
+        a.scale = hadamard_scale(nh);
+        hipError_t e = nd ? launch_fused(c128, a, s) : hipSuccess;
         if (e != hipSuccess) return fail(Z2H_ERR_HIP, "fused gate pass failed: %s", hipGetErrorString(e));
         reset();
         return Z2H_OK;
@@ -302,7 +333,6 @@ z2h_status run_reg(int nq, bool c128, void *st, double *parts, const z2h_gate *g
         a.state = st;
         a.nq = nq;
         a.nt = nt;
-        a.ngates = (int)group.size();
         int loc[kMaxCircuitQubits];
         for (int i = 0; i < kRegBits; ++i) {
             a.rq[i] = U[i];
@@ -316,11 +346,14 @@ z2h_status run_reg(int nq, bool c128, void *st, double *parts, const z2h_gate *g
             else
                 a.cq[c++] = q;
         }
-        for (int i = 0; i < a.ngates; ++i) {
+        int nd = 0, nh = 0;
+        for (int i = 0; i < (int)group.size(); ++i) {
             const z2h_gate &x = g[group[i]];
-            a.gates[i] = device_gate(x, loc[x.q0], x.kind == Z2H_GATE_CNOT ? loc[x.q1] : 0);
+            append_reg_gate(a.gates, nd, 0, x, loc[x.q0], x.kind == Z2H_GATE_CNOT ? loc[x.q1] : 0, nh);
         }
-        hipError_t e = launch_reg(c128, a, s);
+        a.ngates = nd;
+        a.scale = hadamard_scale(nh);
+        hipError_t e = nd ? launch_reg(c128, a, s) : hipSuccess;
         if (e != hipSuccess) return fail(Z2H_ERR_HIP, "register gate pass failed: %s", hipGetErrorString(e));
         U.clear();
         group.clear();

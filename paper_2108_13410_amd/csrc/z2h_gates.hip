@@ -110,21 +110,21 @@ template <typename Real>
 using Regs = typename RegFile<Real>::type;
 
 // The one-qubit gates in the forms their matrices have (the host builds
-// them so): H = r [[1, 1], [1, -1]]; R_x = [[c, i w], [i w, c]]; R_z =
-// diag(d0, d1).  Eight real operations per amplitude pair instead of the
-// sixteen of a general complex 2x2 matrix.
+// them so): H as the unscaled butterfly [[1, 1], [1, -1]] (the group's
+// amplitudes are scaled once at its end); R_x = [[c, i w], [i w, c]]; R_z =
+// diag(d0, d1).  Four or eight real operations per amplitude pair instead
+// of the sixteen of a general complex 2x2 matrix.
 template <typename Real, int B>
-__device__ __forceinline__ void reg_h(Regs<Real> &v, const double *m) {
-    const Real r = (Real)m[0];
+__device__ __forceinline__ void reg_h(Regs<Real> &v) {
 #pragma unroll
     for (int k = 0; k < (1 << kRegBits); ++k)
         if (!(k & (1 << B))) {
             const int j = k | (1 << B);
             const Real xr = v[2 * k], xi = v[2 * k + 1], yr = v[2 * j], yi = v[2 * j + 1];
-            v[2 * k] = r * (xr + yr);
-            v[2 * k + 1] = r * (xi + yi);
-            v[2 * j] = r * (xr - yr);
-            v[2 * j + 1] = r * (xi - yi);
+            v[2 * k] = xr + yr;
+            v[2 * k + 1] = xi + yi;
+            v[2 * j] = xr - yr;
+            v[2 * j + 1] = xi - yi;
         }
 }
 
@@ -165,30 +165,33 @@ __device__ __forceinline__ void reg_proj0(Regs<Real> &v) {
         }
 }
 
-template <typename Real, int C, int T>
+// CNOT with target bit T and control mask M: the target flips where the
+// parity of the control bits is odd (consecutive CNOTs with one target,
+// composed).
+template <typename Real, int T, int M>
 __device__ __forceinline__ void reg_cnot(Regs<Real> &v) {
-    if constexpr (C != T) {
 #pragma unroll
-        for (int k = 0; k < (1 << kRegBits); ++k)
-            if ((k & (1 << C)) && !(k & (1 << T))) {
-                const int j = k | (1 << T);
-                const Real x = v[2 * k], y = v[2 * k + 1];
-                v[2 * k] = v[2 * j];
-                v[2 * k + 1] = v[2 * j + 1];
-                v[2 * j] = x;
-                v[2 * j + 1] = y;
-            }
-    }
+    for (int k = 0; k < (1 << kRegBits); ++k)
+        if (!(k & (1 << T)) && (__builtin_popcount(k & M) & 1)) {
+            const int j = k | (1 << T);
+            const Real x = v[2 * k], y = v[2 * k + 1];
+            v[2 * k] = v[2 * j];
+            v[2 * k + 1] = v[2 * j + 1];
+            v[2 * j] = x;
+            v[2 * j + 1] = y;
+        }
 }
 
-template <typename Real, int C>
-__device__ __forceinline__ void reg_cnot_t(Regs<Real> &v, int t) {
-    switch (t) {
-        case 0: reg_cnot<Real, C, 0>(v); break;
-        case 1: reg_cnot<Real, C, 1>(v); break;
-        case 2: reg_cnot<Real, C, 2>(v); break;
-        case 3: reg_cnot<Real, C, 3>(v); break;
-        default: reg_cnot<Real, C, 4>(v); break;
+template <typename Real, int T, int M = 1>
+__device__ __forceinline__ void reg_cnot_m(Regs<Real> &v, int mask) {
+    if constexpr (M < (1 << kRegBits)) {
+        if constexpr (!(M & (1 << T))) {
+            if (mask == M) {
+                reg_cnot<Real, T, M>(v);
+                return;
+            }
+        }
+        reg_cnot_m<Real, T, M + 1>(v, mask);
     }
 }
 
@@ -196,12 +199,12 @@ template <typename Real>
 __device__ __forceinline__ void reg_gate(Regs<Real> &v, const GateDev &g) {
     static_assert(kRegBits == 5, "the switches below cover five register bits");
     if (g.kind == Z2H_GATE_CNOT) {
-        switch (g.q0) {
-            case 0: reg_cnot_t<Real, 0>(v, g.q1); break;
-            case 1: reg_cnot_t<Real, 1>(v, g.q1); break;
-            case 2: reg_cnot_t<Real, 2>(v, g.q1); break;
-            case 3: reg_cnot_t<Real, 3>(v, g.q1); break;
-            default: reg_cnot_t<Real, 4>(v, g.q1); break;
+        switch (g.q1) {
+            case 0: reg_cnot_m<Real, 0>(v, g.q0); break;
+            case 1: reg_cnot_m<Real, 1>(v, g.q0); break;
+            case 2: reg_cnot_m<Real, 2>(v, g.q0); break;
+            case 3: reg_cnot_m<Real, 3>(v, g.q0); break;
+            default: reg_cnot_m<Real, 4>(v, g.q0); break;
         }
     } else if (g.kind == Z2H_GATE_PROJ0) {
         switch (g.q0) {
@@ -213,11 +216,11 @@ __device__ __forceinline__ void reg_gate(Regs<Real> &v, const GateDev &g) {
         }
     } else if (g.kind == Z2H_GATE_H) {
         switch (g.q0) {
-            case 0: reg_h<Real, 0>(v, g.m); break;
-            case 1: reg_h<Real, 1>(v, g.m); break;
-            case 2: reg_h<Real, 2>(v, g.m); break;
-            case 3: reg_h<Real, 3>(v, g.m); break;
-            default: reg_h<Real, 4>(v, g.m); break;
+            case 0: reg_h<Real, 0>(v); break;
+            case 1: reg_h<Real, 1>(v); break;
+            case 2: reg_h<Real, 2>(v); break;
+            case 3: reg_h<Real, 3>(v); break;
+            default: reg_h<Real, 4>(v); break;
         }
     } else if (g.kind == Z2H_GATE_RX) {
         switch (g.q0) {
@@ -236,6 +239,12 @@ __device__ __forceinline__ void reg_gate(Regs<Real> &v, const GateDev &g) {
             default: reg_rz<Real, 4>(v, g.m); break;
         }
     }
+}
+
+template <typename Real>
+__device__ __forceinline__ void scale_regs(Regs<Real> &v, Real f) {
+#pragma unroll
+    for (int k = 0; k < (2 << kRegBits); ++k) v[k] *= f;
 }
 
 // Register k of a thread whose base index is `base`: the bits of k select
@@ -384,6 +393,7 @@ fused_kernel(FusedArgs a) {
             for (const int end = (int)(a.phase[p] >> 24); g < end; ++g) reg_gate<Real>(v, a.gates[g]);
         }
         if (cur != home) relayout<Real>(v, lds, t, cur, home);
+        if (a.scale != 1.0) scale_regs<Real>(v, (Real)a.scale);
         uint64_t base = tb | toff;
         // keeps the 32 store addresses from being computed before the gates
         asm volatile("" : "+v"(base));
@@ -409,6 +419,7 @@ __global__ void __launch_bounds__(256) reg_kernel(RegArgs a) {
         Regs<Real> v;
         load_regs<Real>(v, st, tb | tpart, off);
         for (int g = 0; g < a.ngates; ++g) reg_gate<Real>(v, a.gates[g]);
+        if (a.scale != 1.0) scale_regs<Real>(v, (Real)a.scale);
         uint64_t base = tb | tpart;
         asm volatile("" : "+v"(base));
         store_regs<Real>(v, st, base, off);

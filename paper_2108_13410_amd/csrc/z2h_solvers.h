@@ -140,10 +140,14 @@ constexpr int kRegBits = 5;         // qubits held in a thread's registers
 // packed 4 bits each, ascending, in bits 0..19 of phase[p], and applies the
 // gates up to index phase[p] >> 24 (exclusive).  Gate qubits are register
 // bit indices into the layout of their phase.  Loads and stores use the
-// home layout, the top kRegBits local bits.
+// home layout, the top kRegBits local bits.  In the register kernels a
+// CNOT's q0 is the mask of its control bits (the target flips with their
+// parity), and a Hadamard is the unscaled butterfly: the amplitudes are
+// multiplied by `scale` (2^(-h/2) for h Hadamards) after the last gate.
 struct FusedArgs {
     void *state;
     int32_t nq, m, ngates, nphase;
+    double scale;
     int32_t lq[16];
     int32_t cq[40];
     uint32_t phase[kFuseMaxGates];
@@ -158,11 +162,13 @@ static_assert(sizeof(FusedArgs) <= 4096, "kernel argument block");
 struct RegArgs {
     void *state;
     int32_t nq, nt, ngates, pad;
+    double scale;
     int32_t rq[kRegBits], pad2[3];
     int32_t tq[8];
     int32_t cq[40];
     GateDev gates[kFuseMaxGates];
 };
+static_assert(sizeof(RegArgs) <= 4096, "kernel argument block");
 
 hipError_t launch_gate(bool c128, void *state, int nq, const GateDev &g, hipStream_t s);
 hipError_t launch_reg(bool c128, const RegArgs &a, hipStream_t s);
