@@ -194,3 +194,43 @@ def test_random_gate_lists(nq, fuse, dtype):
     got = psi.cpu().numpy().astype(np.complex128)
     tol = 1e-12 if dtype == z2h.Z2H_C128 else 5e-6
     assert np.abs(got - ref).max() < tol
+
+
+def _lib_array(lib):
+    arr = (z2h.z2h_gate * len(lib))()
+    for a, (k, q0, q1, th) in zip(arr, lib):
+        a.kind, a.q0, a.q1, a.theta = k, q0, q1, th
+    return arr
+
+
+@pytest.mark.parametrize("nq", [12, 15])
+@pytest.mark.parametrize("fuse", [1, 2])
+@pytest.mark.parametrize("dtype", [z2h.Z2H_C128, z2h.Z2H_C64])
+def test_cnot_runs_and_hadamard_counts(nq, fuse, dtype):
+    """Runs of CNOTs with one target (composed by the register kernels),
+    including a control that cancels itself and a run that cancels
+    completely, between odd and even numbers of Hadamards per group, against
+    the oracle's gate-by-gate application."""
+    H, RX, RZ, CX = z2h.Z2H_GATE_H, z2h.Z2H_GATE_RX, z2h.Z2H_GATE_RZ, z2h.Z2H_GATE_CNOT
+    t, a, b, c = nq - 1, 1, 5, nq - 3
+    lib = [(H, a, 0, 0.0), (H, b, 0, 0.0), (H, c, 0, 0.0),
+           (CX, a, t, 0.0), (CX, b, t, 0.0), (CX, a, t, 0.0), (CX, c, t, 0.0),   # a cancels: mask b ^ c
+           (RZ, t, 0, 0.7),
+           (CX, c, t, 0.0), (CX, b, t, 0.0),
+           (CX, b, a, 0.0), (CX, b, a, 0.0),                                     # cancels completely
+           (H, a, 0, 0.0), (RX, b, 0, -0.4), (H, t, 0, 0.0),
+           (CX, t, b, 0.0), (CX, a, b, 0.0), (RZ, b, 0, 1.3), (CX, a, b, 0.0), (CX, t, b, 0.0),
+           (H, c, 0, 0.0), (H, b, 0, 0.0), (H, 0, 0, 0.0)]
+    name = {H: "H", RX: "RX", RZ: "RZ", CX: "CNOT"}
+    ora = [(name[k], (q0, q1)) if k == CX else ((name[k], (q0,)) if k == H else (name[k], (q0,), th))
+           for k, q0, q1, th in lib]
+    print(f"case CNOT runs nq={nq} fuse={fuse} dtype={dtype}", flush=True)
+    rng = np.random.default_rng(7 + nq)
+    x = rng.normal(size=1 << nq) + 1j * rng.normal(size=1 << nq)
+    x /= np.linalg.norm(x)
+    ref = circuit.apply(x, ora)
+    psi = torch.tensor(x, dtype=CDT[dtype], device="cuda")
+    run(nq, dtype, psi, _lib_array(lib), len(lib), fuse)
+    got = psi.cpu().numpy().astype(np.complex128)
+    tol = 1e-12 if dtype == z2h.Z2H_C128 else 2e-6
+    assert np.abs(got - ref).max() < tol
