@@ -501,13 +501,15 @@ z2h_status z2h_circuit_prep(int32_t Lx, int32_t Ly, int32_t which, z2h_gate *out
  * Apply gates[0..ngates) (host array, time order) to the state of nq qubits
  * (2^nq complex elements of dtype at d_state, 256-byte aligned; nq in
  * [2, 34]).  fuse 0: one kernel launch per gate (each a pass over the
- * state).  fuse 1: consecutive gates whose qubits fit one tile are applied
+ * state).  fuse 1 and 2 group the gates, and may move a gate ahead of gates
+ * on other qubits (with which it commutes); groups never cross a NORM gate.
+ * fuse 1: gates whose qubits fit one tile are applied
  * together, one pass per group; a tile always holds the four lowest qubits
  * (coalesced rows) and up to 8 (complex128) or 9 (complex64) others, each
  * thread holds 32 of its amplitudes in registers and the gates run there in
  * phases of at most five qubits, with layout changes through LDS; states of
- * fewer than 6 qubits use fuse 0.  fuse 2: consecutive gates on at most five
- * qubits are applied together in registers (each thread holds the 32
+ * fewer than 6 qubits use fuse 0.  fuse 2: gates on at most five qubits are
+ * applied together in registers (each thread holds the 32
  * amplitudes that differ in those qubits), one pass per group; states of
  * fewer than 11 qubits use fuse 1.
  * NORM gates end a group; NORM leaves a zero state zero.  Results agree

@@ -205,31 +205,91 @@ z2h_status run_unfused(int nq, bool c128, void *st, double *parts, const z2h_gat
     return Z2H_OK;
 }
 
-// Greedy grouping: consecutive gates join the current group while the union
-// of their qubits and the always-local low qubits fits the tile width.
-// Within a group, consecutive gates form a phase while the union of their
-// local bits fits the kRegBits register bits; a phase's layout is padded
-// with the highest local bits, so a phase on the top local bits needs no
-// change of layout.
+// Qubits a gate acts on, as a bit mask.
+static uint64_t gate_mask(const z2h_gate &x) {
+    return (1ull << x.q0) | (x.kind == Z2H_GATE_CNOT ? 1ull << x.q1 : 0ull);
+}
+
+// Groups of the gates g[lo, hi) (no renormalisation among them) for the
+// fused executors.  Each group is built by one scan over the gates not yet
+// placed, in their order: a gate joins if no skipped earlier gate shares a
+// qubit with it and the union of the group's qubits and `base` stays within
+// `limit` qubits.  A gate that does not join blocks its qubits for the rest
+// of the scan.  So a gate only ever moves ahead of gates on other qubits,
+// with which it commutes, and each group keeps the gates' relative order.
+// Rotation layers thereby join the gadget groups that touch their qubits.
+static std::vector<std::vector<int>> gate_groups(const z2h_gate *g, int lo, int hi, int limit, uint64_t base) {
+    std::vector<int> rest, left;
+    for (int i = lo; i < hi; ++i) rest.push_back(i);
+    std::vector<std::vector<int>> out;
+    while (!rest.empty()) {
+        std::vector<int> grp;
+        uint64_t used = base, blocked = 0;
+        left.clear();
+        for (int i : rest) {
+            const uint64_t m = gate_mask(g[i]);
+            if (!(m & blocked) && __builtin_popcountll(used | m) <= limit && (int)grp.size() < kFuseMaxGates) {
+                grp.push_back(i);
+                used |= m;
+            } else {
+                blocked |= m;
+                left.push_back(i);
+            }
+        }
+        out.push_back(std::move(grp));
+        rest.swap(left);
+    }
+    return out;
+}
+
+// Run the gate list in fused groups: each maximal run of gates between
+// renormalisations is grouped by gate_groups and handed group by group to
+// `pass` (group indices, union of the group's qubits); renormalisations run
+// in between.
+template <typename Pass>
+static z2h_status run_grouped(int nq, bool c128, void *st, double *parts, const z2h_gate *g, int ng, int limit,
+                              uint64_t base, hipStream_t s, Pass pass) {
+    int lo = 0;
+    for (int i = 0; i <= ng; ++i) {
+        if (i < ng && g[i].kind != Z2H_GATE_NORM) continue;
+        for (const std::vector<int> &grp : gate_groups(g, lo, i, limit, base)) {
+            uint64_t used = 0;
+            for (int j : grp) used |= gate_mask(g[j]);
+            z2h_status st_ = pass(grp, used);
+            if (st_) return st_;
+        }
+        if (i < ng) {
+            hipError_t e = launch_normalize(c128, st, nq, parts, gate_parts(nq), s);
+            if (e != hipSuccess) return fail(Z2H_ERR_HIP, "normalisation failed: %s", hipGetErrorString(e));
+        }
+        lo = i + 1;
+    }
+    return Z2H_OK;
+}
+
+// Tile groups: gate_groups with the tile width as the limit and the four
+// lowest qubits always in the tile (coalesced rows of 16 amplitudes); the
+// tile is padded with the lowest remaining qubits.  Within a group,
+// consecutive gates form a phase while the union of their local bits fits
+// the kRegBits register bits; a phase's layout is padded with the highest
+// local bits, so a phase on the top local bits needs no change of layout.
 z2h_status run_fused(int nq, bool c128, void *st, double *parts, const z2h_gate *g, int ng, hipStream_t s) {
     if (nq < kRegBits + 1) return run_unfused(nq, c128, st, parts, g, ng, s);
     const int mloc = std::min(nq, c128 ? 12 : 13);
     const int nbase = std::min(4, mloc);
-    std::vector<char> in(nq, 0);
-    std::vector<int> group;
-    int used = 0;
-    auto reset = [&]() {
-        std::fill(in.begin(), in.end(), 0);
-        for (int q = 0; q < nbase; ++q) in[q] = 1;
-        used = nbase;
-        group.clear();
-    };
-    auto flush = [&]() -> z2h_status {
-        if (group.empty()) return Z2H_OK;
-        for (int q = 0; q < nq && used < mloc; ++q)
+    const uint64_t base = (1ull << nbase) - 1ull;
+    auto pass = [&](const std::vector<int> &group, uint64_t used) -> z2h_status {
+        std::vector<char> in(nq, 0);
+        int nin = 0;
+        for (int q = 0; q < nq; ++q)
+            if ((used | base) >> q & 1ull) {
+                in[q] = 1;
+                ++nin;
+            }
+        for (int q = 0; q < nq && nin < mloc; ++q)
             if (!in[q]) {
                 in[q] = 1;
-                ++used;
+                ++nin;
             }
         FusedArgs a;
         memset(&a, 0, sizeof a);
@@ -283,46 +343,27 @@ z2h_status run_fused(int nq, bool c128, void *st, double *parts, const z2h_gate 
         a.scale = hadamard_scale(nh);
         hipError_t e = nd ? launch_fused(c128, a, s) : hipSuccess;
         if (e != hipSuccess) return fail(Z2H_ERR_HIP, "fused gate pass failed: %s", hipGetErrorString(e));
-        reset();
         return Z2H_OK;
     };
-    reset();
-    for (int i = 0; i < ng; ++i) {
-        z2h_status st_ = Z2H_OK;
-        if (g[i].kind == Z2H_GATE_NORM) {
-            if ((st_ = flush())) return st_;
-            hipError_t e = launch_normalize(c128, st, nq, parts, gate_parts(nq), s);
-            if (e != hipSuccess) return fail(Z2H_ERR_HIP, "normalisation failed: %s", hipGetErrorString(e));
-            continue;
-        }
-        int add = !in[g[i].q0];
-        if (g[i].kind == Z2H_GATE_CNOT && !in[g[i].q1] && g[i].q1 != g[i].q0) ++add;
-        if (used + add > mloc || (int)group.size() == kFuseMaxGates) {
-            if ((st_ = flush())) return st_;
-            add = !in[g[i].q0] + (g[i].kind == Z2H_GATE_CNOT && !in[g[i].q1]);
-        }
-        if (!in[g[i].q0]) in[g[i].q0] = 1;
-        if (g[i].kind == Z2H_GATE_CNOT) in[g[i].q1] = 1;
-        used += add;
-        group.push_back(i);
-    }
-    return flush();
+    return run_grouped(nq, c128, st, parts, g, ng, mloc, base, s, pass);
 }
 
-// Register groups: consecutive gates on at most kRegBits qubits, applied by
-// one pass in which every thread holds the amplitudes that differ in those
+// Register groups: gate_groups on at most kRegBits qubits, applied by one
+// pass in which every thread holds the amplitudes that differ in those
 // qubits.  The group's qubit set is padded with the highest remaining qubits
 // so that the 256 threads of a block cover the lowest ones (coalesced
 // access).  States of fewer than kRegBits + 6 qubits use tile groups instead.
 z2h_status run_reg(int nq, bool c128, void *st, double *parts, const z2h_gate *g, int ng, hipStream_t s) {
     if (nq < kRegBits + 6) return run_fused(nq, c128, st, parts, g, ng, s);
     const int nt = std::min(8, nq - kRegBits);
-    std::vector<int> U, group;
-    auto has = [&](int q) { return std::find(U.begin(), U.end(), q) != U.end(); };
-    auto flush = [&]() -> z2h_status {
-        if (group.empty()) return Z2H_OK;
+    auto pass = [&](const std::vector<int> &group, uint64_t used) -> z2h_status {
         std::vector<char> in(nq, 0);
-        for (int q : U) in[q] = 1;
+        std::vector<int> U;
+        for (int q = 0; q < nq; ++q)
+            if (used >> q & 1ull) {
+                in[q] = 1;
+                U.push_back(q);
+            }
         for (int q = nq - 1; (int)U.size() < kRegBits; --q)
             if (!in[q]) {
                 in[q] = 1;
@@ -355,27 +396,9 @@ z2h_status run_reg(int nq, bool c128, void *st, double *parts, const z2h_gate *g
         a.scale = hadamard_scale(nh);
         hipError_t e = nd ? launch_reg(c128, a, s) : hipSuccess;
         if (e != hipSuccess) return fail(Z2H_ERR_HIP, "register gate pass failed: %s", hipGetErrorString(e));
-        U.clear();
-        group.clear();
         return Z2H_OK;
     };
-    for (int i = 0; i < ng; ++i) {
-        z2h_status st_;
-        if (g[i].kind == Z2H_GATE_NORM) {
-            if ((st_ = flush())) return st_;
-            hipError_t e = launch_normalize(c128, st, nq, parts, gate_parts(nq), s);
-            if (e != hipSuccess) return fail(Z2H_ERR_HIP, "normalisation failed: %s", hipGetErrorString(e));
-            continue;
-        }
-        const bool cn = g[i].kind == Z2H_GATE_CNOT;
-        const int add = !has(g[i].q0) + (cn && !has(g[i].q1));
-        if ((int)U.size() + add > kRegBits || (int)group.size() == kFuseMaxGates)
-            if ((st_ = flush())) return st_;
-        if (!has(g[i].q0)) U.push_back(g[i].q0);
-        if (cn && !has(g[i].q1)) U.push_back(g[i].q1);
-        group.push_back(i);
-    }
-    return flush();
+    return run_grouped(nq, c128, st, parts, g, ng, kRegBits, 0ull, s, pass);
 }
 
 z2h_status run_gates(int nq, z2h_dtype dtype, void *d_state, void *d_ws, size_t ws_bytes, const z2h_gate *gates,
