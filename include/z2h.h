@@ -521,6 +521,18 @@ size_t z2h_gates_ws_bytes(int32_t nq);
 z2h_status z2h_gates_run(int32_t nq, z2h_dtype dtype, void *d_state, void *d_ws, size_t ws_bytes,
                          const z2h_gate *gates, int32_t ngates, int32_t fuse, void *stream);
 
+/*
+ * The passes z2h_gates_run would make for this gate list (host only, no
+ * device work): pass_of[i] (host array of ngates) receives the index of the
+ * pass that applies gates[i], counting each NORM gate as a pass of its own;
+ * *npasses the number of passes.  With fuse 0, or below the fused
+ * executors' minimum state sizes, every gate is its own pass.  Passes run
+ * in index order; gates within one pass keep their relative order.
+ * Errors: as z2h_gates_run's argument checks.
+ */
+z2h_status z2h_gates_schedule(int32_t nq, z2h_dtype dtype, const z2h_gate *gates, int32_t ngates, int32_t fuse,
+                              int32_t *pass_of, int32_t *npasses);
+
 /* The adiabatic ramp of the schedule at gate level: for each step
  * k_begin <= k < k_end, the circuit of z2h_circuit_step with the step's
  * couplings (x-type at sX[k] or s_k, z-type at sZ[k] or s_k), applied by

@@ -242,29 +242,57 @@ static std::vector<std::vector<int>> gate_groups(const z2h_gate *g, int lo, int 
     return out;
 }
 
-// Run the gate list in fused groups: each maximal run of gates between
-// renormalisations is grouped by gate_groups and handed group by group to
-// `pass` (group indices, union of the group's qubits); renormalisations run
-// in between.
-template <typename Pass>
-static z2h_status run_grouped(int nq, bool c128, void *st, double *parts, const z2h_gate *g, int ng, int limit,
-                              uint64_t base, hipStream_t s, Pass pass) {
+// The passes of a fused run: each maximal run of gates between
+// renormalisations is grouped by gate_groups; a renormalisation is a pass of
+// its own (a group holding just that gate).
+static std::vector<std::vector<int>> plan_passes(const z2h_gate *g, int ng, int limit, uint64_t base) {
+    std::vector<std::vector<int>> plan;
     int lo = 0;
     for (int i = 0; i <= ng; ++i) {
         if (i < ng && g[i].kind != Z2H_GATE_NORM) continue;
-        for (const std::vector<int> &grp : gate_groups(g, lo, i, limit, base)) {
-            uint64_t used = 0;
-            for (int j : grp) used |= gate_mask(g[j]);
-            z2h_status st_ = pass(grp, used);
-            if (st_) return st_;
-        }
-        if (i < ng) {
-            hipError_t e = launch_normalize(c128, st, nq, parts, gate_parts(nq), s);
-            if (e != hipSuccess) return fail(Z2H_ERR_HIP, "normalisation failed: %s", hipGetErrorString(e));
-        }
+        for (std::vector<int> &grp : gate_groups(g, lo, i, limit, base)) plan.push_back(std::move(grp));
+        if (i < ng) plan.push_back({i});
         lo = i + 1;
     }
+    return plan;
+}
+
+// Run the plan: each group goes to `pass` (group indices, union of the
+// group's qubits); renormalisations run in between.
+template <typename Pass>
+static z2h_status run_grouped(int nq, bool c128, void *st, double *parts, const z2h_gate *g, int ng, int limit,
+                              uint64_t base, hipStream_t s, Pass pass) {
+    for (const std::vector<int> &grp : plan_passes(g, ng, limit, base)) {
+        if (grp.size() == 1 && g[grp[0]].kind == Z2H_GATE_NORM) {
+            hipError_t e = launch_normalize(c128, st, nq, parts, gate_parts(nq), s);
+            if (e != hipSuccess) return fail(Z2H_ERR_HIP, "normalisation failed: %s", hipGetErrorString(e));
+            continue;
+        }
+        uint64_t used = 0;
+        for (int j : grp) used |= gate_mask(g[j]);
+        z2h_status st_ = pass(grp, used);
+        if (st_) return st_;
+    }
     return Z2H_OK;
+}
+
+// Qubit limit and always-local qubits of a fused executor (fuse 1: tile
+// groups, fuse 2: register groups) for nq qubits, after the fallbacks of
+// run_fused and run_reg; limit 0 means gate by gate.
+static void fused_limits(int nq, bool c128, int fuse, int *limit, uint64_t *base) {
+    if (fuse == 2 && nq >= kRegBits + 6) {
+        *limit = kRegBits;
+        *base = 0;
+        return;
+    }
+    if (fuse >= 1 && nq >= kRegBits + 1) {
+        const int mloc = std::min(nq, c128 ? 12 : 13);
+        *limit = mloc;
+        *base = (1ull << std::min(4, mloc)) - 1ull;
+        return;
+    }
+    *limit = 0;
+    *base = 0;
 }
 
 // Tile groups: gate_groups with the tile width as the limit and the four
@@ -275,9 +303,9 @@ static z2h_status run_grouped(int nq, bool c128, void *st, double *parts, const 
 // local bits, so a phase on the top local bits needs no change of layout.
 z2h_status run_fused(int nq, bool c128, void *st, double *parts, const z2h_gate *g, int ng, hipStream_t s) {
     if (nq < kRegBits + 1) return run_unfused(nq, c128, st, parts, g, ng, s);
-    const int mloc = std::min(nq, c128 ? 12 : 13);
-    const int nbase = std::min(4, mloc);
-    const uint64_t base = (1ull << nbase) - 1ull;
+    int mloc;
+    uint64_t base;
+    fused_limits(nq, c128, 1, &mloc, &base);
     auto pass = [&](const std::vector<int> &group, uint64_t used) -> z2h_status {
         std::vector<char> in(nq, 0);
         int nin = 0;
@@ -462,6 +490,34 @@ z2h_status z2h_gates_run(int32_t nq, z2h_dtype dtype, void *d_state, void *d_ws,
         return run_gates(nq, dtype, d_state, d_ws, ws_bytes, gates, ngates, fuse, (hipStream_t)stream);
     } catch (...) {
         return fail(Z2H_ERR_OOM, "exception in z2h_gates_run");
+    }
+}
+
+z2h_status z2h_gates_schedule(int32_t nq, z2h_dtype dtype, const z2h_gate *gates, int32_t ngates, int32_t fuse,
+                              int32_t *pass_of, int32_t *npasses) {
+    try {
+        if (nq < 2 || nq > kMaxCircuitQubits)
+            return fail(Z2H_ERR_INVALID, "nq = %d outside [2, %d]", nq, kMaxCircuitQubits);
+        if (dtype != Z2H_C64 && dtype != Z2H_C128) return fail(Z2H_ERR_INVALID, "unknown dtype %d", dtype);
+        if (fuse < 0 || fuse > 2) return fail(Z2H_ERR_INVALID, "fuse must be 0, 1 or 2");
+        if (ngates < 0 || (ngates > 0 && (!gates || !pass_of)) || !npasses) return fail(Z2H_ERR_INVALID, "arguments");
+        z2h_status st = check_gates(nq, gates, ngates);
+        if (st) return st;
+        int limit;
+        uint64_t base;
+        fused_limits(nq, dtype == Z2H_C128, fuse, &limit, &base);
+        if (limit == 0) {
+            for (int i = 0; i < ngates; ++i) pass_of[i] = i;
+            *npasses = ngates;
+            return Z2H_OK;
+        }
+        const std::vector<std::vector<int>> plan = plan_passes(gates, ngates, limit, base);
+        for (size_t p = 0; p < plan.size(); ++p)
+            for (int i : plan[p]) pass_of[i] = (int32_t)p;
+        *npasses = (int32_t)plan.size();
+        return Z2H_OK;
+    } catch (...) {
+        return fail(Z2H_ERR_OOM, "exception in z2h_gates_schedule");
     }
 }
 

@@ -132,6 +132,7 @@ SIGNATURES = {
     "z2h_circuit_prep": (_i32, [_i32, _i32, _i32, _P, _i32, ctypes.POINTER(_i32)]),
     "z2h_gates_ws_bytes": (_sz, [_i32]),
     "z2h_gates_run": (_i32, [_i32, _i32, _P, _P, _sz, _P, _i32, _i32, _P]),
+    "z2h_gates_schedule": (_i32, [_i32, _i32, _P, _i32, _i32, _P, _P]),
     "z2h_circuit_evolve": (_i32, [_i32, _i32, _i32, _P, _P, _sz, ctypes.POINTER(z2h_schedule), _i32, _P]),
     "z2h_paths_sizes": (_i32, [_P, _i32, _P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(_sz)]),
     "z2h_paths_evolve": (_i32, [_P, _i32, _P, _P, _sz, _P, _P, _i32, _P, _i32, _P, _P]),
@@ -479,6 +480,16 @@ def gates_to_list(arr, n):
 
 def z2h_gates_ws_bytes(nq):
     return int(lib().z2h_gates_ws_bytes(int(nq)))
+
+
+def z2h_gates_schedule(nq, dtype, gates, ngates, fuse=1):
+    """The passes z2h_gates_run would make (host only): (pass index of each
+    gate as a list, number of passes)."""
+    pass_of = (ctypes.c_int32 * max(int(ngates), 1))()
+    npasses = ctypes.c_int32()
+    _check(lib().z2h_gates_schedule(int(nq), int(dtype), gates, int(ngates), int(fuse), pass_of,
+                                    ctypes.byref(npasses)))
+    return list(pass_of[:int(ngates)]), npasses.value
 
 
 def z2h_gates_run(nq, dtype, state, ws, gates, ngates, fuse=1, stream=None):

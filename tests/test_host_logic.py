@@ -483,3 +483,83 @@ def test_exact_solver_workspace_checks():
     assert code == -6
     code = L.z2h_hamiltonian_apply(plan.handle, v, ctypes.c_void_p((1 << 40) + 256), ctypes.byref(H), None)
     assert code == -1 and b"overlap" in L.z2h_last_error()
+
+
+def _gate_array(lib_gates):
+    arr = (z2h.z2h_gate * max(len(lib_gates), 1))()
+    for a, (k, q0, q1, th) in zip(arr, lib_gates):
+        a.kind, a.q0, a.q1, a.theta = k, q0, q1, th
+    return arr
+
+
+def test_gate_schedule_pass_counts():
+    """Commutation-aware grouping of the 4x4 Trotter-step circuit (928 gates,
+    33 qubits): 32 tile passes in complex64 (tile of 13 qubits), 33 in
+    complex128 (12), 71 register passes (five qubits; one per gadget, 64, is
+    the floor), every gate its own pass gate by gate."""
+    arr, ng = z2h.z2h_circuit_step(4, 4, (0.5, 0.5, 0.3, 0.2), (0.5, 0.5, 0.3, 0.2), 0.1)
+    assert ng == 928
+    assert z2h.z2h_gates_schedule(33, z2h.Z2H_C64, arr, ng, 1)[1] == 32
+    assert z2h.z2h_gates_schedule(33, z2h.Z2H_C128, arr, ng, 1)[1] == 33
+    assert z2h.z2h_gates_schedule(33, z2h.Z2H_C64, arr, ng, 2)[1] == 71
+    assert z2h.z2h_gates_schedule(33, z2h.Z2H_C64, arr, ng, 0) == (list(range(928)), 928)
+
+
+@pytest.mark.parametrize("nq,fuse,dtype", [(12, 1, 0), (12, 2, 0), (15, 1, 1), (16, 2, 1), (8, 2, 0), (5, 1, 0)])
+def test_gate_schedule_is_a_valid_reordering(nq, fuse, dtype):
+    """Random gate lists with renormalisations: a gate never passes an
+    earlier gate on one of its qubits, renormalisations are passes of their
+    own that nothing crosses, each pass fits the executor's qubit limit, and
+    applying the gates in executed order (pass, then index) gives the state
+    of the written order (oracle circuit application)."""
+    from oracle import circuit
+    rng = np.random.default_rng(77 + nq + 10 * fuse)
+    tile = min(nq, {0: 13, 1: 12}[dtype])
+    K = 5 if (fuse == 2 and nq >= 11) else tile
+    base = 0xF if (fuse == 1 or nq < 11) else 0
+    lib, ora = [], []
+    for i in range(160):
+        r = rng.random()
+        if i in (50, 51, 120):
+            lib.append((z2h.Z2H_GATE_NORM, 0, 0, 0.0))
+            ora.append(("NORM", ()))
+        elif r < 0.4:
+            c, t = (int(x) for x in rng.choice(nq, 2, replace=False))
+            lib.append((z2h.Z2H_GATE_CNOT, c, t, 0.0))
+            ora.append(("CNOT", (c, t)))
+        else:
+            q, th = int(rng.integers(nq)), float(rng.uniform(-2, 2))
+            k = ("H", "RX", "RZ")[int(rng.integers(3))]
+            lib.append(({"H": z2h.Z2H_GATE_H, "RX": z2h.Z2H_GATE_RX, "RZ": z2h.Z2H_GATE_RZ}[k], q, 0, th))
+            ora.append((k, (q,)) if k == "H" else (k, (q,), th))
+    pass_of, npasses = z2h.z2h_gates_schedule(nq, dtype, _gate_array(lib), len(lib), fuse)
+    assert sorted(set(pass_of)) == list(range(npasses))
+    if nq < 6:
+        assert pass_of == list(range(len(lib)))
+        return
+
+    def qubits(g):
+        k, q0, q1, _ = g
+        return {q0, q1} if k == z2h.Z2H_GATE_CNOT else {q0}
+    for i, gi in enumerate(lib):
+        for j in range(i + 1, len(lib)):
+            gj = lib[j]
+            if gi[0] == z2h.Z2H_GATE_NORM or gj[0] == z2h.Z2H_GATE_NORM:
+                assert pass_of[i] < pass_of[j]
+            elif qubits(gi) & qubits(gj):
+                assert pass_of[i] <= pass_of[j]
+    for p in range(npasses):
+        members = [lib[i] for i in range(len(lib)) if pass_of[i] == p]
+        if members[0][0] == z2h.Z2H_GATE_NORM:
+            assert len(members) == 1
+            continue
+        used = base
+        for g in members:
+            for q in qubits(g):
+                used |= 1 << q
+        assert bin(used).count("1") <= K
+    order = sorted(range(len(lib)), key=lambda i: (pass_of[i], i))
+    x = rng.normal(size=1 << nq) + 1j * rng.normal(size=1 << nq)
+    a = circuit.apply(x, ora)
+    b = circuit.apply(x, [ora[i] for i in order])
+    assert np.abs(a - b).max() < 1e-12
