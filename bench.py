@@ -541,14 +541,21 @@ def circuit_leg(z2h, torch, with_4x4=False):
     ng = z2h.z2h_circuit_step(3, 3, c0, c0, dt)[1]
     a, b, r, c = gate_level(3, 3, z2h.Z2H_C128, 0, 10), gate_level(3, 3, z2h.Z2H_C128, 1, 20), \
         gate_level(3, 3, z2h.Z2H_C128, 2, 20), trotter_path(3, 3, z2h.Z2H_C128, 200)
-    out["3x3_c128"] = {"gates_per_step": ng, "gate_by_gate_ms_per_step": a * 1e3, "lds_groups_ms_per_step": b * 1e3,
+    arr3 = z2h.z2h_circuit_step(3, 3, c0, c0, dt)[0]
+    passes3 = {f: z2h.z2h_gates_schedule(19, z2h.Z2H_C128, arr3, ng, f)[1] for f in (1, 2)}
+    out["3x3_c128"] = {"gates_per_step": ng, "tile_passes_per_step": passes3[1],
+                       "register_passes_per_step": passes3[2],
+                       "gate_by_gate_ms_per_step": a * 1e3, "lds_groups_ms_per_step": b * 1e3,
                        "register_groups_ms_per_step": r * 1e3, "trotter_path_ms_per_step": c * 1e3,
                        "trotter_path_speedup_over_best_gates": min(b, r) / c}
     if with_4x4:
         ng4 = z2h.z2h_circuit_step(4, 4, c0, c0, dt)[1]
         b4, r4, c4 = gate_level(4, 4, z2h.Z2H_C64, 1, 1), gate_level(4, 4, z2h.Z2H_C64, 2, 1), \
             trotter_path(4, 4, z2h.Z2H_C64, 3)
-        out["4x4_c64"] = {"gates_per_step": ng4, "lds_groups_ms_per_step": b4 * 1e3,
+        arr4 = z2h.z2h_circuit_step(4, 4, c0, c0, dt)[0]
+        passes4 = {f: z2h.z2h_gates_schedule(33, z2h.Z2H_C64, arr4, ng4, f)[1] for f in (1, 2)}
+        out["4x4_c64"] = {"gates_per_step": ng4, "tile_passes_per_step": passes4[1],
+                          "register_passes_per_step": passes4[2], "lds_groups_ms_per_step": b4 * 1e3,
                           "register_groups_ms_per_step": r4 * 1e3, "trotter_path_ms_per_step": c4 * 1e3,
                           "trotter_path_speedup_over_best_gates": min(b4, r4) / c4}
     return out
