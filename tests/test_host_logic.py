@@ -563,3 +563,29 @@ def test_gate_schedule_is_a_valid_reordering(nq, fuse, dtype):
     a = circuit.apply(x, ora)
     b = circuit.apply(x, [ora[i] for i in order])
     assert np.abs(a - b).max() < 1e-12
+
+
+def test_gate_schedule_validation():
+    """z2h_gates_schedule rejects what z2h_gates_run rejects, and NULL
+    outputs; a valid call writes one pass index per gate."""
+    G = z2h.z2h_gate
+    L = z2h.lib()
+    out = (ctypes.c_int32 * 4)()
+    npass = ctypes.c_int32()
+
+    def sched(nq, gates, fuse=1, dtype=z2h.Z2H_C64, pass_of=out, np_=ctypes.byref(npass)):
+        arr = (G * max(len(gates), 1))(*[G(*g) for g in gates])
+        return L.z2h_gates_schedule(nq, dtype, arr, len(gates), fuse, pass_of, np_)
+
+    h0 = (z2h.Z2H_GATE_H, 0, 0, 0, 0.0)
+    assert sched(12, [(z2h.Z2H_GATE_H, 12, 0, 0, 0.0)]) == -1     # qubit out of range
+    assert sched(12, [(z2h.Z2H_GATE_CNOT, 3, 3, 0, 0.0)]) == -1   # control == target
+    assert sched(12, [h0], fuse=3) == -1                            # unknown executor
+    assert sched(12, [h0], dtype=7) == -1                           # unknown dtype
+    assert sched(1, [h0]) == -1 and sched(35, [h0]) == -1            # nq out of range
+    assert sched(12, [h0], pass_of=None) == -1                      # NULL output
+    assert sched(12, [h0], np_=None) == -1
+    assert sched(12, []) == 0 and npass.value == 0                   # empty list
+    gates = [h0, (z2h.Z2H_GATE_CNOT, 0, 11, 0, 0.0), (z2h.Z2H_GATE_NORM, 0, 0, 0, 0.0), (z2h.Z2H_GATE_RZ, 5, 0, 0, 0.3)]
+    assert sched(12, gates) == 0 and npass.value == 3 and list(out) == [0, 0, 1, 2]
+    assert sched(12, gates, fuse=0) == 0 and npass.value == 4 and list(out) == [0, 1, 2, 3]
