@@ -116,6 +116,38 @@ def test_gate_level_ramp_equals_fused_trotter_path(fuse):
 
 @pytest.mark.slow
 @pytest.mark.parametrize("fuse", [1, 2])
+def test_gate_level_4x4_with_ancilla_c128(fuse):
+    """33 qubits in complex128 (128 GiB, with the 64 GiB Trotter-path state
+    beside it): two steps of the 4x4 ramp from psi_1 against the complex128
+    Trotter path on 2^16 sampled link amplitudes (1e-11 of the largest) and
+    the ancilla half on 2^16 samples."""
+    Lx, Ly, n, M, dt = 4, 4, 32, 200, 0.1
+    c0, c1 = (0.5, 0.5, 0.0, 0.0), (0.5, 0.5, 0.4, 0.3)
+    print(f"case gate-level 4x4 + ancilla c128 fuse={fuse}", flush=True)
+    torch.cuda.empty_cache()
+    plan = z2h.z2h_plan_create(Lx, Ly, z2h.Z2H_C128)
+    phi = z2h.alloc_state(plan)
+    z2h.z2h_state_init(plan, phi, z2h.Z2H_INIT_PSI1)
+    psi = torch.zeros(1 << (n + 1), dtype=torch.complex128, device="cuda")
+    psi[: 1 << n].copy_(phi)
+    ws = z2h.alloc_bytes(z2h.z2h_gates_ws_bytes(n + 1))
+    z2h.z2h_circuit_evolve(Lx, Ly, z2h.Z2H_C128, psi, ws, z2h.schedule(c0, c1, M, dt, k_end=2), fuse=fuse)
+    sz = z2h.z2h_plan_sizes(plan)
+    z2h.z2h_evolve(plan, phi, z2h.alloc_bytes(sz["ws_evolve"]), z2h.schedule(c0, c1, M, dt, k_end=2))
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(10)
+    idx = torch.tensor(rng.integers(0, 1 << n, 1 << 16), device="cuda")
+    a, b = psi[idx].cpu().numpy(), phi[idx].cpu().numpy()
+    scale = np.abs(b).max()
+    assert np.abs(a - b).max() < 1e-11 * scale
+    anc = psi[idx + (1 << n)].cpu().numpy()
+    assert np.abs(anc).max() < 1e-11 * scale
+    del psi, phi
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("fuse", [1, 2])
 def test_gate_level_4x4_with_ancilla(fuse):
     """33 qubits in complex64 (64 GiB), LDS or register gate groups: two
     steps of the 4x4 ramp from psi_1 against the Trotter path (complex64) on
