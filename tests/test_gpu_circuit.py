@@ -266,3 +266,41 @@ def test_cnot_runs_and_hadamard_counts(nq, fuse, dtype):
     got = psi.cpu().numpy().astype(np.complex128)
     tol = 1e-12 if dtype == z2h.Z2H_C128 else 2e-6
     assert np.abs(got - ref).max() < tol
+
+
+@pytest.mark.slow
+@pytest.mark.parametrize("fuse", [0, 1, 2])
+def test_max_qubits_circuit_then_inverse(fuse):
+    """34 qubits, the largest state the gate API accepts (complex64,
+    128 GiB): a random circuit on qubits spread over the whole index
+    (including the top qubit, 64 GiB apart) changes the state, and the
+    inverse circuit (reversed, angles negated) restores 2^16 sampled
+    amplitudes to 1e-4 of the largest."""
+    nq = 34
+    H, RX, RZ, CX = z2h.Z2H_GATE_H, z2h.Z2H_GATE_RX, z2h.Z2H_GATE_RZ, z2h.Z2H_GATE_CNOT
+    rng = np.random.default_rng(34 + fuse)
+    pool = [0, 1, 2, 5, 9, 14, 20, 27, 31, 32, 33]
+    fwd = []
+    for _ in range(40 if fuse else 12):
+        if rng.random() < 0.4:
+            c, t = (int(q) for q in rng.choice(pool, 2, replace=False))
+            fwd.append((CX, c, t, 0.0))
+        else:
+            fwd.append(((H, RX, RZ)[int(rng.integers(3))], int(rng.choice(pool)), 0, float(rng.uniform(-2, 2))))
+    inv = [(k, q0, q1, -th if k in (RX, RZ) else 0.0) for k, q0, q1, th in reversed(fwd)]
+    print(f"case 34 qubits circuit and inverse fuse={fuse}", flush=True)
+    torch.cuda.empty_cache()
+    psi = torch.randn(1 << nq, dtype=torch.complex64, device="cuda")
+    idx = torch.tensor(rng.integers(0, 1 << nq, 1 << 16), device="cuda")
+    idx[:4] = torch.tensor([0, (1 << nq) - 1, 1 << 33, (1 << 33) - 1], device="cuda")
+    before = psi[idx].cpu().numpy()
+    ws = z2h.alloc_bytes(z2h.z2h_gates_ws_bytes(nq))
+    z2h.z2h_gates_run(nq, z2h.Z2H_C64, psi, ws, _lib_array(fwd), len(fwd), fuse=fuse)
+    mid = psi[idx].cpu().numpy()
+    z2h.z2h_gates_run(nq, z2h.Z2H_C64, psi, ws, _lib_array(inv), len(inv), fuse=fuse)
+    after = psi[idx].cpu().numpy()
+    scale = np.abs(before).max()
+    assert np.abs(mid - before).max() > 0.1 * scale
+    assert np.abs(after - before).max() < 1e-4 * scale
+    del psi
+    torch.cuda.empty_cache()
