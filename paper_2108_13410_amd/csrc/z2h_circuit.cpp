@@ -295,83 +295,93 @@ static void fused_limits(int nq, bool c128, int fuse, int *limit, uint64_t *base
     *base = 0;
 }
 
+// One tile-group pass: the tile holds the group's qubits `used`, the four
+// lowest qubits (coalesced rows of 16 amplitudes) and, as padding, the
+// lowest remaining qubits, mloc in all.  Within the group, consecutive gates
+// form a phase while the union of their local bits fits the kRegBits
+// register bits; a phase's layout is padded with the highest local bits, so
+// a phase on the top local bits needs no change of layout.
+static z2h_status tile_pass(int nq, bool c128, void *st, const z2h_gate *g, const std::vector<int> &group,
+                            uint64_t used, hipStream_t s) {
+    int mloc;
+    uint64_t base;
+    fused_limits(nq, c128, 1, &mloc, &base);
+    std::vector<char> in(nq, 0);
+    int nin = 0;
+    for (int q = 0; q < nq; ++q)
+        if ((used | base) >> q & 1ull) {
+            in[q] = 1;
+            ++nin;
+        }
+    for (int q = 0; q < nq && nin < mloc; ++q)
+        if (!in[q]) {
+            in[q] = 1;
+            ++nin;
+        }
+    FusedArgs a;
+    memset(&a, 0, sizeof a);
+    a.state = st;
+    a.nq = nq;
+    a.m = mloc;
+    int loc[kMaxCircuitQubits];
+    int nl = 0, nc = 0;
+    for (int q = 0; q < nq; ++q) {
+        if (in[q]) {
+            loc[q] = nl;
+            a.lq[nl++] = q;
+        } else {
+            a.cq[nc++] = q;
+        }
+    }
+    const int ng_src = (int)group.size();
+    std::vector<int> bits;
+    int first = 0, nd = 0, nh = 0;
+    auto close = [&](int end) {
+        std::vector<int> lay = bits;
+        for (int b = mloc - 1; (int)lay.size() < kRegBits; --b)
+            if (std::find(lay.begin(), lay.end(), b) == lay.end()) lay.push_back(b);
+        std::sort(lay.begin(), lay.end());
+        uint32_t code = 0;
+        int rb[16];
+        for (int b = 0; b < kRegBits; ++b) {
+            code |= (uint32_t)lay[b] << (4 * b);
+            rb[lay[b]] = b;
+        }
+        const int from = nd;
+        for (int i = first; i < end; ++i) {
+            const z2h_gate &x = g[group[i]];
+            append_reg_gate(a.gates, nd, from, x, rb[loc[x.q0]], x.kind == Z2H_GATE_CNOT ? rb[loc[x.q1]] : 0, nh);
+        }
+        if (nd > from) a.phase[a.nphase++] = code | (uint32_t)nd << 24;
+        first = end;
+        bits.clear();
+    };
+    for (int i = 0; i < ng_src; ++i) {
+        const z2h_gate &x = g[group[i]];
+        const int b0 = loc[x.q0], b1 = x.kind == Z2H_GATE_CNOT ? loc[x.q1] : b0;
+        const bool h0 = std::find(bits.begin(), bits.end(), b0) != bits.end();
+        const bool h1 = b1 == b0 || std::find(bits.begin(), bits.end(), b1) != bits.end();
+        if ((int)bits.size() + !h0 + !h1 > kRegBits) close(i);
+        if (std::find(bits.begin(), bits.end(), b0) == bits.end()) bits.push_back(b0);
+        if (std::find(bits.begin(), bits.end(), b1) == bits.end()) bits.push_back(b1);
+    }
+    close(ng_src);
+    a.ngates = nd;
+    a.scale = hadamard_scale(nh);
+    hipError_t e = nd ? launch_fused(c128, a, s) : hipSuccess;
+    if (e != hipSuccess) return fail(Z2H_ERR_HIP, "fused gate pass failed: %s", hipGetErrorString(e));
+    return Z2H_OK;
+}
+
 // Tile groups: gate_groups with the tile width as the limit and the four
-// lowest qubits always in the tile (coalesced rows of 16 amplitudes); the
-// tile is padded with the lowest remaining qubits.  Within a group,
-// consecutive gates form a phase while the union of their local bits fits
-// the kRegBits register bits; a phase's layout is padded with the highest
-// local bits, so a phase on the top local bits needs no change of layout.
+// lowest qubits always in the tile.
 z2h_status run_fused(int nq, bool c128, void *st, double *parts, const z2h_gate *g, int ng, hipStream_t s) {
     if (nq < kRegBits + 1) return run_unfused(nq, c128, st, parts, g, ng, s);
     int mloc;
     uint64_t base;
     fused_limits(nq, c128, 1, &mloc, &base);
     auto pass = [&](const std::vector<int> &group, uint64_t used) -> z2h_status {
-        std::vector<char> in(nq, 0);
-        int nin = 0;
-        for (int q = 0; q < nq; ++q)
-            if ((used | base) >> q & 1ull) {
-                in[q] = 1;
-                ++nin;
-            }
-        for (int q = 0; q < nq && nin < mloc; ++q)
-            if (!in[q]) {
-                in[q] = 1;
-                ++nin;
-            }
-        FusedArgs a;
-        memset(&a, 0, sizeof a);
-        a.state = st;
-        a.nq = nq;
-        a.m = mloc;
-        int loc[kMaxCircuitQubits];
-        int nl = 0, nc = 0;
-        for (int q = 0; q < nq; ++q) {
-            if (in[q]) {
-                loc[q] = nl;
-                a.lq[nl++] = q;
-            } else {
-                a.cq[nc++] = q;
-            }
-        }
-        const int ng_src = (int)group.size();
-        std::vector<int> bits;
-        int first = 0, nd = 0, nh = 0;
-        auto close = [&](int end) {
-            std::vector<int> lay = bits;
-            for (int b = mloc - 1; (int)lay.size() < kRegBits; --b)
-                if (std::find(lay.begin(), lay.end(), b) == lay.end()) lay.push_back(b);
-            std::sort(lay.begin(), lay.end());
-            uint32_t code = 0;
-            int rb[16];
-            for (int b = 0; b < kRegBits; ++b) {
-                code |= (uint32_t)lay[b] << (4 * b);
-                rb[lay[b]] = b;
-            }
-            const int from = nd;
-            for (int i = first; i < end; ++i) {
-                const z2h_gate &x = g[group[i]];
-                append_reg_gate(a.gates, nd, from, x, rb[loc[x.q0]], x.kind == Z2H_GATE_CNOT ? rb[loc[x.q1]] : 0, nh);
-            }
-            if (nd > from) a.phase[a.nphase++] = code | (uint32_t)nd << 24;
-            first = end;
-            bits.clear();
-        };
-        for (int i = 0; i < ng_src; ++i) {
-            const z2h_gate &x = g[group[i]];
-            const int b0 = loc[x.q0], b1 = x.kind == Z2H_GATE_CNOT ? loc[x.q1] : b0;
-            const bool h0 = std::find(bits.begin(), bits.end(), b0) != bits.end();
-            const bool h1 = b1 == b0 || std::find(bits.begin(), bits.end(), b1) != bits.end();
-            if ((int)bits.size() + !h0 + !h1 > kRegBits) close(i);
-            if (std::find(bits.begin(), bits.end(), b0) == bits.end()) bits.push_back(b0);
-            if (std::find(bits.begin(), bits.end(), b1) == bits.end()) bits.push_back(b1);
-        }
-        close(ng_src);
-        a.ngates = nd;
-        a.scale = hadamard_scale(nh);
-        hipError_t e = nd ? launch_fused(c128, a, s) : hipSuccess;
-        if (e != hipSuccess) return fail(Z2H_ERR_HIP, "fused gate pass failed: %s", hipGetErrorString(e));
-        return Z2H_OK;
+        return tile_pass(nq, c128, st, g, group, used, s);
     };
     return run_grouped(nq, c128, st, parts, g, ng, mloc, base, s, pass);
 }
@@ -385,6 +395,11 @@ z2h_status run_reg(int nq, bool c128, void *st, double *parts, const z2h_gate *g
     if (nq < kRegBits + 6) return run_fused(nq, c128, st, parts, g, ng, s);
     const int nt = std::min(8, nq - kRegBits);
     auto pass = [&](const std::vector<int> &group, uint64_t used) -> z2h_status {
+        // With qubits 0, 1 and 2 in the registers, a wave's lanes would lie
+        // at least 64 B apart and every line would be assembled from several
+        // loads and stores; the tile kernel applies such a group with
+        // coalesced rows instead (the group also fits its tile).
+        if ((used & 7ull) == 7ull) return tile_pass(nq, c128, st, g, group, used, s);
         std::vector<char> in(nq, 0);
         std::vector<int> U;
         for (int q = 0; q < nq; ++q)
