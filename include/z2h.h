@@ -510,8 +510,9 @@ z2h_status z2h_circuit_prep(int32_t Lx, int32_t Ly, int32_t which, z2h_gate *out
  * phases of at most five qubits, with layout changes through LDS; states of
  * fewer than 6 qubits use fuse 0.  fuse 2: gates on at most five qubits are
  * applied together in registers (each thread holds the 32
- * amplitudes that differ in those qubits), one pass per group; states of
- * fewer than 11 qubits use fuse 1.
+ * amplitudes that differ in those qubits), one pass per group (a group
+ * holding qubits 0, 1 and 2 runs as a tile group, with coalesced rows);
+ * states of fewer than 11 qubits use fuse 1.
  * NORM gates end a group; NORM leaves a zero state zero.  Results agree
  * with fuse 0 to rounding.  d_ws: z2h_gates_ws_bytes bytes (norm partials).
  * Errors: Z2H_ERR_INVALID (qubit out of range, q0 == q1 for CNOT, unknown
