@@ -387,6 +387,13 @@ def z2h_lanczos_ground(plan, v, ws, H, max_iter=300, tol=1e-13, stream=None):
     return e0.value, it.value, a[:it.value].copy(), b[:it.value].copy()
 
 
+def z2h_lanczos_vector_sizes(plan, iters):
+    """Workspace bytes of z2h_lanczos_vector for a recurrence of iters steps."""
+    n = ctypes.c_size_t()
+    _check(lib().z2h_lanczos_vector_sizes(plan.handle, int(iters), ctypes.byref(n)))
+    return n.value
+
+
 def z2h_lanczos_vector(plan, v, H, alpha, beta, stream=None):
     """Ground-state vector into v (which must hold the start vector of the
     z2h_lanczos_ground run that produced alpha, beta).  Returns (energy,
@@ -500,6 +507,15 @@ def z2h_gates_run(nq, dtype, state, ws, gates, ngates, fuse=1, stream=None):
 def z2h_circuit_evolve(Lx, Ly, dtype, state, ws, sched, fuse=1, stream=None):
     _check(lib().z2h_circuit_evolve(int(Lx), int(Ly), int(dtype), _ptr(state), _ptr(ws),
                                     ws.numel() * ws.element_size(), ctypes.byref(sched), int(fuse), _stream(stream)))
+
+
+def z2h_paths_sizes(plan, paths):
+    """(trace samples, workspace bytes) of z2h_paths_evolve for these paths."""
+    arr = (z2h_path * len(paths))(*paths)
+    ns = ctypes.c_int64()
+    wsb = ctypes.c_size_t()
+    _check(lib().z2h_paths_sizes(plan.handle, len(paths), arr, ctypes.byref(ns), ctypes.byref(wsb)))
+    return ns.value, wsb.value
 
 
 def z2h_paths_evolve(plan, paths, states=None, inits=None, zmasks=None, xmasks=None, stream=None):

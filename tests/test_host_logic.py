@@ -589,3 +589,24 @@ def test_gate_schedule_validation():
     gates = [h0, (z2h.Z2H_GATE_CNOT, 0, 11, 0, 0.0), (z2h.Z2H_GATE_NORM, 0, 0, 0, 0.0), (z2h.Z2H_GATE_RZ, 5, 0, 0, 0.3)]
     assert sched(12, gates) == 0 and npass.value == 3 and list(out) == [0, 0, 1, 2]
     assert sched(12, gates, fuse=0) == 0 and npass.value == 4 and list(out) == [0, 1, 2, 3]
+
+
+def test_binding_covers_the_header():
+    """Every function declared in include/z2h.h has a ctypes signature and a
+    wrapper of the same name in the Python binding."""
+    hdr = open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "..", "include", "z2h.h")).read()
+    names = set(re.findall(r"^\s*(?:z2h_status|size_t|int32_t|const char \*|void|double|uint64_t)\s+\**(z2h_[a-z0-9_]+)\s*\(",
+                           hdr, re.M))
+    assert len(names) > 40
+    src = open(z2h.__file__).read()
+    assert not [n for n in names if f'"{n}"' not in src]
+    assert not [n for n in names if not callable(getattr(z2h, n, None))]
+
+
+def test_size_queries_through_the_binding():
+    """The two size queries other wrappers use internally, called directly."""
+    plan = z2h.z2h_plan_create(3, 3, z2h.Z2H_C128)
+    assert z2h.z2h_lanczos_vector_sizes(plan, 40) > 0
+    p = z2h.make_path([(1, 1, 0, 0), (1, 1, 0.3, 0.3)], [100], 0.02, every=10)
+    samples, ws = z2h.z2h_paths_sizes(plan, [p, p])
+    assert samples == 11 and ws > 0
