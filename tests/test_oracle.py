@@ -523,3 +523,129 @@ def test_circuit_gate_count():
         n, nv = 2 * Lx * Ly, Lx * Ly
         assert len(circuit.step_gates(Lx, Ly, (1, 1, 0.1, 0.1), (1, 1, 0.1, 0.1), 0.1)) == 3 * n + 2 * 26 * nv
     assert 3 * 18 + 2 * 26 * 9 == 522
+
+
+# ------------------------------------------------------------------ schedule branches of the ramp (Sec. III, Appendix)
+
+def _single_link_ramp(c0, c1, M, dt, sx_of, sz_of):
+    """Closed form of one decoupled link (JA = JB = 0): per step the x-field
+    half, the full z-field factor and the x-field half again (Sec. III), with
+    the x field taken at sx_of(k) and the z field at sz_of(k).  Matrices come
+    from scipy's expm of the 2x2 Pauli generators, not from the oracle."""
+    u = np.array([1, 0], complex)
+    for k in range(M):
+        sx, sz = sx_of(k), sz_of(k)
+        hx = (1 - sx) * c0[2] + sx * c1[2]
+        hz = (1 - sz) * c0[3] + sz * c1[3]
+        half = sla.expm(0.5j * hx * dt * SX)
+        u = half @ sla.expm(1j * hz * dt * SZ) @ half @ u
+    return u
+
+
+def _product_amplitudes(u, n):
+    w = np.array([bin(i).count("1") for i in range(1 << n)])
+    return u[0] ** (n - w) * u[1] ** w
+
+
+def test_right_endpoint_sampling_closed_form():
+    """Appendix, Eq. (target): the paper's ramp takes g = n dg for n = 1..N,
+    i.e. step k (0-based) uses s_k = (k + 1)/M.  JA = JB = 0 from |0...0>:
+    every link follows the single-link product at those s_k.  Midpoint or
+    left-end sampling moves the fields by dg/2 or dg per step and fails by
+    far more than the tolerance."""
+    Lx, Ly, n = 2, 3, 12
+    c0, c1 = (0.0, 0.0, 0.1, 0.4), (0.0, 0.0, 0.9, -0.3)
+    M, dt = 13, 0.31
+    psi = oracle.state(n)
+    psi[0] = 1
+    oracle.evolve(Lx, Ly, psi, c0, c1, M, dt, sampling=1)
+    right = _product_amplitudes(_single_link_ramp(c0, c1, M, dt, lambda k: (k + 1) / M, lambda k: (k + 1) / M), n)
+    assert np.abs(psi - right).max() < 1e-13
+    for wrong in (lambda k: k / M, lambda k: (k + 0.5) / M):
+        other = _product_amplitudes(_single_link_ramp(c0, c1, M, dt, wrong, wrong), n)
+        assert np.abs(psi - other).max() > 1e-3
+
+
+def test_per_step_schedule_arrays_closed_form():
+    """Per-step schedule values (the adjoint's free parameters): the x-type
+    couplings of step k sit at sX[k] and the z-type ones at sZ[k].  JA = JB = 0
+    from |0...0> pins the fields: h_x at sX[k], h_z at sZ[k] (the swapped
+    assignment fails)."""
+    Lx, Ly, n = 2, 3, 12
+    c0, c1 = (0.0, 0.0, 0.2, 0.5), (0.0, 0.0, 0.8, -0.4)
+    M, dt = 11, 0.27
+    rng = np.random.default_rng(17)
+    sZ, sX = rng.uniform(-0.2, 1.2, M), rng.uniform(-0.2, 1.2, M)
+    psi = oracle.state(n)
+    psi[0] = 1
+    oracle.evolve(Lx, Ly, psi, c0, c1, M, dt, sZ=sZ, sX=sX)
+    ref = _product_amplitudes(_single_link_ramp(c0, c1, M, dt, lambda k: sX[k], lambda k: sZ[k]), n)
+    assert np.abs(psi - ref).max() < 1e-13
+    swapped = _product_amplitudes(_single_link_ramp(c0, c1, M, dt, lambda k: sZ[k], lambda k: sX[k]), n)
+    assert np.abs(psi - swapped).max() > 1e-3
+
+
+def test_per_step_schedule_arrays_stabilizer_phase():
+    """Zero fields, per-step schedule values: psi_1 (Eq. (ini1)) is a +1
+    eigenstate of every A_v and B_p, so step k multiplies it by
+    exp(+i dt (JA(sX[k]) Ns + JB(sZ[k]) Np)).  Pins that the star coupling
+    follows sX and the plaquette coupling sZ."""
+    Lx, Ly = 2, 3
+    nv = Lx * Ly
+    c0, c1 = (0.3, 1.4, 0.0, 0.0), (1.1, -0.2, 0.0, 0.0)
+    M, dt = 9, 0.21
+    rng = np.random.default_rng(18)
+    sZ, sX = rng.uniform(0, 1, M), rng.uniform(0, 1, M)
+    psi0 = oracle.init_psi1(Lx, Ly)
+    psi = psi0.copy()
+    oracle.evolve(Lx, Ly, psi, c0, c1, M, dt, sZ=sZ, sX=sX)
+    ang = sum(dt * nv * (((1 - sX[k]) * c0[0] + sX[k] * c1[0]) + ((1 - sZ[k]) * c0[1] + sZ[k] * c1[1]))
+              for k in range(M))
+    assert np.abs(psi - np.exp(1j * ang) * psi0).max() < 1e-13
+    bad = sum(dt * nv * (((1 - sZ[k]) * c0[0] + sZ[k] * c1[0]) + ((1 - sX[k]) * c0[1] + sX[k] * c1[1]))
+              for k in range(M))
+    assert np.abs(psi - np.exp(1j * bad) * psi0).max() > 1e-3
+
+
+@pytest.mark.parametrize("sampling", [0, 1])
+def test_schedule_arrays_equal_to_linear_schedule_are_the_default(sampling):
+    """sZ = sX = the default sampling points reproduces the default run bit
+    for bit (same couplings, same arithmetic), for both samplings."""
+    Lx, Ly, M, dt = 2, 3, 15, 0.2
+    c0, c1 = (1.0, 0.8, 0.0, 0.1), (0.7, 1.0, 0.45, 0.3)
+    k = np.arange(M, dtype=np.float64)
+    s = (k + 1) / M if sampling else (k + 0.5) / M
+    a = oracle.init_psi1(Lx, Ly)
+    b = a.copy()
+    oracle.evolve(Lx, Ly, a, c0, c1, M, dt, sampling=sampling)
+    oracle.evolve(Lx, Ly, b, c0, c1, M, dt, sZ=s, sX=s.copy(), sampling=sampling)
+    assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("sampling", [0, 1])
+@pytest.mark.parametrize("order", [0, 1])
+def test_circuit_ramp_equals_oracle_ramp(sampling, order):
+    """The gate-level ramp (ancilla gadgets, Sec. III) equals the oracle's
+    Pauli-exponential ramp at 2x2 for both samplings and both orders, with
+    the ancilla back in |0>; the two share no code."""
+    Lx, Ly, n, M, dt = 2, 2, 8, 7, 0.33
+    c0, c1 = (1.0, 0.6, 0.0, 0.2), (0.8, 1.0, 0.5, 0.35)
+    x = oracle.init_psi1(Lx, Ly)
+    got = circuit.evolve(Lx, Ly, circuit.with_ancilla(x), c0, c1, M, dt, sampling=sampling, order=order)
+    ref = x.copy()
+    oracle.evolve(Lx, Ly, ref, c0, c1, M, dt, sampling=sampling, order=order)
+    assert np.abs(got[: 1 << n] - ref).max() < 1e-13
+    assert np.abs(got[1 << n:]).max() < 1e-14
+
+
+def test_circuit_ramp_right_endpoint_closed_form():
+    """Gate-level ramp with JA = JB = 0 from |0...0> (plus the ancilla) at
+    s_k = (k + 1)/M: the decoupled-link closed form."""
+    Lx, Ly, n, M, dt = 2, 2, 8, 6, 0.4
+    c0, c1 = (0.0, 0.0, 0.3, -0.2), (0.0, 0.0, 0.7, 0.6)
+    x = oracle.state(n + 1)
+    x[0] = 1
+    got = circuit.evolve(Lx, Ly, x, c0, c1, M, dt, sampling=1)
+    ref = _product_amplitudes(_single_link_ramp(c0, c1, M, dt, lambda k: (k + 1) / M, lambda k: (k + 1) / M), n)
+    assert np.abs(got[: 1 << n] - ref).max() < 1e-13
+    assert np.abs(got[1 << n:]).max() < 1e-14
