@@ -29,7 +29,7 @@ namespace {
 struct Group {
     Plan P;
     std::vector<int> jobs;        // global job indices, decreasing level count
-    std::vector<JobDev> h_jobs;   // host copies (norm_part filled per workspace)
+    std::vector<JobDev> h_jobs;   // host copies of the device records
     std::vector<InitJob> h_init;
     std::vector<JobDev> h_p1p;    // jobs whose initial state needs the transform
     std::vector<uint64_t> h_off;  // element offsets
@@ -39,12 +39,13 @@ struct Group {
     int nz, nx;
     // device copies (inside the batch's table allocation)
     JobDev *d_jobs, *d_p1p;
+    double *parts_norm;           // per-job norm partials of the z passes (batch-owned)
     InitJob *d_init;
     uint64_t *d_off;
     double *d_H;
     int32_t *d_out;
-    // workspace pieces (set per workspace)
-    double *parts_norm, *partZ, *partX;
+    // workspace pieces (set per workspace): observable partials only
+    double *partZ, *partX;
 };
 
 }  // namespace
@@ -65,15 +66,16 @@ struct z2h_batch {
     hipGraphExec_t exec;
     void *g_states, *g_ws;
     double *g_obs;
-    void *up_ws;                     // workspace the device job records point into
     int chunk_jobs;                  // jobs evolved together (0: all)
     // traced runs (z2h_batch_run_trace): graph and the inputs it was recorded for
     hipGraphExec_t exec_t;
     void *t_states, *t_ws;
     double *t_obs, *t_trace;
     int t_every;
-    void *t_up_ws;                   // workspace holding the uploaded segment records
-    int t_up_every;
+    // segment records of traced runs: batch-owned, uploaded for one interval
+    void *d_trace_tab;
+    size_t trace_tab_bytes;
+    int t_up_every;                  // interval the uploaded records belong to (0: none)
     std::vector<TimedLaunch> timed;  // event pairs of the last timed run
     int device;
 };
@@ -97,6 +99,7 @@ static void free_batch(z2h_batch *b) {
         (void)hipEventDestroy(t.b);
     }
     if (b->d_tables) (void)hipFree(b->d_tables);
+    if (b->d_trace_tab) (void)hipFree(b->d_trace_tab);
     if (b->side) (void)hipStreamDestroy(b->side);
     if (b->cap) (void)hipStreamDestroy(b->cap);
     if (b->fork) (void)hipEventDestroy(b->fork);
@@ -105,14 +108,16 @@ static void free_batch(z2h_batch *b) {
 }
 
 // Workspace layout of a batch: transformed-copy scratch mirroring the state
-// buffer, then per group the norm partials and observable records.
+// buffer, then per group the observable records.  Every piece is written
+// before it is read within one run, so the caller may use the workspace for
+// anything else between runs.  (Job records and norm partials, which the
+// device records point to, are the batch's own.)
 static size_t layout_ws(z2h_batch *b, char *base) {
     Carver c{base, 0};
     void *scratch = c.take(b->states_bytes);
     (void)scratch;
     for (auto &g : b->groups) {
         const size_t nj = g.jobs.size();
-        g.parts_norm = (double *)c.take(sizeof(double) * nj * norm_parts(g.P));
         g.partZ = (double *)c.take(sizeof(double) * nj * obs_workers(g.P.geom[0]) * kObsQ);
         g.partX = (double *)c.take(sizeof(double) * nj * obs_workers(g.P.geom[g.P.K - 1]) * kObsQ);
     }
@@ -215,8 +220,9 @@ static int64_t trace_samples(const z2h_batch *b, int every) {
     return maxM <= 0 ? 0 : (maxM + every - 1) / every;
 }
 
-static size_t trace_ws_bytes(const z2h_batch *b, int64_t nseg) {
-    Carver c{nullptr, b->ws_bytes};
+// Bytes of the segment records of a traced run (batch-owned table).
+static size_t trace_tab_size(const z2h_batch *b, int64_t nseg) {
+    Carver c{nullptr, 0};
     for (const auto &g : b->groups) {
         c.take(sizeof(JobDev) * g.h_jobs.size() * (size_t)nseg);
         c.take(sizeof(double) * 4 * g.h_jobs.size() * (size_t)nseg);
@@ -230,8 +236,8 @@ struct TracePieces {
     std::vector<std::vector<JobDev>> h_seg;   // host copies (step counts for the launch sequence)
 };
 
-static void trace_layout(const z2h_batch *b, int64_t nseg, char *ws, TracePieces &T) {
-    Carver c{ws, b->ws_bytes};
+static void trace_layout(const z2h_batch *b, int64_t nseg, char *tab, TracePieces &T) {
+    Carver c{tab, 0};
     T.d_seg.clear();
     T.d_segH.clear();
     for (const auto &g : b->groups) {
@@ -240,7 +246,7 @@ static void trace_layout(const z2h_batch *b, int64_t nseg, char *ws, TracePieces
     }
 }
 
-// Host records of every segment (norm partials from the current workspace).
+// Host records of every segment (norm partials: the batch's own).
 static void trace_records(const z2h_batch *b, int every, int64_t nseg, TracePieces &T,
                           std::vector<std::vector<double>> &H) {
     T.h_seg.assign(b->groups.size(), {});
@@ -333,16 +339,6 @@ static z2h_status enqueue_traced(z2h_batch *b, void *states, void *ws, double *o
     return enqueue_observe(b, states, ws, obs, Hs, s);
 }
 
-static z2h_status upload_jobs(z2h_batch *b, void *ws) {
-    HIP_TRY(prepare_kernels());
-    layout_ws(b, (char *)ws);
-    for (auto &g : b->groups) {
-        for (size_t j = 0; j < g.h_jobs.size(); ++j)
-            g.h_jobs[j].norm_part = g.parts_norm + j * norm_parts(g.P);
-        HIP_TRY(hipMemcpy(g.d_jobs, g.h_jobs.data(), sizeof(JobDev) * g.h_jobs.size(), hipMemcpyHostToDevice));
-    }
-    return Z2H_OK;
-}
 
 extern "C" {
 
@@ -455,7 +451,8 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
             }
             loops_for(g.P, g.zl, g.nz, g.xl, g.nx);
             const size_t nj = g.jobs.size();
-            tbytes += align256(sizeof(JobDev) * nj) + align256(sizeof(JobDev) * std::max<size_t>(1, g.h_p1p.size())) +
+            tbytes += align256(sizeof(JobDev) * nj) + align256(sizeof(double) * nj * norm_parts(g.P)) +
+                      align256(sizeof(JobDev) * std::max<size_t>(1, g.h_p1p.size())) +
                       align256(sizeof(InitJob) * nj) + align256(sizeof(uint64_t) * nj) +
                       align256(sizeof(double) * 4 * nj) + align256(sizeof(int32_t) * nj);
         }
@@ -470,12 +467,15 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
         for (auto &g : b->groups) {
             const size_t nj = g.jobs.size();
             g.d_jobs = (JobDev *)c.take(sizeof(JobDev) * nj);
+            g.parts_norm = (double *)c.take(sizeof(double) * nj * norm_parts(g.P));
+            for (size_t j = 0; j < nj; ++j) g.h_jobs[j].norm_part = g.parts_norm + j * norm_parts(g.P);
             g.d_p1p = (JobDev *)c.take(sizeof(JobDev) * std::max<size_t>(1, g.h_p1p.size()));
             g.d_init = (InitJob *)c.take(sizeof(InitJob) * nj);
             g.d_off = (uint64_t *)c.take(sizeof(uint64_t) * nj);
             g.d_H = (double *)c.take(sizeof(double) * 4 * nj);
             g.d_out = (int32_t *)c.take(sizeof(int32_t) * nj);
-            bool ok = hipMemcpy(g.d_init, g.h_init.data(), sizeof(InitJob) * nj, hipMemcpyHostToDevice) == hipSuccess &&
+            bool ok = hipMemcpy(g.d_jobs, g.h_jobs.data(), sizeof(JobDev) * nj, hipMemcpyHostToDevice) == hipSuccess &&
+                      hipMemcpy(g.d_init, g.h_init.data(), sizeof(InitJob) * nj, hipMemcpyHostToDevice) == hipSuccess &&
                       hipMemcpy(g.d_off, g.h_off.data(), sizeof(uint64_t) * nj, hipMemcpyHostToDevice) == hipSuccess &&
                       hipMemcpy(g.d_H, g.h_H.data(), sizeof(double) * 4 * nj, hipMemcpyHostToDevice) == hipSuccess &&
                       hipMemcpy(g.d_out, g.h_out.data(), sizeof(int32_t) * nj, hipMemcpyHostToDevice) == hipSuccess &&
@@ -535,10 +535,8 @@ z2h_status z2h_batch_run(z2h_batch *b, void *d_states, void *d_ws, size_t ws_byt
                 (void)hipEventDestroy(t.b);
             }
             b->timed.clear();
-            if (b->up_ws != d_ws) {
-                if ((st = upload_jobs(b, d_ws))) return st;
-                b->up_ws = d_ws;
-            }
+            HIP_TRY(prepare_kernels());
+            layout_ws(b, (char *)d_ws);
             std::vector<TimedLaunch> saved;
             saved.swap(t_launches);
             st = enqueue(b, d_states, d_ws, d_obs, s);
@@ -552,11 +550,8 @@ z2h_status z2h_batch_run(z2h_batch *b, void *d_states, void *d_ws, size_t ws_byt
                 (void)hipGraphExecDestroy(b->exec);
                 b->exec = nullptr;
             }
-            if (b->up_ws != d_ws) {
-                HIP_TRY(hipStreamSynchronize(s));
-                if ((st = upload_jobs(b, d_ws))) return st;
-                b->up_ws = d_ws;
-            }
+            HIP_TRY(prepare_kernels());
+            layout_ws(b, (char *)d_ws);
             // recorded on the batch's own stream (the caller's may be the
             // legacy default stream, which cannot be captured)
             HIP_TRY(hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal));
@@ -603,7 +598,7 @@ z2h_status z2h_batch_trace_sizes(const z2h_batch *b, int32_t every, int64_t *sam
     if (every < 1) return fail(Z2H_ERR_INVALID, "trace interval %d < 1", every);
     const int64_t ns = trace_samples(b, every);
     if (samples_per_job) *samples_per_job = ns;
-    if (ws_bytes) *ws_bytes = trace_ws_bytes(b, ns);
+    if (ws_bytes) *ws_bytes = b->ws_bytes;
     return Z2H_OK;
 }
 
@@ -621,29 +616,43 @@ z2h_status z2h_batch_run_trace(z2h_batch *b, void *d_states, void *d_ws, size_t 
                 if (J.order != g.h_jobs[0].order)
                     return fail(Z2H_ERR_INVALID, "traced batches need one step order per lattice");
         const int64_t nseg = trace_samples(b, every);
-        const size_t need = trace_ws_bytes(b, nseg);
-        if (ws_bytes < need) return fail(Z2H_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
+        if (ws_bytes < b->ws_bytes) return fail(Z2H_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, b->ws_bytes);
         int dev = -1;
         if (hipGetDevice(&dev) != hipSuccess || (b->device >= 0 && dev != b->device))
             return fail(Z2H_ERR_INVALID, "batch used on another device");
         hipStream_t s = (hipStream_t)stream;
-        if (b->up_ws != d_ws) {
+        HIP_TRY(prepare_kernels());
+        layout_ws(b, (char *)d_ws);
+        if (b->t_up_every != every) {
+            // The interval changed: earlier runs' graph and records are
+            // retired before the table is reused or replaced.
             HIP_TRY(hipStreamSynchronize(s));
-            if ((st = upload_jobs(b, d_ws))) return st;
-            b->up_ws = d_ws;
+            HIP_TRY(hipStreamSynchronize(b->cap));
+            if (b->exec_t) {
+                (void)hipGraphExecDestroy(b->exec_t);
+                b->exec_t = nullptr;
+            }
+            b->t_up_every = 0;
+            const size_t need = trace_tab_size(b, nseg);
+            if (need > b->trace_tab_bytes) {
+                if (b->d_trace_tab) (void)hipFree(b->d_trace_tab);
+                b->d_trace_tab = nullptr;
+                b->trace_tab_bytes = 0;
+                if (hipMalloc(&b->d_trace_tab, need) != hipSuccess)
+                    return fail(Z2H_ERR_OOM, "device allocation of %zu bytes for segment records failed", need);
+                b->trace_tab_bytes = need;
+            }
         }
         TracePieces T;
         std::vector<std::vector<double>> H;
-        trace_layout(b, nseg, (char *)d_ws, T);
+        trace_layout(b, nseg, (char *)b->d_trace_tab, T);
         trace_records(b, every, nseg, T, H);
-        if (b->t_up_ws != d_ws || b->t_up_every != every) {
-            HIP_TRY(hipStreamSynchronize(s));
+        if (b->t_up_every != every) {
             for (size_t gi = 0; gi < b->groups.size(); ++gi) {
                 HIP_TRY(hipMemcpy(T.d_seg[gi], T.h_seg[gi].data(), sizeof(JobDev) * T.h_seg[gi].size(),
                                   hipMemcpyHostToDevice));
                 HIP_TRY(hipMemcpy(T.d_segH[gi], H[gi].data(), sizeof(double) * H[gi].size(), hipMemcpyHostToDevice));
             }
-            b->t_up_ws = d_ws;
             b->t_up_every = every;
         }
         if (t_timing) {

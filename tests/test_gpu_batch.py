@@ -174,3 +174,47 @@ def test_traced_batch_against_oracle(dtype):
             compare_observables(row_to_obs(tr[s, j]), ref, tol, n)
         assert tr[ns - 1, j, 1] == ob[j, 1]
         compare_observables(row_to_obs(ob[j]), row_to_obs(obs_plain[j]), tol, n)
+
+
+@pytest.mark.parametrize("dtype", [z2h.Z2H_C128, z2h.Z2H_C64])
+def test_workspace_reuse_between_runs(dtype):
+    """The batch workspace holds only per-run scratch: filling it with other
+    bytes between runs (as a caller reusing it, or torch's allocator handing
+    it out, would) leaves plain and traced runs bitwise unchanged, also
+    after the trace interval changes and returns."""
+    rng = np.random.default_rng(23)
+    jobs = []
+    for (Lx, Ly) in ((3, 3), (2, 3), (2, 2), (3, 3)):
+        hx, hz = rng.uniform(0, 0.6, 2)
+        M = int(rng.integers(8, 24))
+        jobs.append(dict(Lx=Lx, Ly=Ly, c0=workloads.TORIC, c1=(1.0, 1.0, hx, hz), T=0.05 * M, M=M))
+    print(f"case workspace reuse dtype={dtype}", flush=True)
+    b, states, obs0 = run_batch(jobs, dtype)
+    ns5, wsb = z2h.z2h_batch_trace_sizes(b, 5)
+    assert wsb == b.ws_bytes
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    obs = torch.zeros(len(jobs) * z2h.Z2H_OBS_DOUBLES, dtype=torch.float64, device="cuda")
+    z2h.z2h_batch_run(b, states, ws, obs)
+    torch.cuda.synchronize()
+    first = obs.cpu().numpy().copy()
+    ws.fill_(0xFF)
+    obs.zero_()
+    z2h.z2h_batch_run(b, states, ws, obs)
+    torch.cuda.synchronize()
+    assert np.array_equal(obs.cpu().numpy(), first)
+
+    def traced(every):
+        ns, _ = z2h.z2h_batch_trace_sizes(b, every)
+        tr = torch.zeros(ns * len(jobs) * z2h.Z2H_OBS_DOUBLES, dtype=torch.float64, device="cuda")
+        z2h.z2h_batch_run_trace(b, states, ws, obs, every, tr)
+        torch.cuda.synchronize()
+        return tr.cpu().numpy()
+
+    t5 = traced(5)
+    ws.fill_(0xA5)
+    assert np.array_equal(traced(5), t5)
+    t3 = traced(3)
+    ws.fill_(0x00)
+    assert np.array_equal(traced(5), t5)
+    ws.fill_(0x7F)
+    assert np.array_equal(traced(3), t3)
