@@ -307,7 +307,12 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
  * d_obs: device, njobs * Z2H_OBS_DOUBLES doubles.  zloop[0] of each job is
  * the Wilson loop around the 1 x 3 (or 1 x Lx) strip of plaquettes in row 0,
  * zloop[1] the L-shaped three-plaquette loop, zloop[2] and [3] the
- * noncontractible Wilson loops, xloop[0..1] the 't Hooft loops. */
+ * noncontractible Wilson loops, xloop[0..1] the 't Hooft loops.
+ * The workspace (ws_bytes at least z2h_batch_create's figure) holds only
+ * scratch that each run writes before reading it: the caller may use it for
+ * anything else between runs.  Job records and norm partials are the
+ * batch's own.  Runs of one batch must not overlap in time (they share the
+ * batch's norm partials and graph). */
 z2h_status z2h_batch_run(z2h_batch *batch, void *d_states, void *d_ws, size_t ws_bytes,
                          double *d_obs, void *stream);
 void z2h_batch_destroy(z2h_batch *batch); /* NULL-safe */
@@ -323,17 +328,19 @@ void z2h_batch_destroy(z2h_batch *batch); /* NULL-safe */
  * orders are rejected.
  *
  * z2h_batch_trace_sizes: samples per job (ceil(max M / every)) and the
- * workspace a traced run needs (the batch's own plus the segment records).
+ * workspace a traced run needs (the same as z2h_batch_run's).
  *
  * z2h_batch_run_trace: like z2h_batch_run (d_obs receives the final
  * observables), plus d_trace (device, samples * njobs * Z2H_OBS_DOUBLES
  * doubles, sample-major: the record of job j in sample s starts at
  * (s * njobs + j) * Z2H_OBS_DOUBLES).  The launch sequence is recorded in a
- * HIP graph of its own (or issued directly with timing enabled).  The first
- * run with a workspace or interval uploads the segment records into the
- * workspace tail (synchronizing the stream); later runs with the same
- * workspace and interval reuse them, so the caller must not write into the
- * workspace between such runs.  Errors: Z2H_ERR_INVALID for a NULL or
+ * HIP graph of its own (or issued directly with timing enabled).  The
+ * per-segment job records are the batch's own: the first traced run with a
+ * given interval synchronizes the stream, allocates device memory for them
+ * if the batch's table is too small (freed by z2h_batch_destroy) and uploads
+ * them; later runs with the same interval reuse them.  The workspace, as for
+ * z2h_batch_run, holds only per-run scratch.  Errors: Z2H_ERR_OOM if that
+ * allocation fails; Z2H_ERR_INVALID for a NULL or
  * misaligned buffer, every < 1, mixed step orders within a lattice or a
  * batch created on another device; Z2H_ERR_WORKSPACE if ws_bytes is below
  * z2h_batch_trace_sizes' figure.
