@@ -187,6 +187,29 @@ z2h_status z2h_evolve(const z2h_plan *plan, void *d_state, void *d_ws, size_t ws
                       const z2h_schedule *sched, double *d_norms, void *stream);
 
 /*
+ * z2h_evolve for callers that cannot allocate device memory (code under
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): no
+ * workspace argument, and no allocation of any kind.  The scratch z2h_evolve
+ * takes from its workspace (the z passes' per-tile norm partials; device
+ * copies of sZ/sX when the schedule has them) lives in a fixed device array
+ * of Z2H_NOALLOC_SCRATCH_BYTES that the library holds on every device it
+ * runs on until the process ends; its address is looked up on the first
+ * call on each device.  A call needs ws_evolve_bytes of it (z2h_plan_sizes),
+ * plus 16 bytes per step and 512 when sZ or sX is given; beyond the array's
+ * size it returns Z2H_ERR_UNSUPPORTED before touching the device (the 4x4
+ * torus needs 8 MiB).  Arguments, schedule semantics, d_norms and the
+ * result are those of z2h_evolve, with the same kernels.  Every call on a
+ * device shares that device's array: calls that overlap in time on one
+ * device (other streams, other threads) race and corrupt each other's norm
+ * partials; serialize them.  Nothing in the array needs clearing between
+ * calls: each call writes what it reads.  With sZ/sX the host arrays are
+ * copied in and the stream synchronized, as in z2h_evolve.
+ */
+#define Z2H_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+z2h_status z2h_evolve_noalloc(const z2h_plan *plan, void *d_state, const z2h_schedule *sched,
+                              double *d_norms, void *stream);
+
+/*
  * Observables of d_state (not modified) for the couplings H (Sec. IV-V).
  * zmasks/xmasks: up to Z2H_MAX_LOOPS loop masks each (library numbering,
  * bits < n), may be NULL when the count is 0.  h_out (host) is filled after

@@ -19,7 +19,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
           f"--offload-arch={ARCH}"]
 
 SOURCES = ["z2h_kernels.hip", "z2h_host.cpp", "z2h_batch.cpp", "z2h_adjoint.cpp", "z2h_tune.cpp", "z2h_path.cpp",
-           "z2h_krylov_kernels.hip", "z2h_krylov.cpp", "z2h_gates.hip", "z2h_circuit.cpp"]
+           "z2h_krylov_kernels.hip", "z2h_krylov.cpp", "z2h_gates.hip", "z2h_circuit.cpp",
+           "z2h_noalloc.cpp"]
 
 
 def _compile(src, verbose):

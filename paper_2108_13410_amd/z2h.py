@@ -97,6 +97,7 @@ SIGNATURES = {
     "z2h_plan_describe": (_i32, [_P, ctypes.c_char_p, _sz]),
     "z2h_state_init": (_i32, [_P, _P, _i32, _P]),
     "z2h_evolve": (_i32, [_P, _P, _P, _sz, ctypes.POINTER(z2h_schedule), _P, _P]),
+    "z2h_evolve_noalloc": (_i32, [_P, _P, ctypes.POINTER(z2h_schedule), _P, _P]),
     "z2h_observe": (_i32, [_P, _P, _P, _sz, ctypes.POINTER(z2h_couplings), _P, _i32, _P, _i32,
                            ctypes.POINTER(z2h_obs), _P, _P]),
     "z2h_adjoint": (_i32, [_P, _P, _P, _sz, ctypes.POINTER(z2h_schedule), ctypes.POINTER(z2h_couplings),
@@ -293,6 +294,14 @@ def z2h_state_init(plan, state, kind, stream=None):
 def z2h_evolve(plan, state, ws, sched, norms=None, stream=None):
     _check(lib().z2h_evolve(plan.handle, _ptr(state), _ptr(ws), ws.numel() * ws.element_size(),
                             ctypes.byref(sched), _ptr(norms), _stream(stream)))
+
+
+def z2h_evolve_noalloc(plan, state, sched, norms=None, stream=None):
+    _check(lib().z2h_evolve_noalloc(plan.handle, _ptr(state), ctypes.byref(sched), _ptr(norms),
+                                    _stream(stream)))
+
+
+Z2H_NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
 def _masks_arg(masks):
