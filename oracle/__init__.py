@@ -24,7 +24,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# Z2H_ORACLE_LIB names another build of the C core (the sanitizer build run
+# by the CPU tests); default: the in-tree build.
+_LIB_PATH = os.environ.get("Z2H_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 

@@ -8,11 +8,15 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 
 
-def build(verbose=False):
+def build(verbose=False, sanitize=False, out=None):
+    """Build liboracle.so in-tree, or with sanitize=True an ASan + UBSan
+    build at `out` (load it with gcc's libasan preloaded)."""
     src = os.path.join(HERE, "z2h_oracle.c")
-    out = os.path.join(HERE, "liboracle.so")
+    out = out or os.path.join(HERE, "liboracle.so")
     tmp = out + ".tmp"
-    cmd = ["gcc", "-std=c11", "-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
+    opt = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=undefined"] if sanitize else ["-O2"]
+    cmd = ["gcc", "-std=c11", *opt, "-fno-fast-math", "-ffp-contract=off", "-fopenmp",
            "-shared", "-fPIC", src, "-o", tmp, "-lm"]
     if verbose:
         print(" ".join(cmd))

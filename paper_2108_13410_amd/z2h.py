@@ -13,7 +13,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libz2h.so")
+# Z2H_LIB names another build of the same library (the sanitizer build of
+# the host code used by the CPU tests); default: the in-tree gfx950 build.
+LIB_PATH = os.environ.get("Z2H_LIB") or os.path.join(_HERE, "libz2h.so")
 
 Z2H_OK = 0
 Z2H_ERR_INVALID = -1
