@@ -145,25 +145,37 @@ def cache_has(path, n, c128):
     return False
 
 
-def four_by_four(z2h, torch, tune=True, tune_cache=None):
+def four_by_four(z2h, torch, tune=True, tune_cache=None, steps=None, schedules=None, precisions=("c64", "c128")):
     """The 4x4 torus (32 link qubits): ramp from the toric code to
     (0.25, 0.25), T = 20, M = 200, in complex64 (renormalised every step)
-    and complex128; event-timed GB/s per pass kind, energies, norm drift."""
+    and complex128; event-timed GB/s per pass kind, energies, norm drift.
+    steps (profiling runs): fewer steps at the same dt; schedules: explicit
+    schedule string per precision instead of the tuned table's."""
     from paper_2108_13410_amd import workloads
     job = workloads.point_4x4()
+    if steps:
+        job = dict(job, M=int(steps), T=job["T"] * int(steps) / job["M"])
     M, n = job["M"], 32
     zl, xl = z2h.z2h_loop_masks(4, 4)
     res = {}
+    schedules = schedules or {}
     for name, dtype in (("c64", z2h.Z2H_C64), ("c128", z2h.Z2H_C128)):
+        if name not in precisions:
+            continue
         b = 8 if dtype == z2h.Z2H_C64 else 16
         tuned = None
-        if tune:
+        if schedules.get(name):
+            pass
+        elif tune:
             if cache_has(tune_cache, 32, dtype == z2h.Z2H_C128):
                 z2h.z2h_tune_load(tune_cache)
             else:
                 tuned = z2h.z2h_autotune(4, 4, dtype, 1, None if tune_cache == SHIPPED_TABLE else tune_cache)
                 print(f"4x4 {name} autotuned: {tuned}", file=sys.stderr, flush=True)
-        plan = z2h.z2h_plan_create(4, 4, dtype)
+        if schedules.get(name):
+            plan = z2h.z2h_plan_create_config(4, 4, dtype, schedules[name])
+        else:
+            plan = z2h.z2h_plan_create(4, 4, dtype)
         sz = z2h.z2h_plan_sizes(plan)
         info = z2h.z2h_plan_info(plan)
         psi = z2h.alloc_state(plan)
@@ -203,10 +215,27 @@ def four_by_four(z2h, torch, tune=True, tune_cache=None):
         z2h.z2h_plan_destroy(plan)
         torch.cuda.empty_cache()
         print(f"4x4 {name}: {el:.2f} s", file=sys.stderr, flush=True)
+    if "c64" not in res or "c128" not in res:
+        return res
     res["c64_vs_c128"] = {"energy_per_link": abs(res["c64"]["energy"] - res["c128"]["energy"]) / n,
                           "mx": abs(res["c64"]["mx"] - res["c128"]["mx"]),
                           "mz": abs(res["c64"]["mz"] - res["c128"]["mz"])}
     return res
+
+
+def pass_kernel_names(z2h, schedule):
+    """Template instance of the z pass (group 0) and the x pass (top group)
+    kernels of the 3x3 complex64 scan schedule."""
+    if not schedule:
+        return {}
+    plan = z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C64, schedule)
+    d = z2h.z2h_plan_describe(plan)
+    z2h.z2h_plan_destroy(plan)
+    g = d["groups"]
+
+    def name(gr):
+        return f"level_kernel_full<float, {gr['R']}, {gr['full']}, 2, {gr['pair']}>"
+    return {"z": name(g[0]), "x": name(g[-1])}
 
 
 def pmc_summary(fetch_csv, write_csv):
@@ -243,6 +272,11 @@ def pmc_summary(fetch_csv, write_csv):
                     "per_kernel": {f"{k[0][:80]} grid={k[1]}": float(np.mean(v)) for k, v in passes.items()}}
     fb = out["fetch"]["pass_kib_per_dispatch"] * 1024 * scale["fetch"]
     wb = out["write"]["pass_kib_per_dispatch"] * 1024 * scale["write"]
+    # per pass kernel (template instance and grid): scaled fetch + write bytes
+    out["per_kernel_bytes"] = {}
+    for k, v in out["fetch"]["per_kernel"].items():
+        if k in out["write"]["per_kernel"]:
+            out["per_kernel_bytes"][k] = v * 1024 * scale["fetch"] + out["write"]["per_kernel"][k] * 1024 * scale["write"]
     out["bytes_per_launch"] = fb + wb
     out["fetch_bytes_per_launch"] = fb
     out["write_bytes_per_launch"] = wb
@@ -414,6 +448,49 @@ def adjoint_leg(z2h, torch):
     return {"lattice": "3x3", "steps": M, "precision": "complex128", "parameters": 2 * M,
             "loss": float(L.detach()), "forward_ms": fwd * 1e3, "backward_ms": bwd * 1e3,
             "backward_over_forward": bwd / fwd, "grad_norm": float(torch.cat([sZ.grad, sX.grad]).norm())}
+
+
+def scan_c128_leg(z2h, torch, jobs, obs64):
+    """The same 1024-point scan in complex128 (the paper's precision, 4 GiB of
+    states) as one batch run with event-timed pass kernels: throughput, the
+    roofline of each pass kind, and the complex64 scan's distance to it."""
+    nj, n, M = len(jobs), 18, jobs[0]["M"]
+    batch = make_batch(jobs, z2h.Z2H_C128, z2h)
+    states = torch.empty(batch.states_bytes, dtype=torch.uint8, device="cuda")
+    ws = torch.empty(batch.ws_bytes, dtype=torch.uint8, device="cuda")
+    obs = torch.zeros(nj * z2h.Z2H_OBS_DOUBLES, dtype=torch.float64, device="cuda")
+    z2h.z2h_batch_run(batch, states, ws, obs)  # graph recorded
+    z2h.z2h_timing_enable(True)
+    z2h.z2h_batch_run(batch, states, ws, obs)  # timed mode warmed
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    z2h.z2h_batch_run(batch, states, ws, obs)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    counts, ms = z2h.z2h_batch_timing(batch)
+    z2h.z2h_timing_enable(False)
+    t0 = time.perf_counter()
+    z2h.z2h_batch_run(batch, states, ws, obs)
+    torch.cuda.synchronize()
+    graph_s = time.perf_counter() - t0
+    bytes_per_launch = 2 * nj * (1 << n) * 16
+    per_kind = {}
+    for kind, idx in (("z", 0), ("x", 1)):
+        if counts[idx]:
+            avg = float(ms[idx]) / int(counts[idx])
+            ach = bytes_per_launch / (avg * 1e-3) / 1e9
+            per_kind[kind] = {"launches": int(counts[idx]), "avg_launch_ms": avg, "achieved_GBps": ach,
+                              "frac": ach / HBM_PEAK_GBS}
+    o128 = obs.cpu().numpy().reshape(nj, -1)
+    del states, ws, obs, batch
+    torch.cuda.empty_cache()
+    return {"seconds": el, "graph_seconds": graph_s, "amp_updates_per_s": nj * (1 << n) * M / el,
+            "bytes_per_pass_launch": bytes_per_launch, "pass": per_kind,
+            "c64_scan_vs_c128_scan": {
+                "max_abs_err_energy_per_link": float(abs(o128[:, 1] - obs64[:, 1]).max() / n),
+                "max_abs_err_wilson": float(max(abs(o128[:, 6] - obs64[:, 6]).max(),
+                                                abs(o128[:, 7] - obs64[:, 7]).max()))},
+            "c64_scan_speedup": None}
 
 
 def mixed_leg(z2h, torch):
@@ -595,6 +672,12 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-tune", action="store_true")
     ap.add_argument("--no-4x4", action="store_true")
+    ap.add_argument("--no-scan-c128", action="store_true", help="skip the complex128 scan leg")
+    ap.add_argument("--only-4x4", default=None, metavar="PRECISIONS",
+                    help="profiling: run only the 4x4 leg for these precisions (c64,c128) and print it")
+    ap.add_argument("--steps-4x4", type=int, default=None, help="profiling: Trotter steps of the 4x4 leg")
+    ap.add_argument("--schedule-4x4", action="append", default=[], metavar="PRECISION=SCHEDULE",
+                    help="profiling: explicit 4x4 schedule string, e.g. c128=split=12:4:12:0/10:4:13:3/10:4:13:3")
     ap.add_argument("--no-copy", action="store_true")
     ap.add_argument("--no-protocol", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint and mixed-batch legs")
@@ -627,6 +710,17 @@ def main():
     from paper_2108_13410_amd import workloads, z2h
 
     torch.cuda.set_device(0)
+    if args.only_4x4:
+        if args.tune_cache and os.path.exists(args.tune_cache):
+            z2h.z2h_tune_load(args.tune_cache)
+        scheds = dict(x.split("=", 1) for x in args.schedule_4x4)
+        if not args.no_copy:
+            # the 2 GiB device copy that scales rocprofv3's traffic counters
+            print(f"copy reference: {copy_ceiling(torch)}", file=sys.stderr, flush=True)
+        out = four_by_four(z2h, torch, not args.no_tune, args.tune_cache, steps=args.steps_4x4,
+                           schedules=scheds, precisions=tuple(args.only_4x4.split(",")))
+        print(json.dumps({"torus_4x4": out}))
+        return
     jobs = workloads.scan_3x3()
     nj = len(jobs)
     M = jobs[0]["M"]
@@ -688,17 +782,31 @@ def main():
     torch.cuda.synchronize()
     graph_ms = 1000.0 * (time.perf_counter() - t0) / args.steps
 
-    # dominant kernel: the tile pass (z, x and plain-transform passes are one kernel)
-    launches = int(counts[0] + counts[1] + counts[2])
-    avg_ms = float(ms[0] + ms[1] + ms[2]) / launches
+    # Per pass kind (z: group 0 with the Z phase, x: top group with the X
+    # phase, plain: transform only), each a level_kernel_full instance; the
+    # roofline is reported for the kind with the largest total time.
     bytes_per_launch = 2 * nj * (1 << n) * 8  # every amplitude read once and written once
-    achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
         if tr.get("kernel_source_sha256_16") == kernel_hash():
-            traffic = tr.get("bytes_per_launch")
+            traffic = {}
+            names = pass_kernel_names(z2h, tuned.get("scan_c64", (None,))[0])
+            for kind, name in names.items():
+                for k, v in tr.get("per_kernel_bytes", {}).items():
+                    if k.startswith(f"void z2h::{name}(") and k.endswith(f"grid={nj << 14}"):
+                        traffic[kind] = v
+    per_kind = {}
+    for kind, idx in (("z", 0), ("x", 1), ("plain", 2)):
+        if counts[idx] == 0:
+            continue
+        avg = float(ms[idx]) / int(counts[idx])
+        ach = bytes_per_launch / (avg * 1e-3) / 1e9
+        per_kind[kind] = {"launches": int(counts[idx]), "total_ms": float(ms[idx]), "avg_launch_ms": avg,
+                          "achieved_GBps": ach, "frac": ach / HBM_PEAK_GBS,
+                          "traffic": None if traffic is None else traffic.get(kind)}
+    dom = max(("z", "x"), key=lambda k: per_kind[k]["total_ms"])
     obs_np = obs.cpu().numpy().reshape(nj, -1)
 
     line = {
@@ -717,17 +825,16 @@ def main():
         "graph_ms_per_step": graph_ms,
         "schedule": {k: {"config": v[0], "ms_per_trotter_step": v[1]} for k, v in tuned.items()},
         "schedule_source": tuned_from,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "level_kernel_full (tile pass, both groups)", "launches_timed": launches,
-                     "avg_launch_ms": avg_ms, "bytes_per_launch": bytes_per_launch},
-        "pass_ms": {"z": float(ms[0]), "x": float(ms[1]), "plain": float(ms[2]),
-                    "counts": [int(c) for c in counts[:3]]},
+        "roofline": {"bound": "hbm", "achieved": per_kind[dom]["achieved_GBps"], "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": per_kind[dom]["frac"], "traffic": per_kind[dom]["traffic"],
+                     "kernel": f"level_kernel_full, {dom} pass (largest total time)",
+                     "launches_timed": per_kind[dom]["launches"], "avg_launch_ms": per_kind[dom]["avg_launch_ms"],
+                     "bytes_per_launch": bytes_per_launch},
+        "roofline_by_pass": per_kind,
     }
     if not args.no_copy:
-        line["copy_ceiling"] = copy_ceiling(torch)
-        line["roofline"]["frac_of_copy"] = achieved / line["copy_ceiling"]["copy_GBps"]
-        print(f"copy ceiling: {line['copy_ceiling']}", file=sys.stderr, flush=True)
+        line["copy_reference"] = copy_ceiling(torch)
+        print(f"copy reference: {line['copy_reference']}", file=sys.stderr, flush=True)
     if not args.no_plain:
         per_point, res = plain_c128(jobs, z2h, torch, args.plain_points)
         err_e = max(abs(res[j][1] - obs_np[j][1]) / n for j in res)
@@ -742,6 +849,13 @@ def main():
             "max_abs_err_wilson": err_w,
         }
         print(f"plain c128: {per_point*1e3:.2f} ms/point", file=sys.stderr, flush=True)
+    if not args.no_scan_c128:
+        line["scan_c128"] = scan_c128_leg(z2h, torch, jobs, obs_np)
+        line["scan_c128"]["c64_scan_speedup"] = line["scan_c128"]["seconds"] / (elapsed / args.steps)
+        sc = line["scan_c128"]
+        print(f"scan c128: {sc['seconds']:.3f} s, {sc['amp_updates_per_s']:.3e} amplitude-updates/s, passes "
+              + ", ".join(f"{k} {v['achieved_GBps']:.0f} GB/s" for k, v in sc["pass"].items()),
+              file=sys.stderr, flush=True)
     if not args.no_4x4:
         line["torus_4x4"] = four_by_four(z2h, torch, not args.no_tune, args.tune_cache)
     if not args.no_adjoint:
@@ -783,8 +897,8 @@ def main():
                   f"(paper {r['paper_delta_n']}, {r['paper_alpha_n']}), {r['seconds']:.0f} s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(15)
-    line["paper_context"] = {"rtx3090_c128_19q": ">= 0.8e7-1.8e7 link-amplitude-updates/s (derived "
-                             "from 'within 30 minutes' per red path, Sec. VII)"}
+    line["paper_context"] = {"rtx3090_c128_19q": ">= 0.8e7-1.8e7 link-amplitude-updates/s, derived from "
+                             "the wall time per red path the paper states for its RTX 3090 runs (Sec. VII)"}
     print(json.dumps(line))
 
 
