@@ -14,6 +14,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <new>
 #include <vector>
@@ -46,6 +47,10 @@ struct Group {
     int32_t *d_out;
     // workspace pieces (set per workspace): observable partials only
     double *partZ, *partX;
+    // packed level sequence (groups of several passes per step whose step
+    // counts differ): jobs run one after another in slots
+    bool packed;
+    PackedLevels pack;
 };
 
 }  // namespace
@@ -171,6 +176,16 @@ static z2h_status enqueue(z2h_batch *b, void *states, void *ws, double *obs, hip
         // HBM.  Chunks keep the decreasing-step order, so each chunk's running
         // jobs are still a prefix.
         const int nj = (int)g.jobs.size();
+        if (g.packed) {
+            JobSet J;
+            memset(&J, 0, sizeof J);
+            J.d_jobs = g.d_jobs;
+            J.h_jobs = g.h_jobs.data();
+            J.njobs = nj;
+            z2h_status st = run_levels_packed(g.P, states, J, g.pack, s);
+            if (st) return st;
+            continue;
+        }
         const int chunk = b->chunk_jobs > 0 ? b->chunk_jobs : nj;
         for (int c0 = 0; c0 < nj; c0 += chunk) {
             JobSet J;
@@ -261,6 +276,7 @@ static void trace_records(const z2h_batch *b, int every, int64_t nseg, TracePiec
         for (int64_t sg = 0; sg < nseg; ++sg) {
             for (size_t j = 0; j < nj; ++j) {
                 JobDev r = g.h_jobs[j];
+                r.lev0 = 0;  // segments run level-synchronously, never packed
                 const int64_t M = r.M;
                 const int64_t k0 = std::min<int64_t>(sg * every, M), k1 = std::min<int64_t>((sg + 1) * every, M);
                 r.k_begin = (int32_t)k0;
@@ -340,6 +356,64 @@ static z2h_status enqueue_traced(z2h_batch *b, void *states, void *ws, double *o
 }
 
 
+// Slot count for a packed level group, or 0 to keep the level-synchronous
+// launches: the cheaper sequence under the launch cost model above, over
+// slot counts whose launches fill one or two waves of resident workgroups.
+static int choose_slots(const Plan &P, const std::vector<JobDev> &h_jobs, int device) {
+    const int nj = (int)h_jobs.size();
+    const int Pp = 2 * (P.K - 1);
+    int cus = 256;
+    if (device >= 0) {
+        int v = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && v > 0) cus = v;
+    }
+    // workgroups per job and pass, and resident workgroups (LDS-limited,
+    // at most four per compute unit) of the widest pass
+    double waves_per_job = 0.0;
+    for (int k = 0; k < P.K; ++k) {
+        const GroupGeom &g = P.geom[k];
+        const double blocks = (double)(1ull << g.tiles_log2) / (g.pair == 2 ? 2.0 : 1.0);
+        const int per_cu = std::max(1, std::min(4, (int)(kMaxLdsBytes / std::max<size_t>(1, lds_bytes(P, g, g.R)))));
+        waves_per_job = std::max(waves_per_job, blocks / ((double)per_cu * cus));
+    }
+    if (waves_per_job <= 0.0) return 0;
+    std::vector<int64_t> nl(nj);
+    int64_t mx = 0;
+    for (int j = 0; j < nj; ++j) {
+        const JobDev &h = h_jobs[j];
+        nl[j] = h.steps <= 0 ? 0 : (h.order == 0 ? Pp * (h.steps + 1) + 1 : Pp * h.steps + 1);
+        mx = std::max(mx, nl[j]);
+    }
+    const double t0 = 7.0, t1 = 8.0;  // microseconds per launch and per wave
+    auto launch = [&](int active) { return active ? t0 + t1 * std::ceil(active * waves_per_job - 1e-9) : 0.0; };
+    // level-synchronous: job j is active at levels [0, nl[j])
+    std::vector<int64_t> sorted(nl);
+    std::sort(sorted.begin(), sorted.end(), std::greater<int64_t>());
+    double best = 0.0;
+    {
+        int active = nj;
+        for (int64_t L = 0; L < mx; ++L) {
+            while (active > 0 && sorted[active - 1] <= L) --active;
+            best += launch(active);
+        }
+    }
+    int best_slots = 0;
+    const int one_wave = std::max(1, (int)std::floor(1.0 / waves_per_job + 1e-9));
+    for (int slots : {one_wave, 2 * one_wave}) {
+        if (slots >= nj) continue;
+        std::vector<JobDev> tmp(h_jobs);
+        PackedLevels L;
+        pack_levels(P, tmp, slots, L);
+        double cost = 0.0;
+        for (const auto &a : L.active) cost += launch((int)a.size());
+        if (cost < best) {
+            best = cost;
+            best_slots = slots;
+        }
+    }
+    return best_slots;
+}
+
 extern "C" {
 
 z2h_status z2h_loop_masks(int32_t Lx, int32_t Ly, uint64_t *zl, int32_t *nz, uint64_t *xl, int32_t *nx) {
@@ -413,6 +487,14 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
                 if (!std::isfinite(h[k])) { free_batch(b); return fail(Z2H_ERR_INVALID, "job %d: observed couplings not finite", j); }
             b->groups[gid[key]].jobs.push_back(j);
         }
+        // slot count of packed level groups: Z2H_TUNE "slots=N" (0: never
+        // pack), else automatic (-1)
+        int pack_slots = -1;
+        if (const char *tv = getenv("Z2H_TUNE")) {
+            int v;
+            const char *q = strstr(tv, "slots=");
+            if (q && sscanf(q, "slots=%d", &v) == 1 && v >= 0) pack_slots = v;
+        }
         // per group: order jobs by decreasing level count
         for (auto &g : b->groups) {
             const int Pp = 2 * (g.P.K - 1);
@@ -451,6 +533,22 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
             }
             loops_for(g.P, g.zl, g.nz, g.xl, g.nx);
             const size_t nj = g.jobs.size();
+            // Packing (step counts that differ): level-synchronous launches
+            // shrink as jobs finish, down to a few jobs per launch; jobs packed
+            // into slots and run back to back keep every launch the same size.
+            // A launch costs about t0 + t1 per wave of resident workgroups
+            // (measured on MI355X: ~7 us + ~8 us per wave), so the host
+            // compares the level-synchronous sequence with slot counts whose
+            // launches fill one or two waves and keeps the cheapest.
+            g.packed = false;
+            if (g.P.K > 1 && nj > 1 && (1 << g.P.geom[0].tiles_log2) <= kReduceChunk && pack_slots != 0) {
+                const int slots = pack_slots > 0 ? pack_slots : choose_slots(g.P, g.h_jobs, b->device);
+                if (slots > 0 && slots < (int)nj) {
+                    pack_levels(g.P, g.h_jobs, slots, g.pack);
+                    g.packed = true;
+                    tbytes += align256(sizeof(int32_t) * std::max<size_t>(1, g.pack.off.back()));
+                }
+            }
             tbytes += align256(sizeof(JobDev) * nj) + align256(sizeof(double) * nj * norm_parts(g.P)) +
                       align256(sizeof(JobDev) * std::max<size_t>(1, g.h_p1p.size())) +
                       align256(sizeof(InitJob) * nj) + align256(sizeof(uint64_t) * nj) +
@@ -474,13 +572,21 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
             g.d_off = (uint64_t *)c.take(sizeof(uint64_t) * nj);
             g.d_H = (double *)c.take(sizeof(double) * 4 * nj);
             g.d_out = (int32_t *)c.take(sizeof(int32_t) * nj);
+            std::vector<int32_t> flat;
+            if (g.packed) {
+                g.pack.d_idx = (int32_t *)c.take(sizeof(int32_t) * std::max<size_t>(1, g.pack.off.back()));
+                flat.reserve(g.pack.off.back());
+                for (const auto &a : g.pack.active) flat.insert(flat.end(), a.begin(), a.end());
+            }
             bool ok = hipMemcpy(g.d_jobs, g.h_jobs.data(), sizeof(JobDev) * nj, hipMemcpyHostToDevice) == hipSuccess &&
                       hipMemcpy(g.d_init, g.h_init.data(), sizeof(InitJob) * nj, hipMemcpyHostToDevice) == hipSuccess &&
                       hipMemcpy(g.d_off, g.h_off.data(), sizeof(uint64_t) * nj, hipMemcpyHostToDevice) == hipSuccess &&
                       hipMemcpy(g.d_H, g.h_H.data(), sizeof(double) * 4 * nj, hipMemcpyHostToDevice) == hipSuccess &&
                       hipMemcpy(g.d_out, g.h_out.data(), sizeof(int32_t) * nj, hipMemcpyHostToDevice) == hipSuccess &&
                       (g.h_p1p.empty() || hipMemcpy(g.d_p1p, g.h_p1p.data(), sizeof(JobDev) * g.h_p1p.size(),
-                                                    hipMemcpyHostToDevice) == hipSuccess);
+                                                    hipMemcpyHostToDevice) == hipSuccess) &&
+                      (flat.empty() || hipMemcpy((void *)g.pack.d_idx, flat.data(), sizeof(int32_t) * flat.size(),
+                                                 hipMemcpyHostToDevice) == hipSuccess);
             if (!ok) {
                 free_batch(b);
                 return fail(Z2H_ERR_HIP, "upload of batch tables failed");

@@ -797,7 +797,7 @@ static void job_layout(const JobSet &J, LevelArgs &a) {
         a.jbase = J.inl.offset;
         return;
     }
-    if (!J.h_jobs || J.njobs <= 0) return;
+    if (J.d_jidx || !J.h_jobs || J.njobs <= 0) return;
     const uint64_t b0 = J.h_jobs[0].offset;
     const uint64_t st = J.njobs > 1 ? J.h_jobs[1].offset - b0 : 0;
     for (int j = 0; j < J.njobs; ++j)
@@ -824,6 +824,8 @@ z2h_status launch_one_level(const Plan &P, void *states, const JobSet &J, int le
     a.force_plain = force_plain ? 1 : 0;
     a.nt = P.nt;
     a.kind_hint = force_plain ? (int)kPlainH : kind_hint;
+    a.njobs = J.njobs;
+    a.jidx = J.d_jidx;
     job_layout(J, a);
     const uint64_t nblocks = (uint64_t)J.njobs << a.geom.tiles_log2;
     if (nblocks > 0x7fffffffull) return fail(Z2H_ERR_UNSUPPORTED, "grid of %llu blocks", (unsigned long long)nblocks);
@@ -883,6 +885,8 @@ z2h_status run_levels(const Plan &P, void *states, const JobSet &J, hipStream_t 
         if (j > 0 && jl[j] > jl[j - 1])
             return fail(Z2H_ERR_INVALID, "internal: jobs not ordered by decreasing step count");
     }
+    bool uses_norms = false;  // partials are written only where a renormalization or a trace reads them
+    for (int j = 0; j < J.njobs; ++j) uses_norms = uses_norms || J.h_jobs[j].renorm || J.h_jobs[j].norm_trace;
     int active = J.njobs;
     for (int lev = 0; lev < nlev; ++lev) {
         while (active > 0 && jl[active - 1] <= lev) --active;
@@ -906,10 +910,78 @@ z2h_status run_levels(const Plan &P, void *states, const JobSet &J, hipStream_t 
         z2h_status st = launch_one_level(P, states, Ja, lev, op.group, big_parts ? 1 : parts0, false,
                                          pass_kind_of(op), s, uniform ? (int)op.kind : -1);
         if (st) return st;
-        if (big_parts && any_norm) {
+        if (big_parts && any_norm && uses_norms) {
             hipError_t e = launch_reduce_parts(J.d_jobs, J.inl, active, parts0, s);
             if (e != hipSuccess) return fail(Z2H_ERR_HIP, "reduce kernel launch failed: %s", hipGetErrorString(e));
         }
+    }
+    return Z2H_OK;
+}
+
+
+static int job_levels(const Plan &P, const JobDev &h) {
+    const int Pp = 2 * (P.K - 1);
+    return h.steps <= 0 ? 0 : (h.order == 0 ? Pp * (h.steps + 1) + 1 : Pp * h.steps + 1);
+}
+
+void pack_levels(const Plan &P, std::vector<JobDev> &h_jobs, int slots, PackedLevels &L) {
+    const int Pp = 2 * (P.K - 1);
+    const int nj = (int)h_jobs.size();
+    std::vector<int> order(nj);
+    for (int j = 0; j < nj; ++j) order[j] = j;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int x, int y) { return job_levels(P, h_jobs[x]) > job_levels(P, h_jobs[y]); });
+    slots = std::max(1, std::min(slots, nj));
+    std::vector<int64_t> end(slots, 0);
+    int64_t total = 0;
+    for (int j : order) {
+        const int nl = job_levels(P, h_jobs[j]);
+        h_jobs[j].lev0 = 0;
+        if (nl == 0) continue;
+        int best = 0;
+        for (int q = 1; q < slots; ++q)
+            if (end[q] < end[best]) best = q;
+        h_jobs[j].lev0 = (int32_t)end[best];
+        total = std::max<int64_t>(total, end[best] + nl);
+        end[best] = (end[best] + nl + Pp - 1) / Pp * Pp;  // next start on a multiple of the passes per step
+    }
+    L.active.assign((size_t)total, {});
+    for (int j = 0; j < nj; ++j) {
+        const int nl = job_levels(P, h_jobs[j]);
+        for (int l = 0; l < nl; ++l) L.active[(size_t)h_jobs[j].lev0 + l].push_back(j);
+    }
+    L.off.assign(L.active.size() + 1, 0);
+    for (size_t l = 0; l < L.active.size(); ++l) L.off[l + 1] = L.off[l] + L.active[l].size();
+    L.d_idx = nullptr;
+}
+
+z2h_status run_levels_packed(const Plan &P, void *states, const JobSet &J, const PackedLevels &L, hipStream_t s) {
+    const int parts0 = 1 << P.geom[0].tiles_log2;
+    if (parts0 > kReduceChunk)
+        return fail(Z2H_ERR_UNSUPPORTED, "packed batches need at most %d norm partials per state", kReduceChunk);
+    for (size_t lev = 0; lev < L.active.size(); ++lev) {
+        const std::vector<int32_t> &act = L.active[lev];
+        if (act.empty()) continue;
+        LevelOp op{};
+        bool uniform = true;
+        for (int32_t j : act) {
+            const JobDev &h = J.h_jobs[j];
+            LevelOp o = level_op_host((int)lev - h.lev0, P.K, h.steps, h.k_begin, h.order);
+            if (o.kind == kIdle) {
+                uniform = false;
+                continue;
+            }
+            if (op.kind == kIdle) op = o;
+            else if (o.kind != op.kind) uniform = false;
+            if (o.group != op.group) return fail(Z2H_ERR_INVALID, "internal: packed level %zu mixes groups", lev);
+        }
+        if (op.kind == kIdle) continue;
+        JobSet Ja = J;
+        Ja.njobs = (int)act.size();
+        Ja.d_jidx = L.d_idx + L.off[lev];
+        z2h_status st = launch_one_level(P, states, Ja, (int)lev, op.group, parts0, false, pass_kind_of(op), s,
+                                         uniform ? (int)op.kind : -1);
+        if (st) return st;
     }
     return Z2H_OK;
 }

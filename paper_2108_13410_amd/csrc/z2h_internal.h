@@ -54,7 +54,7 @@ struct JobDev {
     double *norm_part;                  // partial norms of the last z-type pass
     double *norm_trace;                 // per-step norms or null
     int32_t norm_parts;                 // number of partials written there
-    int32_t pad;
+    int32_t lev0;                       // launch level at which this job's level 0 runs (0 unless packed)
 };
 
 // Pass kinds inside a job's level sequence.

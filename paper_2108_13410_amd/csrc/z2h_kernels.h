@@ -25,6 +25,9 @@ struct LevelArgs {
     int32_t jmode;             // 0: job jb's state starts at jbase + jb * jstride (elements)
                                // 1: at its record's offset
     uint64_t jbase, jstride;
+    int32_t njobs;             // jobs of this launch
+    int32_t pad2;
+    const int32_t *jidx;       // job of block-job b is jobs[jidx[b]] (packed batches), or null: jobs[b]
     JobDev job_inline;         // used when jobs is null (single state)
 };
 

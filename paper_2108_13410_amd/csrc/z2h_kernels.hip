@@ -135,6 +135,13 @@ __device__ __forceinline__ JobDev job_record(const JobDev *jobs, int jb, const J
     return J;
 }
 
+// Job of a packed launch's block-job b (index list read through the constant
+// address space: a scalar load).
+__device__ __forceinline__ int job_index(const int32_t *jidx, int b) {
+    typedef const __attribute__((address_space(4))) int32_t *ConstInts;
+    return ((ConstInts)jidx)[b];
+}
+
 // ---------------------------------------------------------------- schedule
 
 __device__ __forceinline__ double sched_s(const JobDev &J, int k, int zkind) {
@@ -236,9 +243,9 @@ __global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
     const uint64_t bid = blockIdx.x;
     const int jb = (int)(bid >> g.tiles_log2);
     const uint64_t tile = bid & (tiles - 1);
-    const JobDev J = job_record(a.jobs, jb, a.job_inline);
+    const JobDev J = job_record(a.jobs, a.jidx ? job_index(a.jidx, jb) : jb, a.job_inline);
     const LevelOp op = a.force_plain ? LevelOp{a.group, kPlainH, 0, -1, -1, 0, 0, 0}
-                                     : level_op(a.level, a.K, J.steps, J.k_begin, J.order);
+                                     : level_op(a.level - J.lev0, a.K, J.steps, J.k_begin, J.order);
     if (op.kind == kIdle || op.group != a.group) return;  // uniform per block
 
     Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
@@ -257,7 +264,7 @@ __global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
         double alpha, beta;
         phase_angles(J, op, alpha, beta);
         double scale = op.basis ? ldexp(1.0, -a.lat.n) : 1.0;
-        if (op.renorm && J.norm_part) {
+        if (op.renorm && J.norm_part && (J.renorm || J.norm_trace)) {
             double s = 0.0;
             for (int j = (int)t; j < a.rn_parts; j += blockDim.x) s += gld(J.norm_part, j);
             s = block_sum(s, red);
@@ -282,10 +289,12 @@ __global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
         }
         cur = g.nlay - 1;
     }
-    if (has_phase || op.norm) {
+    // norms are measured only where a renormalization or a trace uses them
+    const bool need_norm = op.norm && (J.renorm || J.norm_trace);
+    if (has_phase || need_norm) {
         LayCtx<R> Lm;
-        lay_ctx<R>(Lm, g, a.lat, tile, g.p[cur], t, has_phase);
-        if (op.norm) {
+        lay_ctx<R>(Lm, g, a.lat, tile, g.p[cur], t, has_phase, op.basis);
+        if (need_norm) {
             double s = block_sum(sumsq<Real, R>(v), red);
             if (t == 0 && J.norm_part) gst(J.norm_part, tile, s);
         }
@@ -479,7 +488,11 @@ __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, 
     const int x1 = g.x1;
     const int p0 = x1 - R, pl = x1 - R * NL;
     constexpr bool kPhase = KIND != kPlainH;
-    const bool want_norm = kPhase && op.renorm && J.norm_part;
+    // norms are measured (z passes) and summed (the next pass) only where a
+    // renormalization or a norm trace uses them
+    const bool use_norms = J.renorm || J.norm_trace;
+    const bool want_norm = kPhase && op.renorm && J.norm_part && use_norms;
+    const bool meas_norm = op.norm && use_norms;
     const int nst = a.lat.nst, n = a.lat.n;
     double part = 0.0;
     if constexpr (kPhase) {
@@ -494,8 +507,8 @@ __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, 
 #pragma unroll
         for (int s = 0; s < NT; ++s) {
             LayCtx<R> Ls;
-            lay_ctx<R>(Ls, g, a.lat, tile0 + s, p0, t, true);
-            if (op.norm) {
+            lay_ctx<R>(Ls, g, a.lat, tile0 + s, p0, t, true, op.basis);
+            if (meas_norm) {
                 const double q = block_sum(sumsq<Real, R>(v[s]), red);
                 if (t == 0 && J.norm_part) gst(J.norm_part, tile0 + s, q);
             }
@@ -513,9 +526,9 @@ __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, 
 #pragma unroll
         for (int s = 0; s < NT; ++s) {
             LayCtx<R> Lm;
-            lay_ctx<R>(Lm, g, a.lat, tile0 + s, pl, t, true);
+            lay_ctx<R>(Lm, g, a.lat, tile0 + s, pl, t, true, op.basis);
             if constexpr (KIND == kPhaseB) {
-                if (op.norm) {
+                if (meas_norm) {
                     const double q = block_sum(sumsq<Real, R>(v[s]), red);
                     if (t == 0 && J.norm_part) gst(J.norm_part, tile0 + s, q);
                 }
@@ -563,9 +576,9 @@ __global__ void __launch_bounds__(512) level_kernel_full(LevelArgs a) {
     Cx<Real> *st = base + a.jbase + (uint64_t)jb * a.jstride;
     if (a.jmode == 0) load_tiles<Real, R, NT>(v, st, L0);
 
-    const JobDev J = job_record(a.jobs, jb, a.job_inline);
+    const JobDev J = job_record(a.jobs, a.jidx ? job_index(a.jidx, jb) : jb, a.job_inline);
     const LevelOp op = a.force_plain ? LevelOp{a.group, kPlainH, 0, -1, -1, 0, 0, 0}
-                                     : level_op(a.level, a.K, J.steps, J.k_begin, J.order);
+                                     : level_op(a.level - J.lev0, a.K, J.steps, J.k_begin, J.order);
     if (op.kind == kIdle || op.group != a.group) return;  // uniform per block
     if (a.jmode != 0) {
         st = base + J.offset;

@@ -99,7 +99,24 @@ struct JobSet {
     JobDev inl;             // used when d_jobs is null
     const JobDev *h_jobs;   // host copies (step counts, order), same order as d_jobs
     int njobs;
+    const int32_t *d_jidx;  // packed launch: block-job b runs d_jobs[d_jidx[b]] (device), or null
 };
+
+// Packed level sequence of a batch group: jobs run one after another in
+// slots, job j's level 0 at launch level lev0[j] (a multiple of the passes
+// per step, so every job of a launch visits the same group).  active[L]
+// lists the jobs (indices into the group's records) running at launch level
+// L; d_idx + off[L] is the same list on the device.
+struct PackedLevels {
+    std::vector<std::vector<int32_t>> active;
+    std::vector<size_t> off;
+    const int32_t *d_idx;
+};
+
+// Slots by longest-processing-time assignment; fills lev0 of every host
+// record and the per-level lists.
+void pack_levels(const Plan &P, std::vector<JobDev> &h_jobs, int slots, PackedLevels &L);
+z2h_status run_levels_packed(const Plan &P, void *states, const JobSet &J, const PackedLevels &L, hipStream_t s);
 
 z2h_status launch_one_level(const Plan &P, void *states, const JobSet &J, int lev, int group,
                             int rn_parts, bool force_plain, int kind, hipStream_t s,

@@ -120,15 +120,17 @@ __device__ __forceinline__ uint32_t syndrome_direct(const uint32_t *masks, int n
     return s;
 }
 
+// want_syn: fill the syndromes; which: 0 plaquettes only, 1 stars only, 2
+// both (a phase pass needs only the basis it applies).
 template <int R>
 __device__ __forceinline__ void lay_ctx(LayCtx<R> &L, const GroupGeom &g, const LatticeDev &lat,
-                                        uint64_t tile, int p, uint32_t t, bool want_syn) {
+                                        uint64_t tile, int p, uint32_t t, bool want_syn, int which = 2) {
     L.i0 = glob(g, tile, lay_base<R>(p, t));
     L.gs = gbit(g, p);
     L.w0 = __builtin_popcountll(L.i0);
     if (want_syn) {
-        L.s0z = syndrome_direct(lat.zmask, lat.nst, L.i0);
-        L.s0x = syndrome_direct(lat.xmask, lat.nst, L.i0);
+        L.s0z = which != 1 ? syndrome_direct(lat.zmask, lat.nst, L.i0) : 0u;
+        L.s0x = which != 0 ? syndrome_direct(lat.xmask, lat.nst, L.i0) : 0u;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             L.lz[r] = lat.zsyn[L.gs + r];

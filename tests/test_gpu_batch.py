@@ -218,3 +218,28 @@ def test_workspace_reuse_between_runs(dtype):
     assert np.array_equal(traced(5), t5)
     ws.fill_(0x7F)
     assert np.array_equal(traced(3), t3)
+
+
+@pytest.mark.parametrize("dtype", [z2h.Z2H_C64, z2h.Z2H_C128])
+def test_packed_levels_equal_level_synchronous(dtype):
+    """Step counts that differ: jobs packed into slots (run back to back)
+    give the observables of the level-synchronous launches bit for bit (same
+    kernels per job), for several slot counts and the automatic choice."""
+    import os
+    rng = np.random.default_rng(41)
+    jobs = []
+    for k in range(11):
+        Lx, Ly = ((3, 3), (2, 3), (3, 4) if dtype == z2h.Z2H_C64 else (3, 3))[k % 3]
+        hx, hz = rng.uniform(0, 0.6, 2)
+        M = int(rng.integers(3, 30))
+        jobs.append(dict(Lx=Lx, Ly=Ly, c0=workloads.TORIC, c1=(1.0, 1.0, hx, hz), T=0.06 * M, M=M))
+    outs = []
+    try:
+        for tv in ("slots=0", "slots=3", "slots=2", "slots=5", "chunk=0"):
+            os.environ["Z2H_TUNE"] = tv
+            print(f"case packed batch dtype={dtype} {tv}", flush=True)
+            outs.append(run_batch(jobs, dtype)[2])
+    finally:
+        os.environ.pop("Z2H_TUNE", None)
+    for o in outs[1:]:
+        assert np.array_equal(o, outs[0])
