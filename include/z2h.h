@@ -319,7 +319,13 @@ z2h_status z2h_paths_evolve(const z2h_plan *plan, int32_t npaths, void *d_states
  * the couplings obsH[j] whose energy is reported.  All states live in one
  * device buffer; state_offsets[j] (host output, bytes) is where state j
  * starts.  The launch sequence of the whole batch (initialization, every
- * pass of every job, observables) is recorded once in a HIP graph.
+ * pass of every job, observables) is recorded once in a HIP graph.  Jobs
+ * of one lattice run level by level (one launch per pass level for every
+ * job that has one); where their step counts differ the host may pack them
+ * into slots, jobs of a slot running back to back, so that launches keep
+ * one size (chosen by a launch-cost model; the environment variable
+ * Z2H_TUNE may force "slots=N", 0 = never pack).  Packing changes only the
+ * grouping of launches, never a job's arithmetic: results are identical.
  */
 z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
                             const z2h_schedule *sched, const z2h_init *init,
