@@ -7,7 +7,12 @@ by results that hold exactly at any size:
     (closed form from 2x2 matrix exponentials);
   - self-duality (Sec. III): x-z-x from psi_1 and z-x-z from psi_1' with the
     couplings exchanged give the same energy, <X> and <Z> swapped;
-  - complex64 against complex128 on the 4x4 ramp (T = 20, M = 200).
+  - complex64 against complex128 on the 4x4 ramp (T = 20, M = 200);
+  - J_B = h_z = 0 from psi_1: dynamics diagonal in the Hadamard basis on
+    the 2^15 plaquette-span codewords (sampled amplitudes as 32768-term
+    sums, <B_p> by enumeration);
+  - h_z = 0: the star sector and the 't Hooft loops stay at +1 through the
+    full mixed dynamics.
 The same 3-group pass structure is checked against the oracle element by
 element at 3x4 and 2x7 (24 and 28 qubits).
 """
@@ -198,3 +203,80 @@ def test_4x4_two_tile_schedule_bitwise():
     assert torch.equal(samples[0], samples[1])
     for key in ("energy", "norm", "mx", "mz"):
         assert abs(obs[0][key] - obs[1][key]) <= 1e-13 * max(1.0, abs(obs[0][key])), key
+
+
+def _plaquette_codewords():
+    """The 2^15 sums (XOR) of plaquette masks of the 4x4 torus (library
+    numbering): 15 of the 16 plaquettes are independent, the product of all
+    is the identity."""
+    st, pl = z2h.z2h_masks(4, 4)
+    words = np.zeros(1, np.uint64)
+    for m in pl[:15]:
+        words = np.concatenate([words, words ^ np.uint64(int(m))])
+    assert np.unique(words).size == 1 << 15
+    return words, pl
+
+
+@pytest.mark.parametrize("dtype", [z2h.Z2H_C128, z2h.Z2H_C64])
+def test_4x4_x_diagonal_dynamics(dtype):
+    """J_B = h_z = 0 from psi_1 (Eq. (ini1)): only the star and x-field terms
+    act, both diagonal in the Hadamard basis.  There psi_1 is the uniform
+    superposition of the 2^15 plaquette-span codewords x (all stars even), so
+    step k multiplies x by exp(+i dt (J_A N_s + h_x (n - 2 w(x)))) at s_k.
+    Closed forms at the full 32 qubits: sampled amplitudes as 32768-term
+    sums, <B_p> by enumerating the codewords, <A_v> = 1, <Z> = 0, <X>
+    constant."""
+    print(f"case 4x4 x-diagonal dtype={dtype}", flush=True)
+    r = Run(dtype)
+    n, ns, M, dt = 32, 16, 6, 0.2
+    c0, c1 = (0.8, 0.0, 0.1, 0.0), (1.1, 0.0, 0.55, 0.0)
+    ob = r.ramp(c0, c1, M, dt, renorm=0)
+    words, pl = _plaquette_codewords()
+    w = _popcount(words)
+
+    def phase(wt):
+        ph = np.zeros(wt.shape)
+        for k in range(M):
+            s = (k + 0.5) / M
+            JA = (1 - s) * c0[0] + s * c1[0]
+            hx = (1 - s) * c0[2] + s * c1[2]
+            ph += dt * (JA * ns + hx * (n - 2 * wt))
+        return ph
+
+    amp = 2.0 ** (-7.5) * np.exp(1j * phase(w))          # Hadamard-basis amplitudes
+    rng = np.random.default_rng(5)
+    idx = rng.integers(0, 1 << 32, 48, dtype=np.uint64)
+    sign = 1 - 2 * (_popcount(idx[:, None] & words[None, :]) & 1)
+    ref = 2.0 ** (-16) * (sign * amp[None, :]).sum(axis=1)
+    got = r.sample(idx)
+    amax = 2.0 ** (-8.5)
+    tol = 1e-11 if dtype == z2h.Z2H_C128 else 2e-5
+    assert np.max(np.abs(got - ref)) < tol * amax
+    # observables
+    otol = 1e-10 if dtype == z2h.Z2H_C128 else 2e-5
+    ph_w = phase(w)
+    sumB = 0.0
+    for m in pl:
+        shifted = words ^ np.uint64(int(m))
+        sumB += np.mean(np.cos(phase(_popcount(shifted)) - ph_w))
+    mx = np.mean(1 - 2 * (_popcount(words[:, None] & (np.uint64(1) << np.arange(n, dtype=np.uint64))[None, :]) & 1))
+    assert abs(ob["sumA"] - ns) < otol * ns
+    assert abs(ob["mz"]) < otol
+    assert abs(ob["mx"] - mx) < otol
+    assert abs(ob["sumB"] - sumB) < otol * ns
+    assert abs(ob["energy"] - (-c1[0] * ob["sumA"] - c1[2] * n * ob["mx"])) < otol * n
+    r.free()
+
+
+def test_4x4_star_sector_conserved():
+    """h_z = 0 (Sec. IV): every term commutes with the stars and with the
+    't Hooft loops, and psi_1 is their +1 eigenstate, so through the full
+    mixed dynamics <A_v> = 1 and <V_1> = <V_2> = 1 at 32 qubits (complex64,
+    renormalised each step)."""
+    print("case 4x4 star sector c64", flush=True)
+    r = Run(z2h.Z2H_C64)
+    ob = r.ramp((1.0, 1.0, 0.0, 0.0), (0.9, 1.2, 0.45, 0.0), 10, 0.15, renorm=1)
+    assert abs(ob["sumA"] - 16) < 16 * 2e-5
+    assert abs(ob["xloop"][0] - 1) < 2e-5 and abs(ob["xloop"][1] - 1) < 2e-5
+    assert 0.2 < ob["mx"] < 1.0 and ob["sumB"] < 16 - 1e-3  # the dynamics did move the state
+    r.free()
