@@ -599,7 +599,11 @@ z2h_status z2h_autotune(int32_t Lx, int32_t Ly, z2h_dtype dtype, int32_t batch, 
  * "split=G:R:m:c/..." lists, from the lowest qubits up, each transform
  * group's width G, register window 2^R, tile bits m and carried low bits c;
  * "uniform,m=..,c=..,R=..,g0=.." is the general planner with fixed tile
- * parameters.  Either may end in ",nt=1" (streaming loads and stores). */
+ * parameters.  Either may end in ",nt=1" (streaming loads and stores)
+ * and ",xcd=<mask>" (bit j set: the workgroups of the passes over group j
+ * are renumbered so that each of the eight XCDs walks a contiguous range of
+ * tiles; launches whose block count is not a multiple of 8 keep the
+ * hardware order; default 1, group 0 only). */
 z2h_status z2h_plan_create_config(int32_t Lx, int32_t Ly, z2h_dtype dtype, const char *schedule,
                                   z2h_plan **out);
 

@@ -413,15 +413,22 @@ static void plan_base(int Lx, int Ly, bool c128, Plan &P) {
     P.esize = c128 ? 16 : 8;
     P.lat = make_latdev(Lx, Ly);
     P.nt = 0;
+    // group 0 (contiguous tiles) in XCD-major order: each XCD streams a
+    // contiguous range of the state, measured faster on every lattice; the
+    // strided groups keep the hardware order, which measured faster for them
+    P.xcd = 1;
 }
 
 // A schedule configuration string: "split=G:R:m:c/G:R:m:c/..." (groups from
 // the lowest qubits up) or "uniform,m=..,R=..,c=..,g0=.."; either may add
-// ",nt=1" (streaming loads and stores in the general pass kernel).
+// ",nt=1" (streaming loads and stores in the general pass kernel) and
+// ",xcd=<mask>" (XCD-major block order in the passes over group j when bit
+// j of the mask is set).
 static z2h_status plan_from_config(Plan &P, const char *cfg, int m_pref, int m_hi, int c_min) {
     int v;
     const char *q;
     if ((q = strstr(cfg, "nt=")) && sscanf(q, "nt=%d", &v) == 1) P.nt = v ? 1 : 0;
+    if ((q = strstr(cfg, "xcd=")) && sscanf(q, "xcd=%d", &v) == 1) P.xcd = v & ((1 << kMaxGroups) - 1);
     if ((q = strstr(cfg, "split="))) {
         GroupChoice ch[kMaxGroups];
         int K = 0;
@@ -807,6 +814,8 @@ static void job_layout(const JobSet &J, LevelArgs &a) {
     a.jstride = st;
 }
 
+constexpr uint64_t kXcdMinBlocks = 8 * 256;  // eight blocks per CU
+
 z2h_status launch_one_level(const Plan &P, void *states, const JobSet &J, int lev, int group,
                                    int rn_parts, bool force_plain, int kind, hipStream_t s,
                                    int kind_hint) {
@@ -829,6 +838,10 @@ z2h_status launch_one_level(const Plan &P, void *states, const JobSet &J, int le
     job_layout(J, a);
     const uint64_t nblocks = (uint64_t)J.njobs << a.geom.tiles_log2;
     if (nblocks > 0x7fffffffull) return fail(Z2H_ERR_UNSUPPORTED, "grid of %llu blocks", (unsigned long long)nblocks);
+    // XCD-major order pays on streaming launches (many blocks per CU); a
+    // launch of a few blocks per CU (a single small state) keeps the
+    // hardware order, which measured slightly faster there
+    a.xcd = ((P.xcd >> group) & 1) && nblocks >= kXcdMinBlocks;
     const size_t lds = lds_bytes(P, a.geom, a.geom.R);
     hipEvent_t e0, e1;
     timed_begin(s, e0, e1);
@@ -1159,7 +1172,8 @@ z2h_status z2h_plan_describe(const z2h_plan *plan, char *buf, size_t len) {
     if (!plan || !buf || len == 0) return fail(Z2H_ERR_INVALID, "NULL argument");
     const Plan &P = plan->P;
     std::string s = "{\"n\": " + std::to_string(P.n) + ", \"R\": " + std::to_string(P.geom[0].R) +
-                    ", \"K\": " + std::to_string(P.K) + ", \"c128\": " + (P.c128 ? "1" : "0") + ", \"groups\": [";
+                    ", \"K\": " + std::to_string(P.K) + ", \"c128\": " + (P.c128 ? "1" : "0") + ", \"nt\": " + std::to_string(P.nt) +
+                    ", \"xcd\": " + std::to_string(P.xcd) + ", \"groups\": [";
     for (int j = 0; j < P.K; ++j) {
         const GroupGeom &g = P.geom[j];
         s += j ? ", " : "";

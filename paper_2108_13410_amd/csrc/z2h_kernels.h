@@ -26,7 +26,7 @@ struct LevelArgs {
                                // 1: at its record's offset
     uint64_t jbase, jstride;
     int32_t njobs;             // jobs of this launch
-    int32_t pad2;
+    int32_t xcd;               // 1: XCD-major block order (consecutive tiles on one XCD)
     const int32_t *jidx;       // job of block-job b is jobs[jidx[b]] (packed batches), or null: jobs[b]
     JobDev job_inline;         // used when jobs is null (single state)
 };

@@ -25,6 +25,7 @@ struct Plan {
     LatticeDev lat;
     int device;
     int nt;                      // streaming loads/stores in the pass kernels
+    int xcd;                     // bit j: XCD-major block order in the passes over group j
 };
 
 namespace rt {

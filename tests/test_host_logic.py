@@ -132,6 +132,19 @@ def test_autotuner_candidates_are_valid_plans(Lx, Ly, dt):
         check_geometry(z2h.z2h_plan_create_config(Lx, Ly, dt, c))
 
 
+def test_block_order_option():
+    """Group 0 runs in XCD-major block order by default; ",xcd=<mask>"
+    selects the groups (bits above the group count are dropped)."""
+    d = z2h.z2h_plan_describe(z2h.z2h_plan_create(3, 3, z2h.Z2H_C64))
+    assert d["xcd"] == 1
+    for cfg, want in (("split=12:4:12:0/6:3:11:5:2", 1), ("split=12:4:12:0/6:3:11:5:2,xcd=0", 0),
+                      ("split=12:4:12:0/6:3:11:5:2,xcd=3", 3), ("uniform,m=12,c=4,xcd=2", 2),
+                      ("split=12:4:12:0/6:3:11:5:2,xcd=255", 15), ("split=12:4:12:0/6:3:11:5:2,nt=1,xcd=0", 0)):
+        d = z2h.z2h_plan_describe(z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C64, cfg))
+        assert d["xcd"] == want, cfg
+    assert z2h.z2h_plan_describe(z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C64, "uniform,m=12,nt=1"))["nt"] == 1
+
+
 def test_schedule_strings_rejected():
     for bad in ("split=10:5:13:0", "split=10:5:13:1/8:4:13:5", "split=10:5:13:0/8:4:19:11", "split=10:5:16:0/8:4:13:5",
                 "split=10:5:11:0/8:4:13:5:3", "split=18:3:18:0:2", "nonsense"):
