@@ -732,14 +732,16 @@ def main():
     if cache_has(args.tune_cache, 18, False) and cache_has(args.tune_cache, 18, True):
         z2h.z2h_tune_load(args.tune_cache)
         tuned_from = os.path.relpath(args.tune_cache, ROOT)
-        # the table's entries for 18 qubits: complex64 batches and single
-        # complex128 states ("qubits precision batch-class config")
+        # the table's entries the scan (18 qubits, complex64, batch class 64)
+        # and the single complex128 states (batch class 1) run with
+        # ("qubits precision batch-class config")
         with open(args.tune_cache) as fh:
             for line in fh:
                 f = line.split()
-                if len(f) == 4 and f[0] == "18":
-                    key = "scan_c64" if f[1] == "0" else "plain_c128"
-                    tuned[key] = (f[3], None)
+                if len(f) == 4 and (f[0], f[1], f[2]) == ("18", "0", "64"):
+                    tuned["scan_c64"] = (f[3], None)
+                elif len(f) == 4 and (f[0], f[1], f[2]) == ("18", "1", "1"):
+                    tuned["plain_c128"] = (f[3], None)
         print(f"schedules loaded from {args.tune_cache}", file=sys.stderr, flush=True)
     elif not args.no_tune:
         out = None if args.tune_cache == SHIPPED_TABLE else args.tune_cache

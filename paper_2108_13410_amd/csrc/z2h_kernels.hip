@@ -557,15 +557,6 @@ constexpr int kAnyKind = -1;
 // NT: consecutive tiles per block (1, or 2 for strided groups whose tiles
 // carry 128-byte rows: the two tiles of a block differ only in the lowest
 // tile bit, so each block reads and writes 256 contiguous bytes per row).
-// Workgroups of a launch are handed to the eight XCDs in turn (block b to
-// XCD b mod 8).  XCD-major order renumbers them so that each XCD walks a
-// contiguous range of tiles: tiles that share cache lines or DRAM pages
-// (neighbouring rows of a strided group) then meet in one L2.  A bijection
-// of [0, nb) when nb is a multiple of 8; other grids keep their order.
-__device__ __forceinline__ uint32_t xcd_major(uint32_t b, uint32_t nb) {
-    return (nb & 7u) ? b : (b & 7u) * (nb >> 3) + (b >> 3);
-}
-
 template <typename Real, int R, int NL, int KS, int NT>
 __global__ void __launch_bounds__(512) level_kernel_full(LevelArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];

@@ -34,6 +34,12 @@ unsigned vec_blocks(const Plan &P) {
     return (unsigned)std::min<uint64_t>(need, (uint64_t)kVecBlocks);
 }
 
+// XCD-major order for the passes over the groups the plan selects, on
+// grids of eight or more workers per CU (as the Trotter pass kernels).
+static int ham_xcd(const Plan &P, int group, int workers) {
+    return ((P.xcd >> group) & 1) && workers >= 8 * 256 ? 1 : 0;
+}
+
 // y = H x: passes over groups 0, 1, .., K-1, .., 1, 0 (one pass when K = 1).
 // The last pass writes Re<x, y> partials to apart (if not null).
 z2h_status ham_passes(const Plan &P, const void *x, void *y, const z2h_couplings &H, double *apart,
@@ -57,6 +63,7 @@ z2h_status ham_passes(const Plan &P, const void *x, void *y, const z2h_couplings
         a.x = a.final_pass ? x : nullptr;
         a.part = a.final_pass ? apart : nullptr;
         const int w = ham_workers(a.geom);
+        a.xcd = ham_xcd(P, gi, w);
         if (a.final_pass && napart) *napart = w;
         hipError_t e = launch_ham(P.c128, a.geom.R, a, (unsigned)w, obs_lds_bytes(P, a.geom, a.geom.R), s);
         if (e != hipSuccess) return fail(Z2H_ERR_HIP, "Hamiltonian pass failed: %s", hipGetErrorString(e));
@@ -164,6 +171,7 @@ z2h_status lanczos_iter(const Plan &P, const z2h_couplings &H, int k, const void
                 a.coef = L.coef;
                 a.k = k;
             }
+            a.xcd = ham_xcd(P, gi, ham_workers(a.geom));
             hipError_t e = launch_ham(P.c128, a.geom.R, a, (unsigned)ham_workers(a.geom),
                                       obs_lds_bytes(P, a.geom, a.geom.R), s);
             if (e != hipSuccess) return fail(Z2H_ERR_HIP, "Lanczos pass failed: %s", hipGetErrorString(e));

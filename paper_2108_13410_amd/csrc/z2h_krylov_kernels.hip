@@ -170,7 +170,9 @@ __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
     }
 
     const bool syn0 = a.final_pass || a.part_z;
-    uint64_t tile = blockIdx.x;
+    // logical block: first tile of the grid-stride walk and partial slot
+    const uint32_t lb = a.xcd ? xcd_major(blockIdx.x, gridDim.x) : blockIdx.x;
+    uint64_t tile = lb;
     Cx<Real> vn[PF ? (1 << R) : 1];
     LayCtx<R> Ln;
     if constexpr (PF) {
@@ -225,19 +227,19 @@ __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
     }
     if (a.part) {
         const double s = block_sum(acc, red);
-        if (t == 0) a.part[blockIdx.x] = s;
+        if (t == 0) a.part[lb] = s;
     }
     if (a.part_w) {
         const double s = block_sum(acc, red);
-        if (t == 0) a.part_w[blockIdx.x] = s;
+        if (t == 0) a.part_w[lb] = s;
     }
     if (a.part_z) {
         const double s = block_sum(accz, red);
-        if (t == 0) a.part_z[blockIdx.x] = s;
+        if (t == 0) a.part_z[lb] = s;
     }
     if (a.part_x) {
         const double s = block_sum(accx, red);
-        if (t == 0) a.part_x[blockIdx.x] = s;
+        if (t == 0) a.part_x[lb] = s;
     }
 }
 

@@ -50,6 +50,8 @@ struct HamArgs {
     int32_t final_pass;        // 1: add D_Z x after the transform
     double JA, JB, hx, hz;
     double xscale;             // 2^-n: the two unnormalised transforms
+    int32_t xcd;               // 1: XCD-major block order (partials indexed by logical block)
+    int32_t pad;
 };
 
 // w = sigma_k (y - alpha_k u) - beta_k sigma_{k-1} p (elementwise; w may equal p)

@@ -187,6 +187,16 @@ __device__ __forceinline__ void store_tile(const Cx<Real> (&v)[1 << R], Cx<Real>
     for (int q = 0; q < (1 << R); ++q) stc<Real, NT>(b + ((uint64_t)q << L.gs), v[q]);
 }
 
+// Workgroups of a launch are handed to the eight XCDs in turn (block b to
+// XCD b mod 8).  XCD-major order renumbers them so that each XCD walks a
+// contiguous range of tiles (of a grid-stride loop's round), so neighbouring
+// tiles meet in one L2 and each XCD streams one region of the state.  A
+// bijection of [0, nb) when nb is a multiple of 8; other grids keep their
+// order.
+__device__ __forceinline__ uint32_t xcd_major(uint32_t b, uint32_t nb) {
+    return (nb & 7u) ? b : (b & 7u) * (nb >> 3) + (b >> 3);
+}
+
 __device__ __forceinline__ double wave_sum(double x) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
