@@ -597,7 +597,10 @@ z2h_status z2h_autotune(int32_t Lx, int32_t Ly, z2h_dtype dtype, int32_t batch, 
 
 /* Plan with an explicit schedule string (as returned by z2h_autotune):
  * "split=G:R:m:c/..." lists, from the lowest qubits up, each transform
- * group's width G, register window 2^R, tile bits m and carried low bits c;
+ * group's width G, register window 2^R, tile bits m and carried low bits c,
+ * optionally followed by ":2" (two neighbouring tiles per workgroup, in two
+ * register windows per thread) or ":2s" (the same two tiles on the two
+ * halves of a workgroup of twice the threads, which share one tile's LDS);
  * "uniform,m=..,c=..,R=..,g0=.." is the general planner with fixed tile
  * parameters.  Either may end in ",nt=1" (streaming loads and stores)
  * and ",xcd=<mask>" (bit j set: the workgroups of the passes over group j

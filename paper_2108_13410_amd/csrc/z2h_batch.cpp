@@ -372,7 +372,7 @@ static int choose_slots(const Plan &P, const std::vector<JobDev> &h_jobs, int de
     double waves_per_job = 0.0;
     for (int k = 0; k < P.K; ++k) {
         const GroupGeom &g = P.geom[k];
-        const double blocks = (double)(1ull << g.tiles_log2) / (g.pair == 2 ? 2.0 : 1.0);
+        const double blocks = (double)(1ull << g.tiles_log2) / (g.pair >= 2 ? 2.0 : 1.0);
         const int per_cu = std::max(1, std::min(4, (int)(kMaxLdsBytes / std::max<size_t>(1, lds_bytes(P, g, g.R)))));
         waves_per_job = std::max(waves_per_job, blocks / ((double)per_cu * cus));
     }

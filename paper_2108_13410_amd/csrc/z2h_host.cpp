@@ -127,7 +127,9 @@ static void choose_lds_blk(const Plan &P, GroupGeom &g) {
     g.lds_blk = 0;
     if (!g.full) return;
     const int R = g.R, G = R * g.full, x0 = g.x0, x1 = g.x1;
-    const int lb = P.c128 ? 4 : 5;
+    // slots per 256 bytes: elements of 8 or 16 bytes, or components of 4 or
+    // 8 bytes with the component exchange
+    const int lb = (P.c128 ? 4 : 5) + (g.cx ? 1 : 0);
     const uint32_t nb = 1u << lb, span = (1u << G) + (1u << (G - R));
     const uint32_t lanes = std::min<uint32_t>(64, 1u << (g.m - R));
     int best_bad = 1 << 30;
@@ -138,7 +140,7 @@ static void choose_lds_blk(const Plan &P, GroupGeom &g) {
         for (int j = 0; j < g.full; ++j) {
             const int p = x1 - R * (j + 1);
             for (uint32_t w0 = 0; w0 < lanes; w0 += nb) {
-                uint32_t hit[32] = {0};
+                uint32_t hit[64] = {0};
                 for (uint32_t l = w0; l < std::min(lanes, w0 + nb); ++l) {
                     const uint32_t e = ((l >> p) << (p + R)) | (l & ((1u << p) - 1u));
                     const uint32_t tb = (e >> x0) & ((1u << G) - 1u);
@@ -250,6 +252,7 @@ static z2h_status plan_uniform(Plan &P, int m_pref, int m_hi, int c_min, int for
 struct GroupChoice {
     int G, R, NL, m, c;
     int np;  // tiles per block: 1, or 2 (two-tile blocks of a strided group)
+    int cx = 0;  // one-tile blocks: 1 = layout changes exchange one component at a time
 };
 
 static bool fit_group(const Plan &P, int j, int b0, int G, int R, int NL, int m_pref, int m_hi, int c_min,
@@ -357,7 +360,15 @@ static z2h_status apply_split(Plan &P, const GroupChoice *ch, int K) {
         g.x1 = g.c + ch[j].G;
         g.tiles_log2 = n - g.m;
         plan_layouts(g, false);
-        if (ch[j].np != 1 && ch[j].np != 2) return fail(Z2H_ERR_INVALID, "group %d: %d tiles per block", j, ch[j].np);
+        if ((ch[j].np != 1 && ch[j].np != 2) || (ch[j].cx && ch[j].np != 1))
+            return fail(Z2H_ERR_INVALID, "group %d: bad tiles-per-block option", j);
+        g.cx = 0;
+        if (ch[j].cx) {
+            if (!g.full || !cx_level_ok(g.R, g.full))
+                return fail(Z2H_ERR_UNSUPPORTED, "group %d: no component-exchange kernel for window %d x %d", j, g.R,
+                            g.full);
+            g.cx = 1;
+        }
         if (ch[j].np == 2) {
             // the block's two tiles differ in the lowest tile bit, which must
             // sit right above the carried bits (strided group) or right above
@@ -420,7 +431,10 @@ static void plan_base(int Lx, int Ly, bool c128, Plan &P) {
 }
 
 // A schedule configuration string: "split=G:R:m:c/G:R:m:c/..." (groups from
-// the lowest qubits up) or "uniform,m=..,R=..,c=..,g0=.."; either may add
+// the lowest qubits up; a group may end in ":2", two tiles per block in two
+// register windows, or ":1c", one tile per block whose layout changes
+// exchange the real and then the imaginary parts through half the LDS) or
+// "uniform,m=..,R=..,c=..,g0=.."; either may add
 // ",nt=1" (streaming loads and stores in the general pass kernel) and
 // ",xcd=<mask>" (XCD-major block order in the passes over group j when bit
 // j of the mask is set).
@@ -434,11 +448,17 @@ static z2h_status plan_from_config(Plan &P, const char *cfg, int m_pref, int m_h
         int K = 0;
         q += 6;
         while (*q && K < kMaxGroups) {
-            int G, R, m, c, np = 1, used = 0, used2 = 0;
+            int G, R, m, c, np = 1, cx = 0, used = 0, used2 = 0;
             if (sscanf(q, "%d:%d:%d:%d%n", &G, &R, &m, &c, &used) != 4) break;
             q += used;
-            if (*q == ':' && sscanf(q, ":%d%n", &np, &used2) == 1) q += used2;
-            ch[K++] = {G, R, G / std::max(R, 1), m, c, np};
+            if (*q == ':' && sscanf(q, ":%d%n", &np, &used2) == 1) {
+                q += used2;
+                if (*q == 'c') {  // ":1c": component exchange
+                    ++q;
+                    cx = 1;
+                }
+            }
+            ch[K++] = {G, R, G / std::max(R, 1), m, c, np, cx};
             if (*q != '/') break;
             ++q;
         }
@@ -541,9 +561,11 @@ z2h_status make_plan(int Lx, int Ly, bool c128, int max_tile_bits, Plan &P, int 
 
 // Tile options of one group of a split: every (m, c) whose block size is
 // within the launch bounds and whose tile fits LDS, with contiguous runs of
-// at least 64 bytes for groups that carry low bits.
+// at least 64 bytes for groups that carry low bits; strided tiles too large
+// for two workgroups per CU also with the component exchange.
 struct TileOpt {
     int m, c, np;
+    int cx = 0;
 };
 
 static std::vector<TileOpt> group_tiles(const Plan &P, int j, int b0, int G, int R, int m_hi) {
@@ -572,6 +594,13 @@ static std::vector<TileOpt> group_tiles(const Plan &P, int j, int b0, int G, int
         if (m - R >= 6 && m - R <= 9 && lds_ok(m)) {
             out.push_back({m, c, 1});
             if (pair && c >= 4 && b0 - c >= 1 && P.n - m >= 1) out.push_back({m, c, 2});
+            GroupGeom g{};
+            g.m = m;
+            g.R = R;
+            g.full = G % R == 0 ? G / R : 0;
+            g.c = c;
+            if (g.full && cx_level_ok(R, g.full) && 2 * lds_bytes(P, g, R) > (size_t)kMaxLdsBytes)
+                out.push_back({m, c, 1, 1});
         }
     }
     return out;
@@ -620,14 +649,17 @@ std::vector<std::string> tune_candidates(int Lx, int Ly, bool c128) {
         for (size_t idx = 0; idx < combos && out.size() < kMaxCands; ++idx) {
             std::string cfg = "split=";
             size_t r = idx;
+            int xcd = 1;  // group 0, and the groups with the component exchange
             for (int j = 0; j < sc.K; ++j) {
                 const auto &o = opts[j][r % opts[j].size()];
                 r /= opts[j].size();
                 char buf[64];
                 snprintf(buf, sizeof buf, "%s%d:%d:%d:%d%s", j ? "/" : "", sc.g[j].G, sc.g[j].R, o.m, o.c,
-                         o.np == 2 ? ":2" : "");
+                         o.np == 2 ? ":2" : (o.cx ? ":1c" : ""));
                 cfg += buf;
+                if (o.cx) xcd |= 1 << j;
             }
+            if (xcd != 1) cfg += ",xcd=" + std::to_string(xcd);
             if (std::find(out.begin(), out.end(), cfg) == out.end()) out.push_back(cfg);
         }
         if (out.size() >= kMaxCands) break;
@@ -669,10 +701,13 @@ size_t lds_bytes(const Plan &P, const GroupGeom &g, int R) {
                                      : ((size_t)1 << G) + ((size_t)1 << (G - R)) + (P.c128 ? 15 : 31);
         elems = std::max(elems, ((size_t)1 << (g.m - G)) * blk);
     }
-    size_t b = elems * P.esize;
+    // exchange region (one element per slot, or one component with the
+    // component exchange; it also holds the table's FP64 factors while the
+    // table is built)
+    size_t b = elems * (g.cx ? P.esize / 2 : P.esize);
+    if (g.cx) b = (b + 15) & ~(size_t)15;
     b += (size_t)(P.nst + 1) * (P.n + 1) * P.esize;  // phase table
     b = (b + 15) & ~(size_t)15;
-    b += (size_t)(P.nst + 1 + P.n + 1) * 16;         // FP64 factors
     b += 16 * sizeof(double);                        // block reduction
     return b;
 }
@@ -1187,7 +1222,8 @@ z2h_status z2h_plan_describe(const z2h_plan *plan, char *buf, size_t len) {
         s += "], \"bhi\": [";
         for (int l = 0; l < g.nlay; ++l) s += (l ? ", " : "") + std::to_string(g.bhi[l]);
         s += "], \"lds_bytes\": " + std::to_string(lds_bytes(P, g, g.R)) + ", \"R\": " + std::to_string(g.R) +
-             ", \"full\": " + std::to_string(g.full) + ", \"pair\": " + std::to_string(g.pair == 2 ? 2 : 1) +
+             ", \"full\": " + std::to_string(g.full) + ", \"pair\": " + std::to_string(g.pair >= 2 ? 2 : 1) +
+             ", \"cx\": " + std::to_string(g.cx) +
              ", \"lds_blk\": " + std::to_string(g.lds_blk) + "}";
     }
     s += "]}";

@@ -39,6 +39,9 @@ struct GroupGeom {
     int32_t tiles_log2;                 // tiles per state = 2^(n - m)
     int32_t pair;                       // 2: each block handles tiles 2u, 2u + 1 (else 1 or 0)
     int32_t lds_blk;                    // full-window LDS block per value of the untransformed bits
+    int32_t cx;                         // 1: layout changes exchange the real, then the imaginary
+                                        // parts (LDS of one component per slot)
+    int32_t pad;
 };
 
 // Per-job data for the level-synchronous pass kernel.

@@ -132,6 +132,7 @@ LevelOp level_op_host(int lev, int K, int S, int k0, int order);
 // Register-window shapes (R, NL) with a compiled straight-line kernel.
 bool full_level_ok(int R, int NL);
 bool pair_level_ok(bool c128, int R, int NL);  // two-tile blocks compiled for this shape
+bool cx_level_ok(int R, int NL);               // component-exchange kernels compiled for this shape
 bool full_resident_ok(int R, int NL);
 
 // Set the dynamic-LDS limit of every kernel (call before graph capture).

@@ -39,6 +39,14 @@ __device__ __forceinline__ void load_tiles(Cx<Real> (&v)[NT][1 << R], const Cx<R
     }
 }
 
+// FP64 factors of the phase table live at the start of the exchange
+// region: every kernel builds its table while no layout change is in flight
+// (before the first exchange of a pass, or after the closing barrier of the
+// last one), and the region (at least 2^8 elements) outsizes the factors.
+__device__ __forceinline__ double2 *table_scratch(unsigned char *smem) {
+    return reinterpret_cast<double2 *>(smem);
+}
+
 // Build the phase table T[k][w] = scale * exp(i (alpha (nst - 2k) + beta (n - 2w)))
 // in LDS (FP64 angles and products, cast to Real).  Two stages so that a
 // pass can compute the factors while its tile loads are in flight and apply
@@ -252,8 +260,8 @@ __global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
     const uint32_t lds_elems = (1u << g.m) + (1u << (g.m - R));
     Cx<Real> *tab = lds + lds_elems;
     const int W = a.lat.n + 1;
-    double2 *fac = align16<double2>(tab + (a.lat.nst + 1) * W);
-    double *red = reinterpret_cast<double *>(fac + (a.lat.nst + 1 + W));
+    double2 *fac = table_scratch(smem);
+    double *red = align16<double>(tab + (a.lat.nst + 1) * W);
 
     const bool has_phase = op.kind != kPlainH;
     const bool preH = op.kind != kHalfIn;
@@ -447,39 +455,64 @@ __device__ __forceinline__ void xchg_rot(Cx<Real> (&v)[1 << R], Cx<Real> *lds, u
     __syncthreads();
 }
 
-template <typename Real, int R, int NL, int J>
+// Layout change with CX = 1: the real parts, then the imaginary parts,
+// through an LDS block of one component per slot (half the bytes of a
+// tile), so that two workgroups of a large tile fit on one CU.  Same slots
+// as the element exchange; CX = 0 is the element exchange.
+template <typename Real, int R, int PF, int PT, int CX>
+__device__ __forceinline__ void xchg_rot_x(Cx<Real> (&v)[1 << R], Cx<Real> *lds, uint32_t bf, uint32_t bt) {
+    if constexpr (CX == 0) {
+        xchg_rot<Real, R, PF, PT>(v, lds, bf, bt);
+    } else {
+        Real *l = reinterpret_cast<Real *>(lds);
+#pragma unroll
+        for (int q = 0; q < (1 << R); ++q) l[bf + slot<R>((uint32_t)q << PF)] = v[q].x;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < (1 << R); ++q) v[q].x = l[bt + slot<R>((uint32_t)q << PT)];
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < (1 << R); ++q) l[bf + slot<R>((uint32_t)q << PF)] = v[q].y;
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < (1 << R); ++q) v[q].y = l[bt + slot<R>((uint32_t)q << PT)];
+        __syncthreads();
+    }
+}
+
+template <typename Real, int R, int NL, int J, int CX = 0>
 __device__ __forceinline__ void fwd_rot_from(Cx<Real> (&v)[1 << R], Cx<Real> *lds, const LdsMap<R, NL> &M) {
     if constexpr (J < NL) {
-        xchg_rot<Real, R, R * (NL - J), R * (NL - 1 - J)>(v, lds, M.base[J - 1], M.base[J]);
+        xchg_rot_x<Real, R, R * (NL - J), R * (NL - 1 - J), CX>(v, lds, M.base[J - 1], M.base[J]);
         bfly_all<Real, R>(v);
-        fwd_rot_from<Real, R, NL, J + 1>(v, lds, M);
+        fwd_rot_from<Real, R, NL, J + 1, CX>(v, lds, M);
     }
 }
 
 // Transform over the group: layouts 0 .. NL-1 (ends in layout NL-1).
-template <typename Real, int R, int NL>
+template <typename Real, int R, int NL, int CX = 0>
 __device__ __forceinline__ void fwd_rot(Cx<Real> (&v)[1 << R], Cx<Real> *lds, const LdsMap<R, NL> &M) {
     bfly_all<Real, R>(v);
-    fwd_rot_from<Real, R, NL, 1>(v, lds, M);
+    fwd_rot_from<Real, R, NL, 1, CX>(v, lds, M);
 }
 
-template <typename Real, int R, int NL, int J>
+template <typename Real, int R, int NL, int J, int CX = 0>
 __device__ __forceinline__ void bwd_rot_from(Cx<Real> (&v)[1 << R], Cx<Real> *lds, const LdsMap<R, NL> &M) {
     if constexpr (J >= 1) {
-        xchg_rot<Real, R, R * (NL - 1 - J), R * (NL - J)>(v, lds, M.base[J], M.base[J - 1]);
+        xchg_rot_x<Real, R, R * (NL - 1 - J), R * (NL - J), CX>(v, lds, M.base[J], M.base[J - 1]);
         bfly_all<Real, R>(v);
-        bwd_rot_from<Real, R, NL, J - 1>(v, lds, M);
+        bwd_rot_from<Real, R, NL, J - 1, CX>(v, lds, M);
     }
 }
 
 // Transform over the group starting in layout NL-1 (ends in layout 0).
-template <typename Real, int R, int NL>
+template <typename Real, int R, int NL, int CX = 0>
 __device__ __forceinline__ void bwd_rot(Cx<Real> (&v)[1 << R], Cx<Real> *lds, const LdsMap<R, NL> &M) {
     bfly_all<Real, R>(v);
-    bwd_rot_from<Real, R, NL, NL - 1>(v, lds, M);
+    bwd_rot_from<Real, R, NL, NL - 1, CX>(v, lds, M);
 }
 
-template <typename Real, int R, int NL, int KIND, int NT>
+template <typename Real, int R, int NL, int KIND, int NT, int CX = 0>
 __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, const LevelOp &op,
                                            uint64_t tile0, uint32_t t, Cx<Real> (&v)[NT][1 << R],
                                            Cx<Real> *st, const LayCtx<R> (&L0)[NT], Cx<Real> *lds,
@@ -518,7 +551,7 @@ __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, 
     LdsMap<R, NL> M;
     lds_map<R, NL, Real>(M, g, t);
 #pragma unroll
-    for (int s = 0; s < NT; ++s) fwd_rot<Real, R, NL>(v[s], lds, M);
+    for (int s = 0; s < NT; ++s) fwd_rot<Real, R, NL, CX>(v[s], lds, M);
     if constexpr (kPhase && KIND != kHalfIn) {
         if (want_norm) renorm_table<Real>(a, J, op, tile0, t, part, tab, red);
     }
@@ -539,9 +572,9 @@ __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, 
 #pragma unroll
     for (int s = 0; s < NT; ++s) {
         if constexpr (KIND == kPhaseB) {
-            bwd_rot<Real, R, NL>(v[s], lds, M);
+            bwd_rot<Real, R, NL, CX>(v[s], lds, M);
         } else {
-            if constexpr (NL > 1) xchg_rot<Real, R, 0, R * (NL - 1)>(v[s], lds, M.base[NL - 1], M.base[0]);
+            if constexpr (NL > 1) xchg_rot_x<Real, R, 0, R * (NL - 1), CX>(v[s], lds, M.base[NL - 1], M.base[0]);
         }
         store_tile<Real, R, true>(v[s], st, L0[s]);
     }
@@ -557,8 +590,8 @@ constexpr int kAnyKind = -1;
 // NT: consecutive tiles per block (1, or 2 for strided groups whose tiles
 // carry 128-byte rows: the two tiles of a block differ only in the lowest
 // tile bit, so each block reads and writes 256 contiguous bytes per row).
-template <typename Real, int R, int NL, int KS, int NT>
-__global__ void __launch_bounds__(512) level_kernel_full(LevelArgs a) {
+template <typename Real, int R, int NL, int KS, int NT, int CX>
+__device__ __forceinline__ void level_body(const LevelArgs &a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const GroupGeom &g = a.geom;
     const uint32_t t = threadIdx.x;
@@ -587,21 +620,35 @@ __global__ void __launch_bounds__(512) level_kernel_full(LevelArgs a) {
 
     Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
     const uint32_t lds_elems = (1u << (g.m - R * NL)) * (uint32_t)g.lds_blk;
-    Cx<Real> *tab = lds + lds_elems;
+    // the exchange region holds one element (CX: one component) per slot
+    Cx<Real> *tab = CX ? align16<Cx<Real>>(reinterpret_cast<Real *>(smem) + lds_elems) : lds + lds_elems;
     const int W = a.lat.n + 1;
-    double2 *fac = align16<double2>(tab + (a.lat.nst + 1) * W);
-    double *red = reinterpret_cast<double *>(fac + (a.lat.nst + 1 + W));
+    double2 *fac = table_scratch(smem);
+    double *red = align16<double>(tab + (a.lat.nst + 1) * W);
 
     if constexpr (KS != kAnyKind) {
-        pass_multi<Real, R, NL, KS, NT>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red);
+        pass_multi<Real, R, NL, KS, NT, CX>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red);
     } else {
         switch (op.kind) {
-            case kPhaseB: pass_multi<Real, R, NL, kPhaseB, NT>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
-            case kPlainH: pass_multi<Real, R, NL, kPlainH, NT>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
-            case kHalfIn: pass_multi<Real, R, NL, kHalfIn, NT>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
-            default: pass_multi<Real, R, NL, kHalfOut, NT>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
+            case kPhaseB: pass_multi<Real, R, NL, kPhaseB, NT, CX>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
+            case kPlainH: pass_multi<Real, R, NL, kPlainH, NT, CX>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
+            case kHalfIn: pass_multi<Real, R, NL, kHalfIn, NT, CX>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
+            default: pass_multi<Real, R, NL, kHalfOut, NT, CX>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
         }
     }
+}
+
+template <typename Real, int R, int NL, int KS, int NT>
+__global__ void __launch_bounds__(512) level_kernel_full(LevelArgs a) {
+    level_body<Real, R, NL, KS, NT, 0>(a);
+}
+
+// One tile per workgroup with the component exchange: two workgroups per CU
+// (complex64: four waves per SIMD, so at most 128 registers per thread).
+template <typename Real, int R, int NL, int KS>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 4 : 2)))
+level_kernel_cx(LevelArgs a) {
+    level_body<Real, R, NL, KS, 1, 1>(a);
 }
 
 // ---------------------------------------------------------------- resident kernel
@@ -625,8 +672,8 @@ __global__ void __launch_bounds__(512) resident_kernel(ResidentArgs a) {
     Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
     const uint32_t lds_elems = (1u << g.m) + (1u << (g.m - R));
     Cx<Real> *tab = lds + lds_elems;
-    double2 *fac = align16<double2>(tab + (nst + 1) * W);
-    double *red = reinterpret_cast<double *>(fac + (nst + 1 + W));
+    double2 *fac = table_scratch(smem);
+    double *red = align16<double>(tab + (nst + 1) * W);
 
     Cx<Real> v[1 << R];
     Cx<Real> *st = reinterpret_cast<Cx<Real> *>(a.states) + J.offset;
@@ -727,8 +774,8 @@ __global__ void __launch_bounds__(512) adj_kernel(AdjArgs a) {
     Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
     const uint32_t lds_elems = (1u << g.m) + (1u << (g.m - R));
     Cx<Real> *tab = lds + lds_elems;
-    double2 *fac = align16<double2>(tab + (nst + 1) * W);
-    double *red = reinterpret_cast<double *>(fac + (nst + 1 + W));
+    double2 *fac = table_scratch(smem);
+    double *red = align16<double>(tab + (nst + 1) * W);
     const int x1 = g.x1, p0 = x1 - R, pl = x1 - R * NL;
     Cx<Real> *A = reinterpret_cast<Cx<Real> *>(a.A);
     Cx<Real> *B = reinterpret_cast<Cx<Real> *>(a.B);
@@ -1048,8 +1095,31 @@ static hipError_t do_level_full_nt(const LevelArgs &a, dim3 grid, size_t lds, hi
 // 2^R complex doubles would not fit the register budget).
 #define Z2H_PAIR_SHAPES(X) X(5, 2) X(4, 2) X(4, 3) X(3, 2) X(3, 3)
 
+// Shapes with a component-exchange variant (one tile per workgroup).
+#define Z2H_CX_SHAPES(X) X(5, 2)
+
+template <typename Real, int R, int NL, int KS>
+static hipError_t do_level_cx_ks(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    const void *fn = reinterpret_cast<const void *>(&level_kernel_cx<Real, R, NL, KS>);
+    hipError_t e = set_lds(fn, lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((level_kernel_cx<Real, R, NL, KS>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
+    return hipGetLastError();
+}
+
 template <typename Real, int R, int NL>
 static hipError_t do_level_full(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    if (a.geom.cx) {
+#define Z2H_CX_CALL(r, nl)                                                                               \
+        if (R == r && NL == nl) {                                                                        \
+            if (a.kind_hint == kPhaseB) return do_level_cx_ks<Real, r, nl, kPhaseB>(a, grid, lds, s);    \
+            if (a.kind_hint == kPlainH) return do_level_cx_ks<Real, r, nl, kPlainH>(a, grid, lds, s);    \
+            return do_level_cx_ks<Real, r, nl, kAnyKind>(a, grid, lds, s);                               \
+        }
+        Z2H_CX_SHAPES(Z2H_CX_CALL)
+#undef Z2H_CX_CALL
+        return hipErrorInvalidValue;
+    }
     if (a.geom.pair == 2) {
         if constexpr (sizeof(Real) == 4) {
 #define Z2H_PAIR_CALL(r, nl) \
@@ -1060,6 +1130,13 @@ static hipError_t do_level_full(const LevelArgs &a, dim3 grid, size_t lds, hipSt
         return hipErrorInvalidValue;
     }
     return do_level_full_nt<Real, R, NL, 1>(a, grid, lds, s);
+}
+
+bool cx_level_ok(int R, int NL) {
+#define Z2H_OK_CX(r, nl) if (R == r && NL == nl) return true;
+    Z2H_CX_SHAPES(Z2H_OK_CX)
+#undef Z2H_OK_CX
+    return false;
 }
 
 bool pair_level_ok(bool c128, int R, int NL) {
@@ -1178,6 +1255,12 @@ static hipError_t prep_real() {
         Z2H_PAIR_SHAPES(Z2H_PREP_PAIR)
 #undef Z2H_PREP_PAIR
     }
+#define Z2H_PREP_CX(r, nl) \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_cx<Real, r, nl, kAnyKind>), kMaxLdsBytes); \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_cx<Real, r, nl, kPhaseB>), kMaxLdsBytes); \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_cx<Real, r, nl, kPlainH>), kMaxLdsBytes);
+    Z2H_CX_SHAPES(Z2H_PREP_CX)
+#undef Z2H_PREP_CX
 #define Z2H_PREP_RES(r, nl) \
     if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&resident_kernel<Real, r, nl>), kMaxLdsBytes);
     Z2H_FULL_RESIDENT_SHAPES(Z2H_PREP_RES)

@@ -176,17 +176,21 @@ def test_three_group_schedule_against_oracle(Lx, Ly, dtype, M):
 
 
 def test_4x4_two_tile_schedule_bitwise():
-    """The autotuned complex64 4x4 schedule (two 128-byte tiles per block in
-    both strided groups) computes exactly what the planner's default schedule
+    """The complex64 4x4 schedules with two 128-byte tiles per block, and
+    with one tile per block and the component exchange (XCD-major order in
+    every group), compute exactly what the planner's default schedule
     computes: blocks only regroup tiles and the renormalisation sums per-tile
     partials in the same order, so 6 Trotter steps of the 4x4 ramp leave
     bit-identical states (checked on 2^20 sampled amplitudes). The observables
     are FP64 sums whose partials follow each plan's own first-group tiling,
     so they agree to rounding (1e-13 relative)."""
-    print("case 4x4 c64 two-tile schedule vs default", flush=True)
+    print("case 4x4 c64 two-tile and component-exchange schedules vs default", flush=True)
     cfg = "split=12:4:12:0/10:5:14:4:2/10:5:14:4:2"
-    plans = [z2h.z2h_plan_create(4, 4, z2h.Z2H_C64), z2h.z2h_plan_create_config(4, 4, z2h.Z2H_C64, cfg)]
+    cfg_cx = "split=12:4:12:0/10:5:14:4:1c/10:5:14:4:1c,xcd=7"
+    plans = [z2h.z2h_plan_create(4, 4, z2h.Z2H_C64), z2h.z2h_plan_create_config(4, 4, z2h.Z2H_C64, cfg),
+             z2h.z2h_plan_create_config(4, 4, z2h.Z2H_C64, cfg_cx)]
     assert [g.get("pair", 1) for g in z2h.z2h_plan_describe(plans[1])["groups"]] == [1, 2, 2]
+    assert [g["cx"] for g in z2h.z2h_plan_describe(plans[2])["groups"]] == [0, 1, 1]
     sz = z2h.z2h_plan_sizes(plans[0])
     ws = z2h.alloc_bytes(max(sz["ws_evolve"], sz["ws_observe"]))
     psi = z2h.alloc_state(plans[0])
@@ -200,9 +204,10 @@ def test_4x4_two_tile_schedule_bitwise():
                                                    k_end=6, renorm=1))
         samples.append(torch.view_as_real(psi[idx]).cpu())
         obs.append(z2h.z2h_observe(plan, psi, ws, job["c1"]))
-    assert torch.equal(samples[0], samples[1])
-    for key in ("energy", "norm", "mx", "mz"):
-        assert abs(obs[0][key] - obs[1][key]) <= 1e-13 * max(1.0, abs(obs[0][key])), key
+    for k in (1, 2):
+        assert torch.equal(samples[0], samples[k])
+        for key in ("energy", "norm", "mx", "mz"):
+            assert abs(obs[0][key] - obs[k][key]) <= 1e-13 * max(1.0, abs(obs[0][key])), key
 
 
 def _plaquette_codewords():

@@ -156,6 +156,19 @@ def test_schedule_strings_rejected():
     ok = z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C64, "split=10:5:11:0/8:4:12:4:2")
     assert z2h.z2h_plan_describe(ok)["groups"][1]["pair"] == 2
     check_geometry(ok)
+    # component exchange: one tile per block, shapes with a compiled kernel
+    for dt, cfg in ((z2h.Z2H_C64, "split=10:5:11:0:1c/10:5:14:4:1c"), (z2h.Z2H_C128, "split=10:5:11:0/10:5:13:3:1c")):
+        cp = z2h.z2h_plan_create_config(2, 5, dt, cfg)
+        d = z2h.z2h_plan_describe(cp)
+        assert [g["cx"] for g in d["groups"]] == ([1, 1] if dt == z2h.Z2H_C64 else [0, 1])
+        full = z2h.z2h_plan_describe(z2h.z2h_plan_create_config(2, 5, dt, cfg.replace(":1c", "")))
+        assert d["groups"][1]["lds_bytes"] < 0.6 * full["groups"][1]["lds_bytes"]
+        check_geometry(cp)
+    for bad in ("split=10:5:11:0:2c/10:5:14:4", "split=10:5:11:0:3/10:5:14:4"):
+        with pytest.raises(z2h.Z2HError):
+            z2h.z2h_plan_create_config(2, 5, z2h.Z2H_C64, bad)
+    with pytest.raises(z2h.Z2HError):  # window shape without a component-exchange kernel
+        z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C64, "split=12:4:12:0/6:3:11:5:1c")
     # group 0 in two-tile blocks (two adjacent chunks)
     ok0 = z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C64, "split=12:4:12:0:2/6:3:11:5:2")
     assert [g["pair"] for g in z2h.z2h_plan_describe(ok0)["groups"]] == [2, 2]
@@ -171,7 +184,8 @@ def check_full_lds(g, n, esize):
     G = R * NL
     blk = g["lds_blk"]
     assert blk >= (1 << G) + (1 << (G - R))
-    lb = 5 if esize == 8 else 4
+    ex = esize // 2 if g.get("cx") else esize  # bytes per LDS slot (component exchange: one component)
+    lb = {4: 6, 8: 5, 16: 4}[ex]
 
     def place(e):
         tb = (e >> x0) & ((1 << G) - 1)
@@ -182,7 +196,8 @@ def check_full_lds(g, n, esize):
     a = place(e)
     assert np.unique(a).size == e.size
     assert a.max() < (1 << (m - G)) * blk
-    assert (1 << (m - G)) * blk * esize + (n // 2 + 1) * (n + 1) * esize <= LDS_LIMIT
+    assert (1 << (m - G)) * blk * ex + (n // 2 + 1) * (n + 1) * esize <= LDS_LIMIT
+    assert g["lds_bytes"] <= LDS_LIMIT
     threads = 1 << (m - R)
     t = np.arange(threads)
     for j in range(NL):
