@@ -576,7 +576,21 @@ __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, 
         } else {
             if constexpr (NL > 1) xchg_rot_x<Real, R, 0, R * (NL - 1), CX>(v[s], lds, M.base[NL - 1], M.base[0]);
         }
-        store_tile<Real, R, true>(v[s], st, L0[s]);
+        if constexpr (NT == 1) {
+            // one tile: the store address is recomputed from an opaque copy
+            // of the thread index rather than kept live through the pass
+            // (two registers, which spill at the component exchange's
+            // register limit).  Two-tile blocks keep it: the registers saved
+            // there raise the number of resident blocks, which measured
+            // slower on the strided rows they stream.
+            uint32_t tt = t;
+            asm volatile("" : "+v"(tt));
+            LayCtx<R> Ls;
+            lay_ctx<R>(Ls, g, a.lat, tile0 + s, x1 - R, tt, false);
+            store_tile<Real, R, true>(v[s], st, Ls);
+        } else {
+            store_tile<Real, R, true>(v[s], st, L0[s]);
+        }
     }
 }
 
@@ -606,16 +620,28 @@ __device__ __forceinline__ void level_body(const LevelArgs &a) {
     LayCtx<R> L0[NT];
 #pragma unroll
     for (int s = 0; s < NT; ++s) lay_ctx<R>(L0[s], g, a.lat, tile0 + s, g.x1 - R, t, false);
+    // The tile loads are issued at one point of the code (two load sites
+    // would hold registers for both and spill).  With a uniform job stride
+    // (jmode 0) they go out before the job record is read; otherwise the
+    // record (scalar loads) gives the state's offset first, and a block whose
+    // job has no pass at this level returns before loading.
     Cx<Real> *st = base + a.jbase + (uint64_t)jb * a.jstride;
-    if (a.jmode == 0) load_tiles<Real, R, NT>(v, st, L0);
-
-    const JobDev J = job_record(a.jobs, a.jidx ? job_index(a.jidx, jb) : jb, a.job_inline);
-    const LevelOp op = a.force_plain ? LevelOp{a.group, kPlainH, 0, -1, -1, 0, 0, 0}
-                                     : level_op(a.level - J.lev0, a.K, J.steps, J.k_begin, J.order);
-    if (op.kind == kIdle || op.group != a.group) return;  // uniform per block
-    if (a.jmode != 0) {
+    JobDev J;
+    LevelOp op;
+    const bool early = a.jmode != 0;
+    if (early) {
+        J = job_record(a.jobs, a.jidx ? job_index(a.jidx, jb) : jb, a.job_inline);
+        op = a.force_plain ? LevelOp{a.group, kPlainH, 0, -1, -1, 0, 0, 0}
+                           : level_op(a.level - J.lev0, a.K, J.steps, J.k_begin, J.order);
+        if (op.kind == kIdle || op.group != a.group) return;  // uniform per block
         st = base + J.offset;
-        load_tiles<Real, R, NT>(v, st, L0);
+    }
+    load_tiles<Real, R, NT>(v, st, L0);
+    if (!early) {
+        J = job_record(a.jobs, a.jidx ? job_index(a.jidx, jb) : jb, a.job_inline);
+        op = a.force_plain ? LevelOp{a.group, kPlainH, 0, -1, -1, 0, 0, 0}
+                           : level_op(a.level - J.lev0, a.K, J.steps, J.k_begin, J.order);
+        if (op.kind == kIdle || op.group != a.group) return;  // uniform per block
     }
 
     Cx<Real> *lds = reinterpret_cast<Cx<Real> *>(smem);
