@@ -40,7 +40,11 @@ static z2h_status adj_launch(const Plan &P, AdjArgs &a, int group, hipStream_t s
     a.geom = P.geom[group];
     a.lat = P.lat;
     const unsigned nb = 1u << a.geom.tiles_log2;
-    hipError_t e = launch_adj(P.c128, a, nb, lds_bytes(P, a.geom, a.geom.R), s);
+    // the adjoint kernel exchanges whole elements whatever the group's
+    // exchange in the Trotter passes: size its LDS for that
+    GroupGeom ge = a.geom;
+    ge.cx = 0;
+    hipError_t e = launch_adj(P.c128, a, nb, lds_bytes(P, ge, ge.R), s);
     if (e != hipSuccess) return fail(Z2H_ERR_HIP, "adjoint kernel launch failed: %s", hipGetErrorString(e));
     return Z2H_OK;
 }

@@ -65,6 +65,32 @@ def test_adjoint_plans_agree():
     np.testing.assert_allclose(a[2], b[2], atol=1e-11)
 
 
+@pytest.mark.parametrize("dtype,cfg", [(z2h.Z2H_C128, "split=10:5:11:0/10:5:13:3:1c"),
+                                       (z2h.Z2H_C64, "split=10:5:11:0:1c/10:5:14:4:1c")])
+def test_adjoint_component_exchange_plan(dtype, cfg):
+    """2x5 torus: a plan whose Trotter passes use the component exchange
+    (half the LDS) gives the gradient of the same plan with element
+    exchanges; the adjoint's own kernels size their LDS for whole elements."""
+    print(f"case adjoint 2x5 dtype={dtype} {cfg}", flush=True)
+    rng = np.random.default_rng(8)
+    M, dt = 6, 0.15
+    c0, c1, H = (1, 1, 0, 0), (1, 0.9, 0.35, 0.25), (1, 0.9, 0.35, 0.25)
+    sZ = (np.arange(M) + 0.5) / M + rng.normal(0, 0.01, M)
+    sX = (np.arange(M) + 0.5) / M + rng.normal(0, 0.01, M)
+    out = []
+    for c in (cfg, cfg.replace(":1c", "")):
+        plan = z2h.z2h_plan_create_config(2, 5, dtype, c)
+        tz = torch.tensor(sZ, dtype=torch.float64, requires_grad=True)
+        tx = torch.tensor(sX, dtype=torch.float64, requires_grad=True)
+        L = EvolveEnergy.apply(tz, tx, plan, c0, c1, dt, H)
+        L.backward()
+        out.append((L.item(), tz.grad.numpy(), tx.grad.numpy()))
+    assert out[0][0] == out[1][0]
+    np.testing.assert_array_equal(out[0][1], out[1][1])
+    np.testing.assert_array_equal(out[0][2], out[1][2])
+    assert np.all(np.isfinite(out[0][1])) and np.abs(out[0][1]).max() > 0
+
+
 @pytest.mark.slow
 def test_adjoint_3x3_config():
     """3x3 torus, M = 200 (T = 20), two schedule values per step from the
