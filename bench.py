@@ -43,7 +43,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_scan_3x3_c64.json")
 SHIPPED_TABLE = os.path.join(ROOT, "paper_2108_13410_amd", "tuned_mi355x.txt")
 # sources the scan's pass kernels are compiled from (the traffic record is
 # keyed by their hash)
-EXACT_4X4_SPLIT = "split=12:4:12:0/10:4:13:3/10:4:13:3"
+EXACT_4X4_SPLIT = "split=12:4:12:0/10:4:13:3/10:4:13:3,xcd=7"
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2108_13410_amd", "csrc", f)
                for f in ("z2h_kernels.hip", "z2h_tile.h", "z2h_kernels.h", "z2h_internal.h")]
 
