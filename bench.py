@@ -10,14 +10,18 @@ inside one HIP-graph launch.
 
 Printed: one JSON line with amplitude-updates/s (sum over states of 2^n per
 Trotter step), the roofline of the dominant pass kernel from HIP events
-recorded inside the timed graph launches, the plain complex128 per-point
-throughput on the same GPU, and the FP64 oracle timed on the host cores.
+around every pass kernel of the timed runs (direct launches on the kernels'
+stream; a HIP-graph replay is timed beside them), the plain complex128
+per-point throughput on the same GPU, and the FP64 oracle timed on the host
+cores.
 
-Also measured (legs of their own, outside the timed region): a plain
-streaming copy and an in-place elementwise kernel of 2 GiB (the chip's
-achievable HBM rate), and the 4x4 torus (32 link qubits, 32 GiB complex64
-and 64 GiB complex128 states) ramped to (0.25, 0.25) in 200 steps, with the
-event-timed GB/s of every pass kind.
+Also measured (legs of their own, outside the timed region): a device copy
+and an in-place elementwise kernel of 2 GiB (reference points; the copy also
+scales the rocprofv3 traffic counters), the same scan as one complex128
+batch, the 4x4 torus (32 link qubits, 32 GiB complex64 and 64 GiB complex128
+states) ramped to (0.25, 0.25) in 200 steps with the event-timed GB/s of
+every pass kind, the adjoint, the mixed batch, the exact solvers, the
+gate-level circuit and the paper's protocol paths.
 
 Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
        python bench.py --pmc-summary FETCH_CSV WRITE_CSV   (host only: turns two
