@@ -156,7 +156,10 @@ z2h_status z2h_plan_create(int32_t Lx, int32_t Ly, z2h_dtype dtype, int32_t max_
 void z2h_plan_destroy(z2h_plan *plan); /* NULL-safe */
 
 /* state_bytes = 2^n * sizeof(complex); ws_evolve_bytes = workspace needed by
- * z2h_evolve; ws_observe_bytes = workspace needed by z2h_observe (includes a
+ * z2h_evolve (the z passes' norm partials and, for multi-group plans with
+ * states of at most 64 MiB, room for the phase tables of 1024 levels, which
+ * one launch computes ahead of the pass launches that read them);
+ * ws_observe_bytes = workspace needed by z2h_observe (includes a
  * state-sized scratch copy); ws_adjoint_bytes = workspace for z2h_adjoint
  * without its per-step part: add 64 bytes per Trotter step plus 1024. */
 z2h_status z2h_plan_sizes(const z2h_plan *plan, size_t *state_bytes, size_t *ws_evolve_bytes,
@@ -194,7 +197,8 @@ z2h_status z2h_evolve(const z2h_plan *plan, void *d_state, void *d_ws, size_t ws
  * copies of sZ/sX when the schedule has them) lives in a fixed device array
  * of Z2H_NOALLOC_SCRATCH_BYTES that the library holds on every device it
  * runs on until the process ends; its address is looked up on the first
- * call on each device.  A call needs ws_evolve_bytes of it (z2h_plan_sizes),
+ * call on each device.  A call needs ws_evolve_bytes of it (z2h_plan_sizes)
+ * less the phase-table room (here every workgroup builds its own table),
  * plus 16 bytes per step and 512 when sZ or sX is given; beyond the array's
  * size it returns Z2H_ERR_UNSUPPORTED before touching the device (the 4x4
  * torus needs 8 MiB).  Arguments, schedule semantics, d_norms and the

@@ -870,6 +870,8 @@ z2h_status launch_one_level(const Plan &P, void *states, const JobSet &J, int le
     a.kind_hint = force_plain ? (int)kPlainH : kind_hint;
     a.njobs = J.njobs;
     a.jidx = J.d_jidx;
+    a.tabs = force_plain ? nullptr : J.d_tabs;
+    a.tab_lev0 = J.tab_lev0;
     job_layout(J, a);
     const uint64_t nblocks = (uint64_t)J.njobs << a.geom.tiles_log2;
     if (nblocks > 0x7fffffffull) return fail(Z2H_ERR_UNSUPPORTED, "grid of %llu blocks", (unsigned long long)nblocks);
@@ -935,10 +937,27 @@ z2h_status run_levels(const Plan &P, void *states, const JobSet &J, hipStream_t 
     }
     bool uses_norms = false;  // partials are written only where a renormalization or a trace reads them
     for (int j = 0; j < J.njobs; ++j) uses_norms = uses_norms || J.h_jobs[j].renorm || J.h_jobs[j].norm_trace;
+    // a single inline job with table room: its phase tables are computed by
+    // one launch per kTabChunk levels instead of by every workgroup
+    const bool tabs = J.d_tabs && !J.d_jobs && J.njobs == 1;
+    int tab_hi = 0, tab_lo = 0;
     int active = J.njobs;
     for (int lev = 0; lev < nlev; ++lev) {
         while (active > 0 && jl[active - 1] <= lev) --active;
         if (active == 0) break;
+        if (tabs && lev >= tab_hi) {
+            tab_lo = lev;
+            tab_hi = std::min(nlev, lev + kTabChunk);
+            TablesArgs ta;
+            memset(&ta, 0, sizeof ta);
+            ta.tabs = J.d_tabs;
+            ta.job = J.inl;
+            ta.lat = P.lat;
+            ta.lev0 = tab_lo;
+            ta.K = P.K;
+            hipError_t e = launch_tables(P.c128, ta, (unsigned)(tab_hi - tab_lo), s);
+            if (e != hipSuccess) return fail(Z2H_ERR_HIP, "table kernel launch failed: %s", hipGetErrorString(e));
+        }
         // the visited group is the same for every job; the kind may differ
         LevelOp op{};
         bool any_norm = false, uniform = true;
@@ -955,6 +974,8 @@ z2h_status run_levels(const Plan &P, void *states, const JobSet &J, hipStream_t 
         if (op.kind == kIdle) continue;
         JobSet Ja = J;
         Ja.njobs = active;
+        if (!tabs) Ja.d_tabs = nullptr;
+        Ja.tab_lev0 = tab_lo;
         z2h_status st = launch_one_level(P, states, Ja, lev, op.group, big_parts ? 1 : parts0, false,
                                          pass_kind_of(op), s, uniform ? (int)op.kind : -1);
         if (st) return st;
@@ -1090,10 +1111,27 @@ size_t norm_parts(const Plan &P) {
     return tiles + (tiles > (size_t)kReduceChunk ? (tiles + kReduceChunk - 1) / kReduceChunk : 0);
 }
 
+// Phase tables of kTabChunk levels, after everything else in the evolve
+// workspace, for multi-group plans whose phase passes run full-window
+// kernels on a cache-resident state (at most 64 MiB).  Such passes are
+// latency-bound and copying a ready table beats building it; on a large
+// state every one of its many workgroups would copy the whole table
+// (measured slower at 4x4: 9 GB of extra cache traffic per complex128 pass).
+constexpr size_t kTablesMaxState = (size_t)64 << 20;
+
+static bool tables_apply(const Plan &P) {
+    return P.K > 1 && P.geom[0].full && P.geom[P.K - 1].full && (P.esize << P.n) <= kTablesMaxState;
+}
+
+size_t ws_tables_size(const Plan &P) {
+    if (!tables_apply(P)) return 0;
+    return align256((size_t)kTabChunk * (size_t)(P.nst + 1) * (size_t)(P.n + 1) * P.esize);
+}
+
 size_t ws_evolve_size(const Plan &P) {
     Carver c{nullptr, 0};
     c.take(sizeof(double) * norm_parts(P));
-    return align256(c.off);
+    return align256(c.off) + ws_tables_size(P);
 }
 
 size_t ws_observe_size(const Plan &P) {
@@ -1267,16 +1305,16 @@ z2h_status z2h_evolve(const z2h_plan *plan, void *d_state, void *d_ws, size_t ws
         if ((st = validate_schedule(P, sched))) return st;
         if (!d_ws) return fail(Z2H_ERR_INVALID, "d_ws is NULL");
         const bool arrays = sched->sZ || sched->sX;
-        size_t need = ws_evolve_size(P);
-        if (arrays) need += align256(sizeof(double) * 2 * (size_t)sched->steps) + 256;
-        if (ws_bytes < need)
-            return fail(Z2H_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
         if (arrays) {
             for (int64_t k = 0; k < sched->steps; ++k) {
                 if ((sched->sZ && !std::isfinite(sched->sZ[k])) || (sched->sX && !std::isfinite(sched->sX[k])))
                     return fail(Z2H_ERR_INVALID, "schedule value at step %lld not finite", (long long)k);
             }
         }
+        size_t need = ws_evolve_size(P);
+        if (arrays) need += align256(sizeof(double) * 2 * (size_t)sched->steps) + 256;
+        if (ws_bytes < need)
+            return fail(Z2H_ERR_WORKSPACE, "workspace of %zu bytes, %zu needed", ws_bytes, need);
         if ((st = check_device_(P))) return st;
         hipStream_t s = (hipStream_t)stream;
         Carver c{(char *)d_ws, 0};
@@ -1295,6 +1333,7 @@ z2h_status z2h_evolve(const z2h_plan *plan, void *d_state, void *d_ws, size_t ws
             J.inl.sZ = sched->sZ ? dz : nullptr;
             J.inl.sX = sched->sX ? dx : nullptr;
         }
+        if (ws_tables_size(P)) J.d_tabs = c.take(ws_tables_size(P));
         J.h_jobs = &J.inl;
         J.njobs = 1;
         return run_levels(P, d_state, J, s);

@@ -530,10 +530,24 @@ __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, 
     double part = 0.0;
     if constexpr (kPhase) {
         if (want_norm && (int)t < a.rn_parts) part = gld(J.norm_part, t);
-        double alpha, beta;
-        phase_angles(J, op, alpha, beta);
-        table_factors(fac, nst, n, alpha, beta);
-        table_products<Real>(tab, fac, nst, n, op.basis ? ldexp(1.0, -n) : 1.0);
+        if (a.tabs) {
+            // the level's table was built by tables_kernel with the same
+            // arithmetic: copy it into LDS
+            typedef typename Vec2<Real>::type V;
+            typedef const __attribute__((address_space(1))) V *GTab;
+            const int entries = (nst + 1) * (n + 1);
+            const GTab src = (GTab)a.tabs + (size_t)(a.level - a.tab_lev0) * entries;
+            for (int j = (int)t; j < entries; j += blockDim.x) {
+                const V w = src[j];
+                tab[j] = Cx<Real>{w.x, w.y};
+            }
+            __syncthreads();
+        } else {
+            double alpha, beta;
+            phase_angles(J, op, alpha, beta);
+            table_factors(fac, nst, n, alpha, beta);
+            table_products<Real>(tab, fac, nst, n, op.basis ? ldexp(1.0, -n) : 1.0);
+        }
     }
     if constexpr (KIND == kHalfIn) {
         if (want_norm) renorm_table<Real>(a, J, op, tile0, t, part, tab, red);
@@ -675,6 +689,33 @@ template <typename Real, int R, int NL, int KS>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(sizeof(Real) == 4 ? 4 : 2)))
 level_kernel_cx(LevelArgs a) {
     level_body<Real, R, NL, KS, 1, 1>(a);
+}
+
+// Phase tables of levels lev0 + blockIdx.x of one job, written to global
+// memory in the layout of the LDS table (one block per level; plain levels
+// leave their slot unwritten).
+template <typename Real>
+__global__ void __launch_bounds__(256) tables_kernel(TablesArgs a) {
+    __shared__ double2 fac[kMaxStab + 1 + kMaxN + 1];
+    const JobDev &J = a.job;
+    const int lev = a.lev0 + (int)blockIdx.x;
+    const LevelOp op = level_op(lev, a.K, J.steps, J.k_begin, J.order);
+    if (op.kind == kIdle || op.kind == kPlainH) return;  // uniform per block
+    const int nst = a.lat.nst, n = a.lat.n;
+    double alpha, beta;
+    phase_angles(J, op, alpha, beta);
+    table_factors(fac, nst, n, alpha, beta);
+    Cx<Real> *tab = reinterpret_cast<Cx<Real> *>(a.tabs) + (size_t)blockIdx.x * (nst + 1) * (n + 1);
+    table_products<Real>(tab, fac, nst, n, op.basis ? ldexp(1.0, -n) : 1.0);
+}
+
+hipError_t launch_tables(bool c128, const TablesArgs &a, unsigned nlevels, hipStream_t s) {
+    if (nlevels == 0) return hipSuccess;
+    if (c128)
+        hipLaunchKernelGGL(tables_kernel<double>, dim3(nlevels), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL(tables_kernel<float>, dim3(nlevels), dim3(256), 0, s, a);
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- resident kernel

@@ -49,8 +49,10 @@ z2h_status scratch_ptr(void **out) {
 }
 
 // Scratch bytes a call needs: z2h_evolve's workspace figure.
+// z2h_evolve's workspace without its phase-table chunk: here every
+// workgroup builds its own table (the fixed array stays small).
 size_t scratch_need(const Plan &P, const z2h_schedule *sched) {
-    size_t need = ws_evolve_size(P);
+    size_t need = ws_evolve_size(P) - ws_tables_size(P);
     if (sched->sZ || sched->sX) need += align256(sizeof(double) * 2 * (size_t)std::max<int64_t>(sched->steps, 0)) + 256;
     return need;
 }

@@ -101,7 +101,14 @@ struct JobSet {
     const JobDev *h_jobs;   // host copies (step counts, order), same order as d_jobs
     int njobs;
     const int32_t *d_jidx;  // packed launch: block-job b runs d_jobs[d_jidx[b]] (device), or null
+    void *d_tabs;           // single inline job: room for the phase tables of kTabChunk levels, or null
+    int tab_lev0;           // first level whose table d_tabs holds
 };
+
+// Levels whose phase tables one table launch precomputes for a single state
+// (the evolve workspace holds one chunk).
+constexpr int kTabChunk = 1024;
+size_t ws_tables_size(const Plan &P);
 
 // Packed level sequence of a batch group: jobs run one after another in
 // slots, job j's level 0 at launch level lev0[j] (a multiple of the passes

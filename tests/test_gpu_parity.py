@@ -226,3 +226,30 @@ def test_component_exchange_bitwise(dtype, order):
     o = _oracle(("2x5-cx", order), lambda: oracle_run(2, 5, TC, c1, M, dt, order=order))
     loss = fidelity_loss(o, to_oracle_order(2, 5, states[0][0].astype(np.complex128)))
     assert loss <= (1e-12 if dtype == C128 else 1e-5), loss
+
+
+@pytest.mark.parametrize("dtype,M,order", [(C64, 600, 1), (C128, 530, 0)])
+def test_precomputed_tables_across_chunks_bitwise(dtype, M, order):
+    """z2h_evolve computes the phase tables of up to 1024 levels per launch
+    ahead of the passes; z2h_evolve_noalloc lets every workgroup build its
+    own. Over more than 1024 levels (two table chunks; order 0 adds the
+    half passes of the z-x-z order) both give the same bits, states and
+    per-step norms."""
+    import torch
+    print(f"case tables 3x3 dtype={dtype} M={M} order={order}", flush=True)
+    c1 = (1.0, 1.0, 0.35, 0.25)
+    plan = z2h.z2h_plan_create(3, 3, dtype)
+    sz = z2h.z2h_plan_sizes(plan)
+    sched = z2h.schedule(TC, c1, M, 0.02, renorm=1 if dtype == C64 else 0, order=order)
+    a = z2h.alloc_state(plan)
+    z2h.z2h_state_init(plan, a, z2h.Z2H_INIT_PSI1)
+    b = a.clone()
+    ws = z2h.alloc_bytes(sz["ws_evolve"])
+    na = torch.zeros(M, dtype=torch.float64, device="cuda")
+    nb = torch.zeros(M, dtype=torch.float64, device="cuda")
+    z2h.z2h_evolve(plan, a, ws, sched, norms=na)
+    z2h.z2h_evolve_noalloc(plan, b, sched, norms=nb)
+    torch.cuda.synchronize()
+    assert torch.equal(torch.view_as_real(a), torch.view_as_real(b))
+    assert torch.equal(na, nb)
+    assert abs(float(na[-1]) - 1.0) < (1e-5 if dtype == C64 else 1e-12)
