@@ -51,6 +51,7 @@ struct Group {
     // counts differ): jobs run one after another in slots
     bool packed;
     PackedLevels pack;
+    bool tables;                  // precomputed phase tables allowed (Z2H_TUNE "tables=0" disables)
 };
 
 }  // namespace
@@ -110,6 +111,21 @@ static void free_batch(z2h_batch *b) {
     if (b->fork) (void)hipEventDestroy(b->fork);
     if (b->join) (void)hipEventDestroy(b->join);
     delete b;
+}
+
+// Phase tables precomputed at creation for a group whose states are
+// cache-resident (at most 64 MiB together) and whose phase passes run
+// full-window kernels: such launch-latency-bound passes copy a ready table
+// instead of building one per workgroup.  Large groups (the scan) build
+// them per workgroup, hidden behind their tile loads.  Bytes for every
+// level of every job of the group (0: none).
+static size_t group_tables_bytes(const Group &g) {
+    const Plan &P = g.P;
+    if (!g.tables || P.K < 2 || !P.geom[0].full || !P.geom[P.K - 1].full) return 0;
+    if ((P.esize << P.n) * g.jobs.size() > ((size_t)64 << 20)) return 0;
+    size_t levels = 0;
+    for (const JobDev &h : g.h_jobs) levels += (size_t)job_levels(P, h);
+    return align256(levels * (size_t)(P.nst + 1) * (P.n + 1) * P.esize);
 }
 
 // Workspace layout of a batch: transformed-copy scratch mirroring the state
@@ -277,6 +293,7 @@ static void trace_records(const z2h_batch *b, int every, int64_t nseg, TracePiec
             for (size_t j = 0; j < nj; ++j) {
                 JobDev r = g.h_jobs[j];
                 r.lev0 = 0;  // segments run level-synchronously, never packed
+                r.tabs = nullptr;  // segment levels are not the whole ramp's: tables built per workgroup
                 const int64_t M = r.M;
                 const int64_t k0 = std::min<int64_t>(sg * every, M), k1 = std::min<int64_t>((sg + 1) * every, M);
                 r.k_begin = (int32_t)k0;
@@ -495,6 +512,14 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
             const char *q = strstr(tv, "slots=");
             if (q && sscanf(q, "slots=%d", &v) == 1 && v >= 0) pack_slots = v;
         }
+        // precomputed phase tables: Z2H_TUNE "tables=0" disables them
+        bool tables = true;
+        if (const char *tv = getenv("Z2H_TUNE")) {
+            int v;
+            const char *q = strstr(tv, "tables=");
+            if (q && sscanf(q, "tables=%d", &v) == 1) tables = v != 0;
+        }
+        for (auto &g : b->groups) g.tables = tables;
         // per group: order jobs by decreasing level count
         for (auto &g : b->groups) {
             const int Pp = 2 * (g.P.K - 1);
@@ -549,6 +574,7 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
                     tbytes += align256(sizeof(int32_t) * std::max<size_t>(1, g.pack.off.back()));
                 }
             }
+            tbytes += group_tables_bytes(g);
             tbytes += align256(sizeof(JobDev) * nj) + align256(sizeof(double) * nj * norm_parts(g.P)) +
                       align256(sizeof(JobDev) * std::max<size_t>(1, g.h_p1p.size())) +
                       align256(sizeof(InitJob) * nj) + align256(sizeof(uint64_t) * nj) +
@@ -567,6 +593,14 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
             g.d_jobs = (JobDev *)c.take(sizeof(JobDev) * nj);
             g.parts_norm = (double *)c.take(sizeof(double) * nj * norm_parts(g.P));
             for (size_t j = 0; j < nj; ++j) g.h_jobs[j].norm_part = g.parts_norm + j * norm_parts(g.P);
+            if (const size_t tb = group_tables_bytes(g)) {
+                char *t = (char *)c.take(tb);
+                const size_t per_level = (size_t)(g.P.nst + 1) * (g.P.n + 1) * g.P.esize;
+                for (size_t j = 0; j < nj; ++j) {
+                    g.h_jobs[j].tabs = t;
+                    t += per_level * (size_t)job_levels(g.P, g.h_jobs[j]);
+                }
+            }
             g.d_p1p = (JobDev *)c.take(sizeof(JobDev) * std::max<size_t>(1, g.h_p1p.size()));
             g.d_init = (InitJob *)c.take(sizeof(InitJob) * nj);
             g.d_off = (uint64_t *)c.take(sizeof(uint64_t) * nj);
@@ -590,6 +624,28 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
             if (!ok) {
                 free_batch(b);
                 return fail(Z2H_ERR_HIP, "upload of batch tables failed");
+            }
+        }
+        // phase tables of the cache-resident groups: every level of every
+        // job, computed once here (the schedules of a batch are fixed)
+        for (auto &g : b->groups) {
+            if (!group_tables_bytes(g)) continue;
+            for (size_t j = 0; j < g.jobs.size(); ++j) {
+                TablesArgs ta;
+                memset(&ta, 0, sizeof ta);
+                ta.tabs = const_cast<void *>(g.h_jobs[j].tabs);
+                ta.job = g.h_jobs[j];
+                ta.lat = g.P.lat;
+                ta.lev0 = 0;
+                ta.K = g.P.K;
+                if (launch_tables(g.P.c128, ta, (unsigned)job_levels(g.P, g.h_jobs[j]), nullptr) != hipSuccess) {
+                    free_batch(b);
+                    return fail(Z2H_ERR_HIP, "table kernel launch failed");
+                }
+            }
+            if (hipDeviceSynchronize() != hipSuccess) {
+                free_batch(b);
+                return fail(Z2H_ERR_HIP, "table kernels failed");
             }
         }
         if (hipStreamCreateWithFlags(&b->side, hipStreamNonBlocking) != hipSuccess ||

@@ -988,7 +988,7 @@ z2h_status run_levels(const Plan &P, void *states, const JobSet &J, hipStream_t 
 }
 
 
-static int job_levels(const Plan &P, const JobDev &h) {
+int job_levels(const Plan &P, const JobDev &h) {
     const int Pp = 2 * (P.K - 1);
     return h.steps <= 0 ? 0 : (h.order == 0 ? Pp * (h.steps + 1) + 1 : Pp * h.steps + 1);
 }

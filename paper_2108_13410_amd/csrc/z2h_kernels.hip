@@ -530,13 +530,15 @@ __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, 
     double part = 0.0;
     if constexpr (kPhase) {
         if (want_norm && (int)t < a.rn_parts) part = gld(J.norm_part, t);
-        if (a.tabs) {
+        if (J.tabs || a.tabs) {
             // the level's table was built by tables_kernel with the same
-            // arithmetic: copy it into LDS
+            // arithmetic (once per batch for the job's own levels, or per
+            // chunk of levels of a single state): copy it into LDS
             typedef typename Vec2<Real>::type V;
             typedef const __attribute__((address_space(1))) V *GTab;
             const int entries = (nst + 1) * (n + 1);
-            const GTab src = (GTab)a.tabs + (size_t)(a.level - a.tab_lev0) * entries;
+            const GTab src = J.tabs ? (GTab)J.tabs + (size_t)(a.level - J.lev0) * entries
+                                    : (GTab)a.tabs + (size_t)(a.level - a.tab_lev0) * entries;
             for (int j = (int)t; j < entries; j += blockDim.x) {
                 const V w = src[j];
                 tab[j] = Cx<Real>{w.x, w.y};

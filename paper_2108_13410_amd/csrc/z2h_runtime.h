@@ -109,6 +109,7 @@ struct JobSet {
 // (the evolve workspace holds one chunk).
 constexpr int kTabChunk = 1024;
 size_t ws_tables_size(const Plan &P);
+int job_levels(const Plan &P, const JobDev &h);  // levels of a job's pass sequence
 
 // Packed level sequence of a batch group: jobs run one after another in
 // slots, job j's level 0 at launch level lev0[j] (a multiple of the passes

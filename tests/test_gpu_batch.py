@@ -243,3 +243,29 @@ def test_packed_levels_equal_level_synchronous(dtype):
         os.environ.pop("Z2H_TUNE", None)
     for o in outs[1:]:
         assert np.array_equal(o, outs[0])
+
+
+@pytest.mark.parametrize("dtype", [z2h.Z2H_C64, z2h.Z2H_C128])
+def test_precomputed_batch_tables_bitwise(dtype):
+    """A cache-resident group (here 12 3x3 states, uneven step counts, packed
+    into slots) gets every job's phase tables computed once at batch
+    creation; the passes copy them. Same bits as the batch built with
+    Z2H_TUNE=tables=0, whose workgroups build their own tables."""
+    import os
+    rng = np.random.default_rng(77)
+    jobs = []
+    for k in range(12):
+        hx, hz = rng.uniform(0, 0.6, 2)
+        M = int(rng.integers(5, 40))
+        jobs.append(dict(Lx=3, Ly=3, c0=workloads.TORIC, c1=(1.0, 1.0, hx, hz), T=0.05 * M, M=M))
+    outs = []
+    try:
+        for tv in ("tables=0", ""):
+            os.environ["Z2H_TUNE"] = tv
+            print(f"case batch tables dtype={dtype} '{tv}'", flush=True)
+            b, states, o = run_batch(jobs, dtype)
+            outs.append((states.cpu().numpy(), o))
+    finally:
+        os.environ.pop("Z2H_TUNE", None)
+    assert np.array_equal(outs[0][0], outs[1][0])
+    assert np.array_equal(outs[0][1], outs[1][1])
