@@ -52,6 +52,8 @@ struct Group {
     bool packed;
     PackedLevels pack;
     bool tables;                  // precomputed phase tables allowed (Z2H_TUNE "tables=0" disables)
+    void *d_tabs;                 // precomputed phase tables (batch-owned), or null
+    uint64_t tab_stride;          // bytes per job record in d_tabs
 };
 
 }  // namespace
@@ -119,13 +121,22 @@ static void free_batch(z2h_batch *b) {
 // instead of building one per workgroup.  Large groups (the scan) build
 // them per workgroup, hidden behind their tile loads.  Bytes for every
 // level of every job of the group (0: none).
+static int group_max_levels(const Group &g) {
+    int mx = 0;
+    for (const JobDev &h : g.h_jobs) mx = std::max(mx, job_levels(g.P, h));
+    return mx;
+}
+
+static uint64_t group_tab_stride(const Group &g) {
+    return align256((size_t)group_max_levels(g) * (size_t)(g.P.nst + 1) * (g.P.n + 1) * g.P.esize);
+}
+
 static size_t group_tables_bytes(const Group &g) {
     const Plan &P = g.P;
     if (!g.tables || P.K < 2 || !P.geom[0].full || !P.geom[P.K - 1].full) return 0;
     if ((P.esize << P.n) * g.jobs.size() > ((size_t)64 << 20)) return 0;
-    size_t levels = 0;
-    for (const JobDev &h : g.h_jobs) levels += (size_t)job_levels(P, h);
-    return align256(levels * (size_t)(P.nst + 1) * (P.n + 1) * P.esize);
+    const size_t bytes = group_tab_stride(g) * g.jobs.size();
+    return bytes <= ((size_t)256 << 20) ? bytes : 0;
 }
 
 // Workspace layout of a batch: transformed-copy scratch mirroring the state
@@ -198,6 +209,8 @@ static z2h_status enqueue(z2h_batch *b, void *states, void *ws, double *obs, hip
             J.d_jobs = g.d_jobs;
             J.h_jobs = g.h_jobs.data();
             J.njobs = nj;
+            J.d_btabs = g.d_tabs;
+            J.btab_stride = g.tab_stride;
             z2h_status st = run_levels_packed(g.P, states, J, g.pack, s);
             if (st) return st;
             continue;
@@ -209,6 +222,8 @@ static z2h_status enqueue(z2h_batch *b, void *states, void *ws, double *obs, hip
             J.d_jobs = g.d_jobs + c0;
             J.h_jobs = g.h_jobs.data() + c0;
             J.njobs = std::min(chunk, nj - c0);
+            J.d_btabs = g.d_tabs ? (const char *)g.d_tabs + (size_t)c0 * g.tab_stride : nullptr;
+            J.btab_stride = g.tab_stride;
             z2h_status st = run_levels(g.P, states, J, s);
             if (st) return st;
         }
@@ -293,7 +308,6 @@ static void trace_records(const z2h_batch *b, int every, int64_t nseg, TracePiec
             for (size_t j = 0; j < nj; ++j) {
                 JobDev r = g.h_jobs[j];
                 r.lev0 = 0;  // segments run level-synchronously, never packed
-                r.tabs = nullptr;  // segment levels are not the whole ramp's: tables built per workgroup
                 const int64_t M = r.M;
                 const int64_t k0 = std::min<int64_t>(sg * every, M), k1 = std::min<int64_t>((sg + 1) * every, M);
                 r.k_begin = (int32_t)k0;
@@ -593,13 +607,11 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
             g.d_jobs = (JobDev *)c.take(sizeof(JobDev) * nj);
             g.parts_norm = (double *)c.take(sizeof(double) * nj * norm_parts(g.P));
             for (size_t j = 0; j < nj; ++j) g.h_jobs[j].norm_part = g.parts_norm + j * norm_parts(g.P);
+            g.d_tabs = nullptr;
+            g.tab_stride = 0;
             if (const size_t tb = group_tables_bytes(g)) {
-                char *t = (char *)c.take(tb);
-                const size_t per_level = (size_t)(g.P.nst + 1) * (g.P.n + 1) * g.P.esize;
-                for (size_t j = 0; j < nj; ++j) {
-                    g.h_jobs[j].tabs = t;
-                    t += per_level * (size_t)job_levels(g.P, g.h_jobs[j]);
-                }
+                g.d_tabs = c.take(tb);
+                g.tab_stride = group_tab_stride(g);
             }
             g.d_p1p = (JobDev *)c.take(sizeof(JobDev) * std::max<size_t>(1, g.h_p1p.size()));
             g.d_init = (InitJob *)c.take(sizeof(InitJob) * nj);
@@ -629,19 +641,19 @@ z2h_status z2h_batch_create(int32_t njobs, const int32_t *Lx, const int32_t *Ly,
         // phase tables of the cache-resident groups: every level of every
         // job, computed once here (the schedules of a batch are fixed)
         for (auto &g : b->groups) {
-            if (!group_tables_bytes(g)) continue;
-            for (size_t j = 0; j < g.jobs.size(); ++j) {
-                TablesArgs ta;
-                memset(&ta, 0, sizeof ta);
-                ta.tabs = const_cast<void *>(g.h_jobs[j].tabs);
-                ta.job = g.h_jobs[j];
-                ta.lat = g.P.lat;
-                ta.lev0 = 0;
-                ta.K = g.P.K;
-                if (launch_tables(g.P.c128, ta, (unsigned)job_levels(g.P, g.h_jobs[j]), nullptr) != hipSuccess) {
-                    free_batch(b);
-                    return fail(Z2H_ERR_HIP, "table kernel launch failed");
-                }
+            if (!g.d_tabs) continue;
+            TablesArgs ta;
+            memset(&ta, 0, sizeof ta);
+            ta.tabs = g.d_tabs;
+            ta.jobs = g.d_jobs;
+            ta.stride = g.tab_stride;
+            ta.lat = g.P.lat;
+            ta.lev0 = 0;
+            ta.K = g.P.K;
+            if (launch_tables(g.P.c128, ta, (unsigned)group_max_levels(g), nullptr, (unsigned)g.jobs.size()) !=
+                hipSuccess) {
+                free_batch(b);
+                return fail(Z2H_ERR_HIP, "table kernel launch failed");
             }
             if (hipDeviceSynchronize() != hipSuccess) {
                 free_batch(b);

@@ -870,8 +870,13 @@ z2h_status launch_one_level(const Plan &P, void *states, const JobSet &J, int le
     a.kind_hint = force_plain ? (int)kPlainH : kind_hint;
     a.njobs = J.njobs;
     a.jidx = J.d_jidx;
-    a.tabs = force_plain ? nullptr : J.d_tabs;
-    a.tab_lev0 = J.tab_lev0;
+    if (!force_plain && J.d_btabs) {
+        a.tabs = J.d_btabs;
+        a.tab_stride = J.btab_stride;
+    } else {
+        a.tabs = force_plain ? nullptr : J.d_tabs;
+        a.tab_lev0 = J.tab_lev0;
+    }
     job_layout(J, a);
     const uint64_t nblocks = (uint64_t)J.njobs << a.geom.tiles_log2;
     if (nblocks > 0x7fffffffull) return fail(Z2H_ERR_UNSUPPORTED, "grid of %llu blocks", (unsigned long long)nblocks);

@@ -58,7 +58,6 @@ struct JobDev {
     double *norm_trace;                 // per-step norms or null
     int32_t norm_parts;                 // number of partials written there
     int32_t lev0;                       // launch level at which this job's level 0 runs (0 unless packed)
-    const void *tabs;                   // phase tables of the job's levels 0, 1, .. (precomputed), or null
 };
 
 // Pass kinds inside a job's level sequence.

@@ -28,7 +28,10 @@ struct LevelArgs {
     int32_t njobs;             // jobs of this launch
     int32_t xcd;               // 1: XCD-major block order (consecutive tiles on one XCD)
     const int32_t *jidx;       // job of block-job b is jobs[jidx[b]] (packed batches), or null: jobs[b]
-    const void *tabs;          // single state: phase tables of levels tab_lev0.. (precomputed), or null
+    const void *tabs;          // precomputed phase tables, or null.  Single state: the tables of
+                               // levels tab_lev0, tab_lev0 + 1, ..  Batch group (tab_stride > 0):
+                               // record r's level l at tabs + r * tab_stride + l * entries
+    uint64_t tab_stride;       // bytes per job record (0: single state)
     int32_t tab_lev0;
     int32_t pad3;
     JobDev job_inline;         // used when jobs is null (single state)
@@ -38,7 +41,9 @@ struct LevelArgs {
 // kernels (single-state evolution).
 struct TablesArgs {
     void *tabs;                // (nst + 1)(n + 1) complex entries per level, level lev0 first
-    JobDev job;
+    JobDev job;                // the job (jobs null)
+    const JobDev *jobs;        // or: job blockIdx.y of this device array, its tables at tabs + y * stride
+    uint64_t stride;           // bytes per job when jobs is set
     LatticeDev lat;
     int32_t lev0, K;
 };
@@ -136,7 +141,7 @@ hipError_t launch_obs(bool c128, int R, const ObsArgs &a, unsigned workers, unsi
                       size_t lds, hipStream_t s);
 hipError_t launch_obs_finalize(const FinalArgs &a, unsigned njobs, hipStream_t s);
 hipError_t launch_init(bool c128, const InitArgs &a, unsigned njobs, hipStream_t s);
-hipError_t launch_tables(bool c128, const TablesArgs &a, unsigned nlevels, hipStream_t s);
+hipError_t launch_tables(bool c128, const TablesArgs &a, unsigned nlevels, hipStream_t s, unsigned njobs = 1);
 hipError_t launch_reduce_parts(const JobDev *jobs, const JobDev &inline_job, int njobs, int parts,
                                hipStream_t s);
 

@@ -48,10 +48,14 @@ __device__ __forceinline__ double2 *table_scratch(unsigned char *smem) {
 }
 
 // Build the phase table T[k][w] = scale * exp(i (alpha (nst - 2k) + beta (n - 2w)))
-// in LDS (FP64 angles and products, cast to Real).  Two stages so that a
+// in LDS (FP64 angles and products, cast to Real).  Contraction into FMAs is
+// off in the schedule, angle and table arithmetic, so every kernel that
+// builds a table (in LDS or ahead of time in global memory) rounds the same
+// way whatever code surrounds it.  Two stages so that a
 // pass can compute the factors while its tile loads are in flight and apply
 // the scale (which may depend on a norm reduction) afterwards.
 __device__ __forceinline__ void table_factors(double2 *fac, int nst, int n, double alpha, double beta) {
+#pragma clang fp contract(off)
     const int t = threadIdx.x, nt = blockDim.x;
     for (int j = t; j < nst + 1 + n + 1; j += nt) {
         double ang = j <= nst ? alpha * (double)(nst - 2 * j) : beta * (double)(n - 2 * (j - nst - 1));
@@ -64,6 +68,7 @@ __device__ __forceinline__ void table_factors(double2 *fac, int nst, int n, doub
 template <typename Real>
 __device__ __forceinline__ void table_products(Cx<Real> *tab, const double2 *fac, int nst, int n,
                                                double scale) {
+#pragma clang fp contract(off)
     const int t = threadIdx.x, nt = blockDim.x;
     __syncthreads();
     const int W = n + 1;
@@ -153,6 +158,7 @@ __device__ __forceinline__ int job_index(const int32_t *jidx, int b) {
 // ---------------------------------------------------------------- schedule
 
 __device__ __forceinline__ double sched_s(const JobDev &J, int k, int zkind) {
+#pragma clang fp contract(off)
     typedef const __attribute__((address_space(4))) double *ConstDoubles;
     const double *arr = zkind ? J.sZ : J.sX;
     if (arr) return ((ConstDoubles)arr)[k];  // read-only; scalar load
@@ -162,6 +168,7 @@ __device__ __forceinline__ double sched_s(const JobDev &J, int k, int zkind) {
 // (coupling, field) of the given basis at step k: inner (Z) basis uses
 // (JB, hz) at sZ, outer (X) basis uses (JA, hx) at sX.
 __device__ __forceinline__ void coup(const JobDev &J, int basis, int k, double &Jc, double &h) {
+#pragma clang fp contract(off)
     const double s = sched_s(J, k, basis == 0);
     const int ij = basis == 0 ? 1 : 0, ih = basis == 0 ? 3 : 2;
     Jc = (1.0 - s) * J.c0[ij] + s * J.c1[ij];
@@ -171,6 +178,7 @@ __device__ __forceinline__ void coup(const JobDev &J, int basis, int k, double &
 // Angles of a phase pass: full step ka (duration dt) or half steps ka, kb.
 __device__ __forceinline__ void phase_angles(const JobDev &J, const LevelOp &op, double &alpha,
                                              double &beta) {
+#pragma clang fp contract(off)
     double Ja, ha, Jb = 0, hb = 0;
     coup(J, op.basis, op.ka, Ja, ha);
     if (op.full) {
@@ -512,8 +520,12 @@ __device__ __forceinline__ void bwd_rot(Cx<Real> (&v)[1 << R], Cx<Real> *lds, co
     bwd_rot_from<Real, R, NL, NL - 1, CX>(v, lds, M);
 }
 
-template <typename Real, int R, int NL, int KIND, int NT, int CX = 0>
-__device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, const LevelOp &op,
+// TAB: the kernel may copy a precomputed phase table (a.tabs) instead of
+// building it.  Only the any-kind kernels carry that branch: launches with
+// tables use them for every phase level, and the single-kind phase kernels
+// keep the shorter set-up of the per-workgroup build.
+template <typename Real, int R, int NL, int KIND, int NT, int CX = 0, bool TAB = false>
+__device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, const LevelOp &op, int jrec,
                                            uint64_t tile0, uint32_t t, Cx<Real> (&v)[NT][1 << R],
                                            Cx<Real> *st, const LayCtx<R> (&L0)[NT], Cx<Real> *lds,
                                            Cx<Real> *tab, double2 *fac, double *red) {
@@ -530,15 +542,19 @@ __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, 
     double part = 0.0;
     if constexpr (kPhase) {
         if (want_norm && (int)t < a.rn_parts) part = gld(J.norm_part, t);
-        if (J.tabs || a.tabs) {
+        if (TAB && a.tabs) {
             // the level's table was built by tables_kernel with the same
-            // arithmetic (once per batch for the job's own levels, or per
-            // chunk of levels of a single state): copy it into LDS
+            // arithmetic (once per batch for every job's levels, or per chunk
+            // of levels of a single state): copy it into LDS
             typedef typename Vec2<Real>::type V;
             typedef const __attribute__((address_space(1))) V *GTab;
             const int entries = (nst + 1) * (n + 1);
-            const GTab src = J.tabs ? (GTab)J.tabs + (size_t)(a.level - J.lev0) * entries
-                                    : (GTab)a.tabs + (size_t)(a.level - a.tab_lev0) * entries;
+            const GTab src =
+                a.tab_stride
+                    ? (GTab)((const __attribute__((address_space(1))) unsigned char *)a.tabs +
+                             (size_t)(a.jidx ? job_index(a.jidx, jrec) : jrec) * a.tab_stride) +
+                          (size_t)(a.level - J.lev0) * entries
+                    : (GTab)a.tabs + (size_t)(a.level - a.tab_lev0) * entries;
             for (int j = (int)t; j < entries; j += blockDim.x) {
                 const V w = src[j];
                 tab[j] = Cx<Real>{w.x, w.y};
@@ -669,13 +685,13 @@ __device__ __forceinline__ void level_body(const LevelArgs &a) {
     double *red = align16<double>(tab + (a.lat.nst + 1) * W);
 
     if constexpr (KS != kAnyKind) {
-        pass_multi<Real, R, NL, KS, NT, CX>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red);
+        pass_multi<Real, R, NL, KS, NT, CX>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red);
     } else {
         switch (op.kind) {
-            case kPhaseB: pass_multi<Real, R, NL, kPhaseB, NT, CX>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
-            case kPlainH: pass_multi<Real, R, NL, kPlainH, NT, CX>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
-            case kHalfIn: pass_multi<Real, R, NL, kHalfIn, NT, CX>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
-            default: pass_multi<Real, R, NL, kHalfOut, NT, CX>(a, J, op, tile0, t, v, st, L0, lds, tab, fac, red); break;
+            case kPhaseB: pass_multi<Real, R, NL, kPhaseB, NT, CX, true>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red); break;
+            case kPlainH: pass_multi<Real, R, NL, kPlainH, NT, CX, true>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red); break;
+            case kHalfIn: pass_multi<Real, R, NL, kHalfIn, NT, CX, true>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red); break;
+            default: pass_multi<Real, R, NL, kHalfOut, NT, CX, true>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red); break;
         }
     }
 }
@@ -699,7 +715,7 @@ level_kernel_cx(LevelArgs a) {
 template <typename Real>
 __global__ void __launch_bounds__(256) tables_kernel(TablesArgs a) {
     __shared__ double2 fac[kMaxStab + 1 + kMaxN + 1];
-    const JobDev &J = a.job;
+    const JobDev J = a.jobs ? job_record(a.jobs, (int)blockIdx.y, a.job) : a.job;
     const int lev = a.lev0 + (int)blockIdx.x;
     const LevelOp op = level_op(lev, a.K, J.steps, J.k_begin, J.order);
     if (op.kind == kIdle || op.kind == kPlainH) return;  // uniform per block
@@ -707,16 +723,17 @@ __global__ void __launch_bounds__(256) tables_kernel(TablesArgs a) {
     double alpha, beta;
     phase_angles(J, op, alpha, beta);
     table_factors(fac, nst, n, alpha, beta);
-    Cx<Real> *tab = reinterpret_cast<Cx<Real> *>(a.tabs) + (size_t)blockIdx.x * (nst + 1) * (n + 1);
+    unsigned char *base = reinterpret_cast<unsigned char *>(a.tabs) + (size_t)blockIdx.y * a.stride;
+    Cx<Real> *tab = reinterpret_cast<Cx<Real> *>(base) + (size_t)blockIdx.x * (nst + 1) * (n + 1);
     table_products<Real>(tab, fac, nst, n, op.basis ? ldexp(1.0, -n) : 1.0);
 }
 
-hipError_t launch_tables(bool c128, const TablesArgs &a, unsigned nlevels, hipStream_t s) {
-    if (nlevels == 0) return hipSuccess;
+hipError_t launch_tables(bool c128, const TablesArgs &a, unsigned nlevels, hipStream_t s, unsigned njobs) {
+    if (nlevels == 0 || njobs == 0) return hipSuccess;
     if (c128)
-        hipLaunchKernelGGL(tables_kernel<double>, dim3(nlevels), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(tables_kernel<double>, dim3(nlevels, njobs), dim3(256), 0, s, a);
     else
-        hipLaunchKernelGGL(tables_kernel<float>, dim3(nlevels), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(tables_kernel<float>, dim3(nlevels, njobs), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -1155,7 +1172,8 @@ static hipError_t do_level_full_ks(const LevelArgs &a, dim3 grid, size_t lds, hi
 
 template <typename Real, int R, int NL, int NT>
 static hipError_t do_level_full_nt(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
-    if (a.kind_hint == kPhaseB) return do_level_full_ks<Real, R, NL, kPhaseB, NT>(a, grid, lds, s);
+    // precomputed tables are read by the any-kind kernels only
+    if (a.kind_hint == kPhaseB && !a.tabs) return do_level_full_ks<Real, R, NL, kPhaseB, NT>(a, grid, lds, s);
     if (a.kind_hint == kPlainH) return do_level_full_ks<Real, R, NL, kPlainH, NT>(a, grid, lds, s);
     return do_level_full_ks<Real, R, NL, kAnyKind, NT>(a, grid, lds, s);
 }
@@ -1181,7 +1199,7 @@ static hipError_t do_level_full(const LevelArgs &a, dim3 grid, size_t lds, hipSt
     if (a.geom.cx) {
 #define Z2H_CX_CALL(r, nl)                                                                               \
         if (R == r && NL == nl) {                                                                        \
-            if (a.kind_hint == kPhaseB) return do_level_cx_ks<Real, r, nl, kPhaseB>(a, grid, lds, s);    \
+            if (a.kind_hint == kPhaseB && !a.tabs) return do_level_cx_ks<Real, r, nl, kPhaseB>(a, grid, lds, s); \
             if (a.kind_hint == kPlainH) return do_level_cx_ks<Real, r, nl, kPlainH>(a, grid, lds, s);    \
             return do_level_cx_ks<Real, r, nl, kAnyKind>(a, grid, lds, s);                               \
         }

@@ -103,6 +103,8 @@ struct JobSet {
     const int32_t *d_jidx;  // packed launch: block-job b runs d_jobs[d_jidx[b]] (device), or null
     void *d_tabs;           // single inline job: room for the phase tables of kTabChunk levels, or null
     int tab_lev0;           // first level whose table d_tabs holds
+    const void *d_btabs;    // batch group: precomputed tables of every level of d_jobs[r] at
+    uint64_t btab_stride;   // d_btabs + r * btab_stride (bytes), or null
 };
 
 // Levels whose phase tables one table launch precomputes for a single state
