@@ -253,6 +253,7 @@ struct GroupChoice {
     int G, R, NL, m, c;
     int np;  // tiles per block: 1, or 2 (two-tile blocks of a strided group)
     int cx = 0;  // one-tile blocks: 1 = layout changes exchange one component at a time
+    int hi = 0;  // > 0: the group's top hi bits are taken from the top of the state
 };
 
 static bool fit_group(const Plan &P, int j, int b0, int G, int R, int NL, int m_pref, int m_hi, int c_min,
@@ -345,13 +346,15 @@ static z2h_status apply_split(Plan &P, const GroupChoice *ch, int K) {
     const int n = P.n;
     memset(P.geom, 0, sizeof P.geom);
     P.K = K;
-    int b = 0;
+    int b = 0, top = 0;  // next free bit from below; bits taken from the top
     for (int j = 0; j < K; ++j) {
         GroupGeom &g = P.geom[j];
         if (ch[j].G <= 0 || ch[j].R < 2 || ch[j].R > 5 || ch[j].m < ch[j].G || ch[j].m > 14)
             return fail(Z2H_ERR_INVALID, "bad split group %d", j);
         if (j == 0 && ch[j].c != 0) return fail(Z2H_ERR_INVALID, "group 0 carries no bits");
         if (j > 0 && (ch[j].c > b || ch[j].m != ch[j].c + ch[j].G)) return fail(Z2H_ERR_INVALID, "bad split group %d", j);
+        if (ch[j].hi < 0 || ch[j].hi >= ch[j].G || (ch[j].hi && j == 0))
+            return fail(Z2H_ERR_INVALID, "group %d: bad high-run width %d", j, ch[j].hi);
         g.R = ch[j].R;
         g.m = ch[j].m;
         g.c = ch[j].c;
@@ -360,6 +363,17 @@ static z2h_status apply_split(Plan &P, const GroupChoice *ch, int K) {
         g.x1 = g.c + ch[j].G;
         g.tiles_log2 = n - g.m;
         plan_layouts(g, false);
+        if (ch[j].hi) {
+            // two runs: [b0, b0 + G - hi) and the top hi bits not yet taken;
+            // every register window must lie inside one run
+            if (!g.full || ch[j].hi % g.R)
+                return fail(Z2H_ERR_INVALID, "group %d: a high run of %d bits needs whole windows of %d", j,
+                            ch[j].hi, g.R);
+            top += ch[j].hi;
+            g.hi = ch[j].hi;
+            g.b1 = n - top;
+            if (g.b1 < g.b0 + ch[j].G - ch[j].hi) return fail(Z2H_ERR_INVALID, "group %d: runs overlap", j);
+        }
         if ((ch[j].np != 1 && ch[j].np != 2) || (ch[j].cx && ch[j].np != 1))
             return fail(Z2H_ERR_INVALID, "group %d: bad tiles-per-block option", j);
         g.cx = 0;
@@ -382,9 +396,9 @@ static z2h_status apply_split(Plan &P, const GroupChoice *ch, int K) {
         } else {
             g.pair = 1;
         }
-        b += ch[j].G;
+        b += ch[j].G - ch[j].hi;
     }
-    if (b != n) return fail(Z2H_ERR_INVALID, "split covers %d of %d bits", b, n);
+    if (b + top != n) return fail(Z2H_ERR_INVALID, "split covers %d of %d bits", b + top, n);
     return check_block(P);
 }
 
@@ -433,7 +447,10 @@ static void plan_base(int Lx, int Ly, bool c128, Plan &P) {
 // A schedule configuration string: "split=G:R:m:c/G:R:m:c/..." (groups from
 // the lowest qubits up; a group may end in ":2", two tiles per block in two
 // register windows, or ":1c", one tile per block whose layout changes
-// exchange the real and then the imaginary parts through half the LDS) or
+// exchange the real and then the imaginary parts through half the LDS, and
+// then in ":h<N>": the group's top N bits are the highest N qubits not yet
+// taken, so that its tile rows are not all the state's largest stride apart)
+// or
 // "uniform,m=..,R=..,c=..,g0=.."; either may add
 // ",nt=1" (streaming loads and stores in the general pass kernel) and
 // ",xcd=<mask>" (XCD-major block order in the passes over group j when bit
@@ -458,7 +475,12 @@ static z2h_status plan_from_config(Plan &P, const char *cfg, int m_pref, int m_h
                     cx = 1;
                 }
             }
-            ch[K++] = {G, R, G / std::max(R, 1), m, c, np, cx};
+            int hi = 0;
+            if (q[0] == ':' && q[1] == 'h') {  // ":h<N>": top N bits from the top of the state
+                if (sscanf(q, ":h%d%n", &hi, &used2) != 1) return fail(Z2H_ERR_INVALID, "unreadable split in \"%s\"", cfg);
+                q += used2;
+            }
+            ch[K++] = {G, R, G / std::max(R, 1), m, c, np, cx, hi};
             if (*q != '/') break;
             ++q;
         }
@@ -1256,7 +1278,8 @@ z2h_status z2h_plan_describe(const z2h_plan *plan, char *buf, size_t len) {
         const GroupGeom &g = P.geom[j];
         s += j ? ", " : "";
         s += "{\"m\": " + std::to_string(g.m) + ", \"c\": " + std::to_string(g.c) +
-             ", \"b0\": " + std::to_string(g.b0) + ", \"x0\": " + std::to_string(g.x0) +
+             ", \"b0\": " + std::to_string(g.b0) + ", \"hi\": " + std::to_string(g.hi) +
+             ", \"b1\": " + std::to_string(g.b1) + ", \"x0\": " + std::to_string(g.x0) +
              ", \"x1\": " + std::to_string(g.x1) + ", \"tiles_log2\": " + std::to_string(g.tiles_log2) +
              ", \"p\": [";
         for (int l = 0; l < g.nlay; ++l) s += (l ? ", " : "") + std::to_string(g.p[l]);

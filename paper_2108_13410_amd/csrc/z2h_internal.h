@@ -41,6 +41,8 @@ struct GroupGeom {
     int32_t lds_blk;                    // full-window LDS block per value of the untransformed bits
     int32_t cx;                         // 1: layout changes exchange the real, then the imaginary
                                         // parts (LDS of one component per slot)
+    int32_t hi;                         // > 0: the top hi local bits [m - hi, m) sit at global
+    int32_t b1;                         // bits [b1, b1 + hi) instead of continuing from b0
     int32_t pad;
 };
 

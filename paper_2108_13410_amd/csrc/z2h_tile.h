@@ -52,18 +52,31 @@ __device__ __forceinline__ uint32_t lay_base(int p, uint32_t t) {
 template <int R>
 __device__ __forceinline__ uint32_t slot(uint32_t e) { return e + (e >> R); }
 
-// Global index (within the state) of local index e of tile "tile".
+// Global index (within the state) of local index e of tile "tile".  Local
+// bits [0, c) are global [0, c); the transformed bits follow from b0, except
+// in a group split in two runs (hi > 0), whose top hi local bits sit at
+// [b1, b1 + hi).  The tile index fills the remaining global bits in
+// ascending order.
 __device__ __forceinline__ uint64_t glob(const GroupGeom &g, uint64_t tile, uint32_t e) {
     const uint32_t cm = (1u << g.c) - 1u;
     const int tlo_bits = g.b0 - g.c;
     const uint64_t tlo = tile & ((1ull << tlo_bits) - 1ull);
-    const uint64_t thi = tile >> tlo_bits;
-    return (uint64_t)(e & cm) | (tlo << g.c) | ((uint64_t)(e >> g.c) << g.b0) |
-           (thi << (g.b0 + g.m - g.c));
+    if (!g.hi)
+        return (uint64_t)(e & cm) | (tlo << g.c) | ((uint64_t)(e >> g.c) << g.b0) |
+               ((tile >> tlo_bits) << (g.b0 + g.m - g.c));
+    const int ga = g.m - g.c - g.hi;            // bits of the run at b0
+    const int tmid_bits = g.b1 - (g.b0 + ga);   // tile bits between the runs
+    const uint64_t tmid = (tile >> tlo_bits) & ((1ull << tmid_bits) - 1ull);
+    const uint64_t thi = tile >> (tlo_bits + tmid_bits);
+    const uint32_t et = e >> g.c;
+    return (uint64_t)(e & cm) | (tlo << g.c) | ((uint64_t)(et & ((1u << ga) - 1u)) << g.b0) |
+           (tmid << (g.b0 + ga)) | ((uint64_t)(et >> ga) << g.b1) | (thi << (g.b1 + g.hi));
 }
 
 // Global bit position of local bit x.
-__device__ __forceinline__ int gbit(const GroupGeom &g, int x) { return x < g.c ? x : g.b0 + (x - g.c); }
+__device__ __forceinline__ int gbit(const GroupGeom &g, int x) {
+    return x < g.c ? x : (g.hi && x >= g.m - g.hi) ? g.b1 + (x - (g.m - g.hi)) : g.b0 + (x - g.c);
+}
 
 template <typename Real, int R>
 __device__ __forceinline__ void butterflies(Cx<Real> (&v)[1 << R], int blo, int bhi) {
@@ -102,7 +115,8 @@ __device__ __forceinline__ void exchange(Cx<Real> (&v)[1 << R], Cx<Real> *lds, i
 
 // Per-thread constants of one layout.  The register bits of a layout are
 // global bits [gs, gs + R) (the planner never lets a layout straddle the
-// carried/transformed boundary), so register element q sits at global index
+// carried/transformed boundary or the boundary between the two runs of a
+// split group), so register element q sits at global index
 // i0 + (q << gs).  s0z/s0x are the plaquette/star syndromes of i0 and lz/lx
 // the syndrome columns of the R register bits (uniform across the block).
 template <int R>

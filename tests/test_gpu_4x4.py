@@ -210,6 +210,41 @@ def test_4x4_two_tile_schedule_bitwise():
             assert abs(obs[0][key] - obs[k][key]) <= 1e-13 * max(1.0, abs(obs[0][key])), key
 
 
+@pytest.mark.parametrize("dtype,cfg", [
+    (z2h.Z2H_C64, "split=12:4:12:0/10:5:14:4:1c:h5/10:5:14:4:1c,xcd=1"),
+    (z2h.Z2H_C128, "split=12:4:12:0/10:5:13:3:1c:h5/10:5:13:3:1c,xcd=3")])
+def test_4x4_split_run_schedule(dtype, cfg):
+    """The shipped 4x4 schedules: the middle group holds qubits 12-16 and
+    27-31, the top group 17-26 (":h5").  The same transforms grouped
+    differently round differently, so 6 Trotter steps of the 4x4 ramp are
+    compared with the planner's default schedule to the precision's
+    rounding on 2^20 sampled amplitudes, and the observables likewise."""
+    print(f"case 4x4 split-run schedule dtype={dtype}", flush=True)
+    plans = [z2h.z2h_plan_create(4, 4, dtype), z2h.z2h_plan_create_config(4, 4, dtype, cfg)]
+    d = z2h.z2h_plan_describe(plans[1])
+    assert [(g["b0"], g["hi"]) for g in d["groups"]] == [(0, 0), (12, 5), (17, 0)] and d["groups"][1]["b1"] == 27
+    sz = z2h.z2h_plan_sizes(plans[0])
+    ws = z2h.alloc_bytes(max(sz["ws_evolve"], sz["ws_observe"]))
+    psi = z2h.alloc_state(plans[0])
+    job = workloads.point_4x4()
+    rng = np.random.default_rng(11)
+    idx = torch.tensor(rng.integers(0, 1 << 32, 1 << 20), dtype=torch.int64, device="cuda")
+    samples, obs = [], []
+    for plan in plans:
+        z2h.z2h_state_init(plan, psi, z2h.Z2H_INIT_PSI1)
+        z2h.z2h_evolve(plan, psi, ws, z2h.schedule(job["c0"], job["c1"], job["M"], job["T"] / job["M"],
+                                                   k_end=6, renorm=1 if dtype == z2h.Z2H_C64 else 0))
+        samples.append(psi[idx].cpu().numpy().astype(np.complex128))
+        obs.append(z2h.z2h_observe(plan, psi, ws, job["c1"]))
+    del psi, ws
+    torch.cuda.empty_cache()
+    tol = 1e-12 if dtype == z2h.Z2H_C128 else 1e-5
+    scale = np.max(np.abs(samples[0]))
+    assert np.max(np.abs(samples[1] - samples[0])) <= tol * scale
+    for key in ("energy", "norm", "mx", "mz"):
+        assert abs(obs[0][key] - obs[1][key]) <= tol * max(1.0, abs(obs[0][key])), key
+
+
 def _plaquette_codewords():
     """The 2^15 sums (XOR) of plaquette masks of the 4x4 torus (library
     numbering): 15 of the 16 plaquettes are independent, the product of all

@@ -100,16 +100,35 @@ def lay_base(p, t, R):
     return (t & ((1 << p) - 1)) | ((t >> p) << (p + R))
 
 
-def glob(g, tile, e):
-    c, b0, m = g["c"], g["b0"], g["m"]
-    tlo_bits = b0 - c
-    tlo = tile & ((1 << tlo_bits) - 1)
-    thi = tile >> tlo_bits
-    return (e & ((1 << c) - 1)) | (tlo << c) | ((e >> c) << b0) | (thi << (b0 + m - c))
+def local_positions(g):
+    """Global bit of each local tile bit: carried bits [0, c), then the run
+    at b0, then (split groups, hi > 0) the run of hi bits at b1."""
+    c, b0, m, hi = g["c"], g["b0"], g["m"], g.get("hi", 0)
+    ga = m - c - hi
+    return list(range(c)) + list(range(b0, b0 + ga)) + list(range(g.get("b1", 0), g.get("b1", 0) + hi))
+
+
+def tile_positions(g, n):
+    """Global bits of the tile index: every other bit, ascending."""
+    loc = set(local_positions(g))
+    return [b for b in range(n) if b not in loc]
+
+
+def deposit(v, positions):
+    v = np.asarray(v, dtype=np.int64)
+    out = np.zeros_like(v)
+    for i, pos in enumerate(positions):
+        out |= ((v >> i) & 1) << pos
+    return out
+
+
+def glob(g, tile, e, n=None):
+    n = n if n is not None else g["tiles_log2"] + g["m"]
+    return deposit(e, local_positions(g)) | deposit(tile, tile_positions(g, n))
 
 
 def gbit(g, x):
-    return x if x < g["c"] else g["b0"] + (x - g["c"])
+    return local_positions(g)[x]
 
 
 PLANS = [(2, 2, 0, 0), (2, 2, 1, 0), (2, 3, 0, 0), (2, 3, 1, 0), (3, 3, 0, 0), (3, 3, 1, 0),
@@ -175,6 +194,32 @@ def test_schedule_strings_rejected():
     check_geometry(ok0)
 
 
+def test_split_run_groups():
+    """":h<N>": a strided group takes its top N bits from the top of the
+    state (two runs of global bits); later groups continue below them."""
+    cfg = "split=12:4:12:0/10:5:14:4:1c:h5/10:5:14:4:1c,xcd=7"
+    d = z2h.z2h_plan_describe(z2h.z2h_plan_create_config(4, 4, z2h.Z2H_C64, cfg))
+    g1, g2 = d["groups"][1], d["groups"][2]
+    assert (g1["b0"], g1["hi"], g1["b1"]) == (12, 5, 27)
+    assert (g2["b0"], g2["hi"]) == (17, 0)
+    assert gbit(g1, 4) == 12 and gbit(g1, 8) == 16 and gbit(g1, 9) == 27 and gbit(g1, 13) == 31
+    check_geometry(z2h.z2h_plan_create_config(4, 4, z2h.Z2H_C64, cfg))
+    check_geometry(z2h.z2h_plan_create_config(4, 4, z2h.Z2H_C128, "split=12:4:12:0/10:5:13:3:1c:h5/10:5:13:3:1c"))
+    # small enough for the exhaustive tile-coverage check (n = 18)
+    small = z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C64, "split=8:4:12:0/6:3:10:4:h3/4:2:8:4")
+    ds = z2h.z2h_plan_describe(small)
+    assert [(g["b0"], g["hi"], g["b1"] if g["hi"] else None) for g in ds["groups"]] == [
+        (0, 0, None), (8, 3, 15), (11, 0, None)]
+    check_geometry(small)
+    for bad in ("split=12:4:12:0:h4/10:5:14:4/10:5:14:4",       # group 0 cannot split
+                "split=12:4:12:0/10:5:14:4:h3/10:5:14:4",         # run not a whole window
+                "split=12:4:12:0/10:5:14:4:h10/10:5:14:4",        # high run as wide as the group
+                "split=12:4:12:0/10:5:14:4:h5/10:5:14:4/5:5:9:4",  # covers more than n bits
+                "split=12:4:12:0/10:5:14:4:hx/10:5:14:4"):
+        with pytest.raises(z2h.Z2HError):
+            z2h.z2h_plan_create_config(4, 4, z2h.Z2H_C64, bad)
+
+
 def check_full_lds(g, n, esize):
     """Re-enact the full-window kernels' LDS placement: one slot per local
     index inside the allocated block, and the bank pattern of every layout
@@ -231,10 +276,17 @@ def check_geometry(plan):
         assert 64 <= threads <= 512
         assert g["lds_bytes"] <= LDS_LIMIT
         assert g["tiles_log2"] == n - m
-        # local bits [0,c) and [c,m) map to global [0,c) and [b0, b0+m-c); tile bits fill the rest
-        local = set(range(c)) | set(range(b0, b0 + m - c))
-        tilebits = set(range(c, b0)) | set(range(b0 + m - c, n))
+        # local bits [0,c) and [c,m) map to global [0,c) and [b0, b0+m-c)
+        # (split groups: [b0, b0+m-c-hi) and [b1, b1+hi)); tile bits fill the rest
+        hr = g["hi"]
+        local = set(local_positions(g))
+        assert len(local) == m and local == set(range(c)) | set(range(b0, b0 + m - c - hr)) | set(
+            range(g["b1"], g["b1"] + hr))
+        tilebits = set(tile_positions(g, n))
         assert not (local & tilebits) and (local | tilebits) == set(range(n))
+        if hr:
+            # every register window lies inside one run
+            assert g["full"] and hr % R == 0 and g["b1"] >= b0 + m - c - hr
         covered += [gbit(g, x) for x in range(x0, x1)]
         # layouts: windows of R local bits inside the transform range, never
         # straddling the carried boundary; butterflies cover [x0, x1) once
@@ -242,6 +294,7 @@ def check_geometry(plan):
         for p, lo, hi in zip(g["p"], g["blo"], g["bhi"]):
             assert x0 <= p and p + R <= m
             assert p >= c or p + R <= c
+            assert hr == 0 or p >= m - hr or p + R <= m - hr
             bits = set(range(p + lo, p + hi))
             assert bits <= set(range(x0, x1)) and not (bits & done)
             done |= bits
