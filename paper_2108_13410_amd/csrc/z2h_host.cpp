@@ -110,6 +110,15 @@ static void plan_layouts(GroupGeom &g, bool resident) {
         g.full = width / R;
 }
 
+// A layout window [p, p + R) that holds bits of both runs of a split group.
+bool geom_straddles(const GroupGeom &g) {
+    if (!g.hi) return false;
+    const int xb = g.m - g.hi;
+    for (int l = 0; l < g.nlay; ++l)
+        if (g.p[l] < xb && g.p[l] + g.R > xb) return true;
+    return false;
+}
+
 static int pick_R(bool c128, int m) {
     int R = c128 ? 4 : 5;
     while (R > 2 && m - R < 6) --R;  // keep at least one wave per workgroup
@@ -172,6 +181,12 @@ static z2h_status check_block(Plan &P) {
         if (lds_bytes(P, P.geom[j], P.geom[j].R) > (size_t)kMaxLdsBytes)
             return fail(Z2H_ERR_UNSUPPORTED, "group %d needs %zu bytes of LDS", j,
                         lds_bytes(P, P.geom[j], P.geom[j].R));
+        // the observables (and the Hamiltonian passes) transform every group
+        // with whole elements in LDS, also where the Trotter passes exchange
+        // one component at a time
+        if (obs_lds_bytes(P, P.geom[j], P.geom[j].R) > (size_t)kMaxLdsBytes)
+            return fail(Z2H_ERR_UNSUPPORTED, "group %d: the observables need %zu bytes of LDS", j,
+                        obs_lds_bytes(P, P.geom[j], P.geom[j].R));
         if (P.K == 1 && !P.geom[0].full)
             return fail(Z2H_ERR_UNSUPPORTED, "no one-workgroup kernel for n = %d", P.n);
     }
@@ -253,7 +268,9 @@ struct GroupChoice {
     int G, R, NL, m, c;
     int np;  // tiles per block: 1, or 2 (two-tile blocks of a strided group)
     int cx = 0;  // one-tile blocks: 1 = layout changes exchange one component at a time
-    int hi = 0;  // > 0: the group's top hi bits are taken from the top of the state
+    int hi = 0;    // > 0: the group's top hi bits form a second run of qubits
+    int at = -1;   // first qubit of the (low) run, or -1: the lowest free qubit
+    int hat = -1;  // first qubit of the high run, or -1: the highest free qubits
 };
 
 static bool fit_group(const Plan &P, int j, int b0, int G, int R, int NL, int m_pref, int m_hi, int c_min,
@@ -346,33 +363,68 @@ static z2h_status apply_split(Plan &P, const GroupChoice *ch, int K) {
     const int n = P.n;
     memset(P.geom, 0, sizeof P.geom);
     P.K = K;
-    int b = 0, top = 0;  // next free bit from below; bits taken from the top
+    // qubits taken so far; a group takes one run, or two (a split group: the
+    // run at b0 and hi qubits at b1), given explicitly or from the free ones
+    uint64_t taken = 0;
+    auto is_free = [&](int lo, int len) {
+        if (lo < 0 || len < 0 || lo + len > n) return false;
+        for (int x = lo; x < lo + len; ++x)
+            if (taken >> x & 1) return false;
+        return true;
+    };
     for (int j = 0; j < K; ++j) {
         GroupGeom &g = P.geom[j];
-        if (ch[j].G <= 0 || ch[j].R < 2 || ch[j].R > 5 || ch[j].m < ch[j].G || ch[j].m > 14)
+        const int G = ch[j].G;
+        if (G <= 0 || ch[j].R < 2 || ch[j].R > 5 || ch[j].m < G || ch[j].m > 14)
             return fail(Z2H_ERR_INVALID, "bad split group %d", j);
-        if (j == 0 && ch[j].c != 0) return fail(Z2H_ERR_INVALID, "group 0 carries no bits");
-        if (j > 0 && (ch[j].c > b || ch[j].m != ch[j].c + ch[j].G)) return fail(Z2H_ERR_INVALID, "bad split group %d", j);
-        if (ch[j].hi < 0 || ch[j].hi >= ch[j].G || (ch[j].hi && j == 0))
-            return fail(Z2H_ERR_INVALID, "group %d: bad high-run width %d", j, ch[j].hi);
+        if (j == 0 && (ch[j].c != 0 || ch[j].hi || ch[j].at > 0)) return fail(Z2H_ERR_INVALID, "group 0 is qubits 0..G-1 and carries none");
+        if (j > 0 && ch[j].m != ch[j].c + G) return fail(Z2H_ERR_INVALID, "bad split group %d", j);
+        if (ch[j].hi < 0 || ch[j].hi >= G) return fail(Z2H_ERR_INVALID, "group %d: bad high-run width %d", j, ch[j].hi);
+        int lowest = 0;
+        while (lowest < n && (taken >> lowest & 1)) ++lowest;
+        int b0 = ch[j].at >= 0 ? ch[j].at : lowest, hi = ch[j].hi, b1 = 0;
+        if (hi) {
+            int h = ch[j].hat;
+            if (h < 0) {  // the highest free qubits
+                h = n;
+                while (h > 0 && (taken >> (h - 1) & 1)) --h;
+                h -= hi;
+            }
+            b1 = h;
+        } else if (ch[j].at < 0) {
+            // the lowest G free qubits, one run or two
+            int got = 0, x = lowest;
+            while (got < G && x < n && !(taken >> x & 1)) { ++x; ++got; }
+            if (got < G) {
+                int y = x;
+                while (y < n && (taken >> y & 1)) ++y;
+                hi = G - got;
+                b1 = y;
+            }
+        }
+        const int ga = G - hi;
+        if (!is_free(b0, ga) || (hi && (!is_free(b1, hi) || b1 < b0 + ga)))
+            return fail(Z2H_ERR_INVALID, "group %d: qubits taken twice or out of range", j);
+        if (j > 0 && ch[j].c > b0) return fail(Z2H_ERR_INVALID, "group %d: carried bits reach its qubits", j);
+        for (int x = b0; x < b0 + ga; ++x) taken |= 1ull << x;
+        for (int x = b1; x < b1 + hi; ++x) taken |= 1ull << x;
         g.R = ch[j].R;
         g.m = ch[j].m;
         g.c = ch[j].c;
-        g.b0 = j == 0 ? 0 : b;
+        g.b0 = b0;
         g.x0 = g.c;
-        g.x1 = g.c + ch[j].G;
+        g.x1 = g.c + G;
         g.tiles_log2 = n - g.m;
         plan_layouts(g, false);
-        if (ch[j].hi) {
-            // two runs: [b0, b0 + G - hi) and the top hi bits not yet taken;
-            // every register window must lie inside one run
-            if (!g.full || ch[j].hi % g.R)
-                return fail(Z2H_ERR_INVALID, "group %d: a high run of %d bits needs whole windows of %d", j,
-                            ch[j].hi, g.R);
-            top += ch[j].hi;
-            g.hi = ch[j].hi;
-            g.b1 = n - top;
-            if (g.b1 < g.b0 + ch[j].G - ch[j].hi) return fail(Z2H_ERR_INVALID, "group %d: runs overlap", j);
+        if (hi && b1 == b0 + ga) hi = 0;  // the two runs meet: one run
+        if (hi) {
+            // two separate runs: only the component-exchange pass kernels
+            // (and the observables, adjoint and Hamiltonian passes) are
+            // compiled for them, including windows across the two runs
+            g.hi = hi;
+            g.b1 = b1;
+            if (!g.full || !ch[j].cx)
+                return fail(Z2H_ERR_INVALID, "group %d: a group in two runs needs whole windows and ':1c'", j);
         }
         if ((ch[j].np != 1 && ch[j].np != 2) || (ch[j].cx && ch[j].np != 1))
             return fail(Z2H_ERR_INVALID, "group %d: bad tiles-per-block option", j);
@@ -396,9 +448,9 @@ static z2h_status apply_split(Plan &P, const GroupChoice *ch, int K) {
         } else {
             g.pair = 1;
         }
-        b += ch[j].G - ch[j].hi;
     }
-    if (b + top != n) return fail(Z2H_ERR_INVALID, "split covers %d of %d bits", b + top, n);
+    const uint64_t all = n == 64 ? ~0ull : (1ull << n) - 1;
+    if (taken != all) return fail(Z2H_ERR_INVALID, "split covers %d of %d bits", __builtin_popcountll(taken), n);
     return check_block(P);
 }
 
@@ -475,12 +527,22 @@ static z2h_status plan_from_config(Plan &P, const char *cfg, int m_pref, int m_h
                     cx = 1;
                 }
             }
-            int hi = 0;
-            if (q[0] == ':' && q[1] == 'h') {  // ":h<N>": top N bits from the top of the state
-                if (sscanf(q, ":h%d%n", &hi, &used2) != 1) return fail(Z2H_ERR_INVALID, "unreadable split in \"%s\"", cfg);
-                q += used2;
+            int hi = 0, at = -1, hat = -1;
+            while (q[0] == ':' && (q[1] == 'h' || q[1] == 'a')) {
+                if (q[1] == 'h') {  // ":h<N>[@<Q>]": the top N bits form a run (at qubit Q)
+                    if (sscanf(q, ":h%d%n", &hi, &used2) != 1 || hi < 1)
+                        return fail(Z2H_ERR_INVALID, "unreadable split in \"%s\"", cfg);
+                    q += used2;
+                    if (*q == '@') {
+                        if (sscanf(q, "@%d%n", &hat, &used2) != 1) return fail(Z2H_ERR_INVALID, "unreadable split in \"%s\"", cfg);
+                        q += used2;
+                    }
+                } else {  // ":at<Q>": the (low) run starts at qubit Q
+                    if (sscanf(q, ":at%d%n", &at, &used2) != 1) return fail(Z2H_ERR_INVALID, "unreadable split in \"%s\"", cfg);
+                    q += used2;
+                }
             }
-            ch[K++] = {G, R, G / std::max(R, 1), m, c, np, cx, hi};
+            ch[K++] = {G, R, G / std::max(R, 1), m, c, np, cx, hi, at, hat};
             if (*q != '/') break;
             ++q;
         }

@@ -29,13 +29,13 @@ namespace z2h {
 // Streaming loads of NT tiles, element by element across the tiles: with
 // two tiles of a strided group the two 128-byte halves of each 256-byte row
 // are requested back to back.
-template <typename Real, int R, int NT>
+template <typename Real, int R, int NT, bool SW = false>
 __device__ __forceinline__ void load_tiles(Cx<Real> (&v)[NT][1 << R], const Cx<Real> *st,
                                            const LayCtx<R> (&L)[NT]) {
 #pragma unroll
     for (int q = 0; q < (1 << R); ++q) {
 #pragma unroll
-        for (int s = 0; s < NT; ++s) v[s][q] = ldc<Real, true>(st + L[s].i0 + ((uint64_t)q << L[s].gs));
+        for (int s = 0; s < NT; ++s) v[s][q] = ldc<Real, true>(st + L[s].i0 + reg_off<R, SW>(L[s], q));
     }
 }
 
@@ -572,7 +572,7 @@ __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, 
 #pragma unroll
         for (int s = 0; s < NT; ++s) {
             LayCtx<R> Ls;
-            lay_ctx<R>(Ls, g, a.lat, tile0 + s, p0, t, true, op.basis);
+            lay_ctx<R, CX != 0>(Ls, g, a.lat, tile0 + s, p0, t, true, op.basis);
             if (meas_norm) {
                 const double q = block_sum(sumsq<Real, R>(v[s]), red);
                 if (t == 0 && J.norm_part) gst(J.norm_part, tile0 + s, q);
@@ -591,7 +591,7 @@ __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, 
 #pragma unroll
         for (int s = 0; s < NT; ++s) {
             LayCtx<R> Lm;
-            lay_ctx<R>(Lm, g, a.lat, tile0 + s, pl, t, true, op.basis);
+            lay_ctx<R, CX != 0>(Lm, g, a.lat, tile0 + s, pl, t, true, op.basis);
             if constexpr (KIND == kPhaseB) {
                 if (meas_norm) {
                     const double q = block_sum(sumsq<Real, R>(v[s]), red);
@@ -618,10 +618,10 @@ __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, 
             uint32_t tt = t;
             asm volatile("" : "+v"(tt));
             LayCtx<R> Ls;
-            lay_ctx<R>(Ls, g, a.lat, tile0 + s, x1 - R, tt, false);
-            store_tile<Real, R, true>(v[s], st, Ls);
+            lay_ctx<R, CX != 0>(Ls, g, a.lat, tile0 + s, x1 - R, tt, false);
+            store_tile<Real, R, true, CX != 0>(v[s], st, Ls);
         } else {
-            store_tile<Real, R, true>(v[s], st, L0[s]);
+            store_tile<Real, R, true, CX != 0>(v[s], st, L0[s]);
         }
     }
 }
@@ -651,7 +651,7 @@ __device__ __forceinline__ void level_body(const LevelArgs &a) {
     Cx<Real> v[NT][1 << R];
     LayCtx<R> L0[NT];
 #pragma unroll
-    for (int s = 0; s < NT; ++s) lay_ctx<R>(L0[s], g, a.lat, tile0 + s, g.x1 - R, t, false);
+    for (int s = 0; s < NT; ++s) lay_ctx<R, CX != 0>(L0[s], g, a.lat, tile0 + s, g.x1 - R, t, false);
     // The tile loads are issued at one point of the code (two load sites
     // would hold registers for both and spill).  With a uniform job stride
     // (jmode 0) they go out before the job record is read; otherwise the
@@ -668,7 +668,7 @@ __device__ __forceinline__ void level_body(const LevelArgs &a) {
         if (op.kind == kIdle || op.group != a.group) return;  // uniform per block
         st = base + J.offset;
     }
-    load_tiles<Real, R, NT>(v, st, L0);
+    load_tiles<Real, R, NT, CX != 0>(v, st, L0);
     if (!early) {
         J = job_record(a.jobs, a.jidx ? job_index(a.jidx, jb) : jb, a.job_inline);
         op = a.force_plain ? LevelOp{a.group, kPlainH, 0, -1, -1, 0, 0, 0}
@@ -866,30 +866,30 @@ __global__ void __launch_bounds__(512) adj_kernel(AdjArgs a) {
     Cx<Real> *A = reinterpret_cast<Cx<Real> *>(a.A);
     Cx<Real> *B = reinterpret_cast<Cx<Real> *>(a.B);
     LayCtx<R> L0, Lm;
-    lay_ctx<R>(L0, g, a.lat, tile, p0, t, true);
-    lay_ctx<R>(Lm, g, a.lat, tile, a.no_transform ? p0 : pl, t, true);
+    lay_ctx<R, true>(L0, g, a.lat, tile, p0, t, true);
+    lay_ctx<R, true>(Lm, g, a.lat, tile, a.no_transform ? p0 : pl, t, true);
     Cx<Real> va[1 << R], vb[1 << R];
 
     if (a.mode == 0) {
-        load_tile<Real, R>(va, A, L0);
+        load_tile<Real, R, false, true>(va, A, L0);
         fwd_full<Real, R, NL>(va, lds, x1, t);
         if (NL > 1) xchg<Real, R>(va, lds, pl, p0, t);
-        store_tile<Real, R>(va, A, L0);
+        store_tile<Real, R, false, true>(va, A, L0);
         if (B) {
-            load_tile<Real, R>(vb, B, L0);
+            load_tile<Real, R, false, true>(vb, B, L0);
             fwd_full<Real, R, NL>(vb, lds, x1, t);
             if (NL > 1) xchg<Real, R>(vb, lds, pl, p0, t);
-            store_tile<Real, R>(vb, B, L0);
+            store_tile<Real, R, false, true>(vb, B, L0);
         }
         return;
     }
     if (a.mode == 2) {
         build_diag_table<Real>(tab, nst, n, a.dJ, a.dh, a.dscale);
-        load_tile<Real, R>(va, A, L0);
+        load_tile<Real, R, false, true>(va, A, L0);
         if (!a.no_transform) fwd_full<Real, R, NL>(va, lds, x1, t);
         apply_phase<Real, R>(va, Lm, a.op.basis, n, tab);
         if (!a.no_transform) bwd_full<Real, R, NL>(va, lds, x1, t);
-        store_tile<Real, R>(va, B, L0);
+        store_tile<Real, R, false, true>(va, B, L0);
         return;
     }
     // mode 1: undo a diagonal level on both states, reducing the gradient
@@ -899,8 +899,8 @@ __global__ void __launch_bounds__(512) adj_kernel(AdjArgs a) {
         const double scale = a.op.basis ? ldexp(1.0, -n) : 1.0;
         build_table<Real>(tab, fac, nst, n, -alpha, -beta, scale);
     }
-    load_tile<Real, R>(va, A, L0);
-    load_tile<Real, R>(vb, B, L0);
+    load_tile<Real, R, false, true>(va, A, L0);
+    load_tile<Real, R, false, true>(vb, B, L0);
     if (!a.no_transform) {
         fwd_full<Real, R, NL>(va, lds, x1, t);
         fwd_full<Real, R, NL>(vb, lds, x1, t);
@@ -910,9 +910,9 @@ __global__ void __launch_bounds__(512) adj_kernel(AdjArgs a) {
     apply_phase<Real, R>(va, Lm, a.op.basis, n, tab);
     apply_phase<Real, R>(vb, Lm, a.op.basis, n, tab);
     if (!a.no_transform) bwd_full<Real, R, NL>(va, lds, x1, t);
-    store_tile<Real, R>(va, A, L0);
+    store_tile<Real, R, false, true>(va, A, L0);
     if (!a.no_transform) bwd_full<Real, R, NL>(vb, lds, x1, t);
-    store_tile<Real, R>(vb, B, L0);
+    store_tile<Real, R, false, true>(vb, B, L0);
 }
 
 // Sum of one level's per-block partials (fixed order).
@@ -966,7 +966,7 @@ __device__ __forceinline__ void obs_accum(const Cx<Real> (&v)[1 << R], const Lay
             s ^= basis ? L.lx[r] : L.lz[r];
 #pragma unroll
             for (int j = 0; j < kMaxLoops; ++j)
-                if (j < nloops) lp[j] ^= (loops[j] >> (L.gs + r)) & 1u;
+                if (j < nloops) lp[j] ^= (loops[j] >> reg_bit(L, r)) & 1u;
         }
         const double p2 = (double)v[q].x * (double)v[q].x + (double)v[q].y * (double)v[q].y;
         const int k = popc(s);
@@ -1013,8 +1013,8 @@ __global__ void __launch_bounds__(512) obs_kernel(ObsArgs a) {
     for (uint64_t tile = blockIdx.x; tile < tiles; tile += gridDim.x) {
         Cx<Real> v[1 << R];
         LayCtx<R> L0;
-        lay_ctx<R>(L0, g, a.lat, tile, g.p[0], t, a.redZ != 0);
-        load_tile<Real, R>(v, src, L0);
+        lay_ctx<R, true>(L0, g, a.lat, tile, g.p[0], t, a.redZ != 0);
+        load_tile<Real, R, false, true>(v, src, L0);
         if (a.redZ) obs_accum<Real, R>(v, L0, 0, a.lat, a.zloops, a.nz, true, accz);
         int cur = 0;
         if (a.doH) {
@@ -1026,12 +1026,12 @@ __global__ void __launch_bounds__(512) obs_kernel(ObsArgs a) {
         }
         if (a.redX) {
             LayCtx<R> Lm;
-            lay_ctx<R>(Lm, g, a.lat, tile, g.p[cur], t, true);
+            lay_ctx<R, true>(Lm, g, a.lat, tile, g.p[cur], t, true);
             obs_accum<Real, R>(v, Lm, 1, a.lat, a.xloops, a.nx, false, accx);
         }
         if (dst) {
             if (cur != 0) exchange<Real, R>(v, lds, g.p[cur], g.p[0], t);
-            store_tile<Real, R>(v, dst, L0);
+            store_tile<Real, R, false, true>(v, dst, L0);
         }
     }
     const size_t rec = ((size_t)job * gridDim.x + blockIdx.x) * kObsQ;

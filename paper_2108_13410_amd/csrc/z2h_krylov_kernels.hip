@@ -88,7 +88,7 @@ __device__ __forceinline__ void add_diag_z(Cx<Real> (&v)[1 << R], const Cx<Real>
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             const int q = (c0 + i) ^ ((c0 + i) >> 1);
-            xv[i] = b[(uint64_t)q << L.gs];
+            xv[i] = b[reg_off<R, true>(L, q)];
         }
 #pragma unroll
         for (int i = 0; i < C; ++i) {
@@ -123,8 +123,8 @@ __device__ __forceinline__ void lanczos_out(const Cx<Real> (&v)[1 << R], const C
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             const int q = (c0 + i) ^ ((c0 + i) >> 1);
-            uv[i] = bu[(uint64_t)q << L.gs];
-            pv[i] = use_prev ? bp[(uint64_t)q << L.gs] : Cx<Real>{(Real)0, (Real)0};
+            uv[i] = bu[reg_off<R, true>(L, q)];
+            pv[i] = use_prev ? bp[reg_off<R, true>(L, q)] : Cx<Real>{(Real)0, (Real)0};
         }
 #pragma unroll
         for (int i = 0; i < C; ++i) {
@@ -132,7 +132,7 @@ __device__ __forceinline__ void lanczos_out(const Cx<Real> (&v)[1 << R], const C
             if (idx) s ^= L.lz[__builtin_ctz(idx)];
             const Real d = (Real)(diag_value(lat.nst, lat.n, s, L.w0 + __builtin_popcount(q), J, h) - alpha);
             Cx<Real> r{rs * (v[q].x + d * uv[i].x) - rc * pv[i].x, rs * (v[q].y + d * uv[i].y) - rc * pv[i].y};
-            bw[(uint64_t)q << L.gs] = r;
+            bw[reg_off<R, true>(L, q)] = r;
             acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -177,8 +177,8 @@ __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
     LayCtx<R> Ln;
     if constexpr (PF) {
         if (tile < tiles) {
-            lay_ctx<R>(Ln, g, a.lat, tile, g.p[0], t, syn0);
-            load_tile<Real, R>(vn, src, Ln);
+            lay_ctx<R, true>(Ln, g, a.lat, tile, g.p[0], t, syn0);
+            load_tile<Real, R, false, true>(vn, src, Ln);
         }
     }
     for (; tile < tiles; tile += gridDim.x) {
@@ -190,12 +190,12 @@ __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
             for (int q = 0; q < (1 << R); ++q) v[q] = vn[q];
             const uint64_t nt = tile + gridDim.x;
             if (nt < tiles) {
-                lay_ctx<R>(Ln, g, a.lat, nt, g.p[0], t, syn0);
-                load_tile<Real, R>(vn, src, Ln);
+                lay_ctx<R, true>(Ln, g, a.lat, nt, g.p[0], t, syn0);
+                load_tile<Real, R, false, true>(vn, src, Ln);
             }
         } else {
-            lay_ctx<R>(L0, g, a.lat, tile, g.p[0], t, syn0);
-            load_tile<Real, R>(v, src, L0);
+            lay_ctx<R, true>(L0, g, a.lat, tile, g.p[0], t, syn0);
+            load_tile<Real, R, false, true>(v, src, L0);
         }
         if (a.part_z) accz += diag_norm_z<Real, R>(v, L0, a.lat, a.JB, a.hz);
         int cur = 0;
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
         }
         if (a.top) {
             LayCtx<R> Lm;
-            lay_ctx<R>(Lm, g, a.lat, tile, g.p[cur], t, true);
+            lay_ctx<R, true>(Lm, g, a.lat, tile, g.p[cur], t, true);
             mul_diag_x<Real, R>(v, Lm, a.lat, a.JA, a.hx, a.xscale, a.part_x ? &accx : nullptr);
             for (int j = g.nlay - 1; j >= 0; --j) {
                 if (j != cur) {
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
             continue;
         }
         if (a.final_pass) add_diag_z<Real, R>(v, x, L0, a.lat, a.JB, a.hz, acc);
-        store_tile<Real, R>(v, dst, L0);
+        store_tile<Real, R, false, true>(v, dst, L0);
     }
     if (a.part) {
         const double s = block_sum(acc, red);

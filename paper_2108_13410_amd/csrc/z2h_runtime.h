@@ -65,6 +65,10 @@ void tune_store(int n, bool c128, int batch, const std::string &cfg);
 z2h_status tune_load(const char *path);
 int tune_batch_class(int batch);
 size_t lds_bytes(const Plan &P, const GroupGeom &g, int R);
+// A group with a layout window across the two runs of a split group: the
+// component-exchange pass kernels, the observables, the adjoint and the
+// Hamiltonian passes load such windows; the other pass kernels do not.
+bool geom_straddles(const GroupGeom &g);
 size_t obs_lds_bytes(const Plan &P, const GroupGeom &g, int R);
 int obs_workers(const GroupGeom &g);
 size_t obs_records(const Plan &P);

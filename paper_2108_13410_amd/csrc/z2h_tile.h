@@ -56,12 +56,14 @@ __device__ __forceinline__ uint32_t slot(uint32_t e) { return e + (e >> R); }
 // bits [0, c) are global [0, c); the transformed bits follow from b0, except
 // in a group split in two runs (hi > 0), whose top hi local bits sit at
 // [b1, b1 + hi).  The tile index fills the remaining global bits in
-// ascending order.
+// ascending order.  SPLIT: the kernel may be given split groups (the
+// planner gives them only to the kernels compiled with it).
+template <bool SPLIT = false>
 __device__ __forceinline__ uint64_t glob(const GroupGeom &g, uint64_t tile, uint32_t e) {
     const uint32_t cm = (1u << g.c) - 1u;
     const int tlo_bits = g.b0 - g.c;
     const uint64_t tlo = tile & ((1ull << tlo_bits) - 1ull);
-    if (!g.hi)
+    if (!SPLIT || !g.hi)
         return (uint64_t)(e & cm) | (tlo << g.c) | ((uint64_t)(e >> g.c) << g.b0) |
                ((tile >> tlo_bits) << (g.b0 + g.m - g.c));
     const int ga = g.m - g.c - g.hi;            // bits of the run at b0
@@ -74,7 +76,9 @@ __device__ __forceinline__ uint64_t glob(const GroupGeom &g, uint64_t tile, uint
 }
 
 // Global bit position of local bit x.
+template <bool SPLIT = false>
 __device__ __forceinline__ int gbit(const GroupGeom &g, int x) {
+    if (!SPLIT) return x < g.c ? x : g.b0 + (x - g.c);
     return x < g.c ? x : (g.hi && x >= g.m - g.hi) ? g.b1 + (x - (g.m - g.hi)) : g.b0 + (x - g.c);
 }
 
@@ -114,18 +118,37 @@ __device__ __forceinline__ void exchange(Cx<Real> (&v)[1 << R], Cx<Real> *lds, i
 }
 
 // Per-thread constants of one layout.  The register bits of a layout are
-// global bits [gs, gs + R) (the planner never lets a layout straddle the
-// carried/transformed boundary or the boundary between the two runs of a
-// split group), so register element q sits at global index
-// i0 + (q << gs).  s0z/s0x are the plaquette/star syndromes of i0 and lz/lx
+// global bits [gs, gs + nlo) and, when the window straddles the boundary
+// between the two runs of a split group, [gs2, gs2 + R - nlo) (the planner
+// never lets a layout straddle the carried/transformed boundary).  Register
+// element q sits at global index i0 + reg_off(q): (q << gs) for a window
+// inside one run.  s0z/s0x are the plaquette/star syndromes of i0 and lz/lx
 // the syndrome columns of the R register bits (uniform across the block).
 template <int R>
 struct LayCtx {
     uint64_t i0;
     int gs, w0;
+    int gs2, nlo;
     uint32_t s0z, s0x;
     uint32_t lz[R], lx[R];
 };
+
+// Global offset of register element q.  SW: the layout may straddle two
+// runs (only the kernels that take split-window groups pass true; for a
+// window inside one run nlo = R and the second term vanishes).
+template <int R, bool SW>
+__device__ __forceinline__ uint64_t reg_off(const LayCtx<R> &L, int q) {
+    if constexpr (SW)
+        return ((uint64_t)(q & ((1 << L.nlo) - 1)) << L.gs) | ((uint64_t)(q >> L.nlo) << L.gs2);
+    else
+        return (uint64_t)q << L.gs;
+}
+
+// Global bit of register bit r of a layout.
+template <int R>
+__device__ __forceinline__ int reg_bit(const LayCtx<R> &L, int r) {
+    return r < L.nlo ? L.gs + r : L.gs2 + (r - L.nlo);
+}
 
 __device__ __forceinline__ uint32_t syndrome_direct(const uint32_t *masks, int nst, uint64_t i) {
     uint32_t s = 0;
@@ -136,19 +159,28 @@ __device__ __forceinline__ uint32_t syndrome_direct(const uint32_t *masks, int n
 
 // want_syn: fill the syndromes; which: 0 plaquettes only, 1 stars only, 2
 // both (a phase pass needs only the basis it applies).
-template <int R>
+template <int R, bool SPLIT = false>
 __device__ __forceinline__ void lay_ctx(LayCtx<R> &L, const GroupGeom &g, const LatticeDev &lat,
                                         uint64_t tile, int p, uint32_t t, bool want_syn, int which = 2) {
-    L.i0 = glob(g, tile, lay_base<R>(p, t));
-    L.gs = gbit(g, p);
+    L.i0 = glob<SPLIT>(g, tile, lay_base<R>(p, t));
+    L.gs = gbit<SPLIT>(g, p);
+    if constexpr (SPLIT) {
+        const int xb = g.m - g.hi;  // local start of the second run
+        L.nlo = (g.hi && p < xb && p + R > xb) ? xb - p : R;
+        L.gs2 = g.b1;
+    } else {
+        L.nlo = R;
+        L.gs2 = 0;
+    }
     L.w0 = __builtin_popcountll(L.i0);
     if (want_syn) {
         L.s0z = which != 1 ? syndrome_direct(lat.zmask, lat.nst, L.i0) : 0u;
         L.s0x = which != 0 ? syndrome_direct(lat.xmask, lat.nst, L.i0) : 0u;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-            L.lz[r] = lat.zsyn[L.gs + r];
-            L.lx[r] = lat.xsyn[L.gs + r];
+            const int b = SPLIT ? reg_bit(L, r) : L.gs + r;
+            L.lz[r] = lat.zsyn[b];
+            L.lx[r] = lat.xsyn[b];
         }
     }
 }
@@ -180,25 +212,25 @@ __device__ __forceinline__ void stc(Cx<Real> *p, Cx<Real> x) {
     }
 }
 
-template <typename Real, int R, bool NT = false>
+template <typename Real, int R, bool NT = false, bool SW = false>
 __device__ __forceinline__ void load_tile(Cx<Real> (&v)[1 << R], const Cx<Real> *st,
                                           const LayCtx<R> &L) {
     const Cx<Real> *b = st + L.i0;
 #pragma unroll
-    for (int q = 0; q < (1 << R); ++q) v[q] = ldc<Real, NT>(b + ((uint64_t)q << L.gs));
+    for (int q = 0; q < (1 << R); ++q) v[q] = ldc<Real, NT>(b + reg_off<R, SW>(L, q));
 }
 
 // The base index is passed through an empty asm statement so that the
 // compiler recomputes the 2^R store addresses instead of keeping the load
 // addresses alive through the whole pass (2 VGPRs each).
-template <typename Real, int R, bool NT = false>
+template <typename Real, int R, bool NT = false, bool SW = false>
 __device__ __forceinline__ void store_tile(const Cx<Real> (&v)[1 << R], Cx<Real> *st,
                                            const LayCtx<R> &L) {
     uint64_t i0 = L.i0;
     asm volatile("" : "+v"(i0));
     Cx<Real> *b = st + i0;
 #pragma unroll
-    for (int q = 0; q < (1 << R); ++q) stc<Real, NT>(b + ((uint64_t)q << L.gs), v[q]);
+    for (int q = 0; q < (1 << R); ++q) stc<Real, NT>(b + reg_off<R, SW>(L, q), v[q]);
 }
 
 // Workgroups of a launch are handed to the eight XCDs in turn (block b to

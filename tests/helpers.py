@@ -70,11 +70,13 @@ def fidelity_loss(a, b):
 
 
 def gpu_run(Lx, Ly, dtype, c0, c1, M, dt, init=z2h.Z2H_INIT_PSI1, max_tile_bits=0, obsH=None,
-            chunks=None, **kw):
-    """Init + evolve (+ optional split into step chunks) + observe on cuda:0.
+            chunks=None, config=None, **kw):
+    """Init + evolve (+ optional split into step chunks) + observe on cuda:0
+    (planner's schedule, or the schedule string `config`).
     Returns (state as complex128 numpy in library order, observables, norms)."""
     import torch
-    plan = z2h.z2h_plan_create(Lx, Ly, dtype, max_tile_bits)
+    plan = (z2h.z2h_plan_create_config(Lx, Ly, dtype, config) if config
+            else z2h.z2h_plan_create(Lx, Ly, dtype, max_tile_bits))
     sizes = z2h.z2h_plan_sizes(plan)
     psi = z2h.alloc_state(plan)
     extra = 16 * M + 1024

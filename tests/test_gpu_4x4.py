@@ -212,17 +212,22 @@ def test_4x4_two_tile_schedule_bitwise():
 
 @pytest.mark.parametrize("dtype,cfg", [
     (z2h.Z2H_C64, "split=12:4:12:0/10:5:14:4:1c:h5/10:5:14:4:1c,xcd=1"),
-    (z2h.Z2H_C128, "split=12:4:12:0/10:5:13:3:1c:h5/10:5:13:3:1c,xcd=3")])
+    (z2h.Z2H_C64, "split=12:4:12:0/10:5:14:4:1c:h5@23/10:5:14:4:1c,xcd=1"),
+    (z2h.Z2H_C128, "split=12:4:12:0/10:5:13:3:1c:h5/10:5:13:3:1c,xcd=3"),
+    (z2h.Z2H_C128, "split=12:4:12:0/10:5:13:3:1c:h7@22/10:5:13:3:1c,xcd=3")])
 def test_4x4_split_run_schedule(dtype, cfg):
-    """The shipped 4x4 schedules: the middle group holds qubits 12-16 and
-    27-31, the top group 17-26 (":h5").  The same transforms grouped
-    differently round differently, so 6 Trotter steps of the 4x4 ramp are
-    compared with the planner's default schedule to the precision's
-    rounding on 2^20 sampled amplitudes, and the observables likewise."""
-    print(f"case 4x4 split-run schedule dtype={dtype}", flush=True)
+    """4x4 schedules whose strided groups are two runs of qubits (":h"):
+    the middle group 12-16 and 27-31 with the top group 17-26, or both
+    groups in two runs with register windows across them (middle 12-16 and
+    23-27, top 17-22 and 28-31; complex128: middle 12-14 and 22-28, top
+    15-21 and 29-31).  The same transforms grouped differently round
+    differently, so 6 Trotter steps of the 4x4 ramp are compared with the
+    planner's default schedule to the precision's rounding on 2^20 sampled
+    amplitudes, and the observables likewise."""
+    print(f"case 4x4 split-run schedule dtype={dtype} {cfg}", flush=True)
     plans = [z2h.z2h_plan_create(4, 4, dtype), z2h.z2h_plan_create_config(4, 4, dtype, cfg)]
     d = z2h.z2h_plan_describe(plans[1])
-    assert [(g["b0"], g["hi"]) for g in d["groups"]] == [(0, 0), (12, 5), (17, 0)] and d["groups"][1]["b1"] == 27
+    assert d["groups"][1]["hi"] > 0
     sz = z2h.z2h_plan_sizes(plans[0])
     ws = z2h.alloc_bytes(max(sz["ws_evolve"], sz["ws_observe"]))
     psi = z2h.alloc_state(plans[0])

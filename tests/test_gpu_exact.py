@@ -77,16 +77,20 @@ def test_hamiltonian_apply_full(Lx, Ly, dtype):
     assert torch.equal(x, x0)  # x is read only
 
 
-@pytest.mark.parametrize("Lx,Ly,dtype", [(3, 4, z2h.Z2H_C128), (3, 4, z2h.Z2H_C64), (4, 4, z2h.Z2H_C64),
-                                         (4, 4, z2h.Z2H_C128)])
-def test_hamiltonian_apply_sampled_rows(Lx, Ly, dtype):
-    """Three-group pass chains (3x4, 4x4): 4096 sampled rows, including the
+@pytest.mark.parametrize("Lx,Ly,dtype,cfg", [
+    (3, 4, z2h.Z2H_C128, None), (3, 4, z2h.Z2H_C64, None), (4, 4, z2h.Z2H_C64, None), (4, 4, z2h.Z2H_C128, None),
+    (2, 5, z2h.Z2H_C128, "split=4:2:8:0/10:5:13:3:1c:h3@17/6:3:9:3"),
+    (2, 5, z2h.Z2H_C64, "split=4:2:8:0/6:3:10:4:at8/10:5:14:4:1c"),
+    (4, 4, z2h.Z2H_C128, "split=12:4:12:0/10:5:13:3:1c:h7@22/10:5:13:3:1c,xcd=7")])
+def test_hamiltonian_apply_sampled_rows(Lx, Ly, dtype, cfg):
+    """Three-group pass chains (3x4, 4x4, and groups in two runs of qubits
+    with register windows across them): 4096 sampled rows, including the
     first and last index, against the row-by-row definition of H."""
     n = 2 * Lx * Ly
     c = (0.5, 0.8, 0.35, 0.2)
-    print(f"case H x sampled {Lx}x{Ly} dtype={dtype}", flush=True)
+    print(f"case H x sampled {Lx}x{Ly} dtype={dtype} {cfg}", flush=True)
     torch.cuda.empty_cache()
-    plan = z2h.z2h_plan_create(Lx, Ly, dtype)
+    plan = z2h.z2h_plan_create_config(Lx, Ly, dtype, cfg) if cfg else z2h.z2h_plan_create(Lx, Ly, dtype)
     assert len(z2h.z2h_plan_describe(plan)["groups"]) >= 2
     x = random_state_gpu(n, dtype, 11)
     y = z2h.alloc_state(plan)

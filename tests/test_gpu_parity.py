@@ -228,31 +228,26 @@ def test_component_exchange_bitwise(dtype, order):
     assert loss <= (1e-12 if dtype == C128 else 1e-5), loss
 
 
-@pytest.mark.parametrize("dtype,order", [(C128, 0), (C128, 1), (C64, 0)])
-def test_split_run_group(dtype, order):
-    """A middle group in two runs of qubits (":h3": qubits 8-10 and 15-17,
-    the last group then takes 11-14) against the oracle: the same
-    transform, only the tiles gather their rows differently."""
-    import torch
+@pytest.mark.parametrize("dtype,order,cfg", [(C128, 0, "split=4:2:8:0/10:5:13:3:1c:h3@17/6:3:9:3"),
+                                             (C64, 1, "split=4:2:8:0/10:5:14:4:1c:h3@17/6:3:10:4"),
+                                             (C128, 1, "split=4:2:8:0/6:3:9:3:at8/10:5:13:3:1c"),
+                                             (C64, 0, "split=4:2:8:0/6:3:10:4:at8/10:5:14:4:1c")])
+def test_split_run_group(dtype, order, cfg):
+    """2x5 torus (20 qubits) with a group in two runs of qubits, one of
+    whose register windows holds bits of both runs: the middle group
+    (qubits 4-10 and 17-19), or the last group (qubits 4-7 and 14-19, with
+    the x-basis phase and the x-basis observables on it).  State and
+    observables against the oracle."""
     c1 = (1.0, 0.8, 0.35, 0.25)
-    M, dt = 30, 0.05
-    cfg = "split=8:4:12:0/6:3:10:4:h3/4:2:8:4"
-    print(f"case 3x3 {cfg} dtype={dtype} order={order}", flush=True)
-    plan = z2h.z2h_plan_create_config(3, 3, dtype, cfg)
-    assert [g["hi"] for g in z2h.z2h_plan_describe(plan)["groups"]] == [0, 3, 0]
-    sizes = z2h.z2h_plan_sizes(plan)
-    psi = z2h.alloc_state(plan)
-    ws = z2h.alloc_bytes(sizes["ws_evolve"] + 16 * M + 1024)
-    z2h.z2h_state_init(plan, psi, z2h.Z2H_INIT_PSI1)
-    z2h.z2h_evolve(plan, psi, ws, z2h.schedule(TC, c1, M, dt, renorm=1 if dtype == C64 else 0, order=order))
-    torch.cuda.synchronize()
-    got = to_oracle_order(3, 3, psi.cpu().numpy().astype(np.complex128))
+    M, dt = 12, 0.1
+    print(f"case 2x5 {cfg} dtype={dtype} order={order}", flush=True)
+    plan = z2h.z2h_plan_create_config(2, 5, dtype, cfg)
+    assert any(g["hi"] for g in z2h.z2h_plan_describe(plan)["groups"])
     z2h.z2h_plan_destroy(plan)
-    o = _oracle(("3x3-split", order), lambda: oracle_run(3, 3, TC, c1, M, dt, order=order))
-    loss = fidelity_loss(o, got)
-    assert loss <= (1e-12 if dtype == C128 else 1e-5), loss
-    if dtype == C128:
-        assert np.max(np.abs(got - o)) <= 1e-10
+    g_psi, g_obs, _ = gpu_run(2, 5, dtype, TC, c1, M, dt, config=cfg, order=order,
+                              renorm=1 if dtype == C64 else 0)
+    o = _oracle(("2x5-split", order), lambda: oracle_run(2, 5, TC, c1, M, dt, order=order))
+    _check(2, 5, dtype, g_psi, g_obs, o, c1)
 
 
 @pytest.mark.parametrize("dtype,M,order", [(C64, 600, 1), (C128, 530, 0)])

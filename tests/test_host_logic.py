@@ -205,19 +205,41 @@ def test_split_run_groups():
     assert gbit(g1, 4) == 12 and gbit(g1, 8) == 16 and gbit(g1, 9) == 27 and gbit(g1, 13) == 31
     check_geometry(z2h.z2h_plan_create_config(4, 4, z2h.Z2H_C64, cfg))
     check_geometry(z2h.z2h_plan_create_config(4, 4, z2h.Z2H_C128, "split=12:4:12:0/10:5:13:3:1c:h5/10:5:13:3:1c"))
-    # small enough for the exhaustive tile-coverage check (n = 18)
-    small = z2h.z2h_plan_create_config(3, 3, z2h.Z2H_C64, "split=8:4:12:0/6:3:10:4:h3/4:2:8:4")
-    ds = z2h.z2h_plan_describe(small)
-    assert [(g["b0"], g["hi"], g["b1"] if g["hi"] else None) for g in ds["groups"]] == [
-        (0, 0, None), (8, 3, 15), (11, 0, None)]
-    check_geometry(small)
-    for bad in ("split=12:4:12:0:h4/10:5:14:4/10:5:14:4",       # group 0 cannot split
-                "split=12:4:12:0/10:5:14:4:h3/10:5:14:4",         # run not a whole window
-                "split=12:4:12:0/10:5:14:4:h10/10:5:14:4",        # high run as wide as the group
-                "split=12:4:12:0/10:5:14:4:h5/10:5:14:4/5:5:9:4",  # covers more than n bits
+    # explicit run positions; the last group takes the free qubits, here in two runs
+    for dt, cfg, want in (
+            (z2h.Z2H_C64, "split=12:4:12:0/10:5:14:4:1c:h5@23/10:5:14:4:1c", [(12, 5, 23), (17, 4, 28)]),
+            (z2h.Z2H_C128, "split=12:4:12:0/10:5:13:3:1c:h7@22/10:5:13:3:1c", [(12, 7, 22), (15, 3, 29)]),
+            (z2h.Z2H_C64, "split=12:4:12:0/10:5:14:4:1c:at17:h4@28/10:5:14:4:1c", [(17, 4, 28), (12, 5, 23)])):
+        plan = z2h.z2h_plan_create_config(4, 4, dt, cfg)
+        gs = z2h.z2h_plan_describe(plan)["groups"]
+        assert [(g["b0"], g["hi"], g["b1"]) for g in gs[1:]] == want, cfg
+        check_geometry(plan)
+    # small enough for the exhaustive tile-coverage check (n = 20): a window
+    # across the two runs in the middle group, and in the last (phase) group
+    for dt, cfg, j, want in ((z2h.Z2H_C64, "split=4:2:8:0/10:5:14:4:1c:h3@17/6:3:10:4", 1, (4, 3, 17)),
+                             (z2h.Z2H_C128, "split=4:2:8:0/10:5:13:3:1c:h3@17/6:3:9:3", 1, (4, 3, 17)),
+                             (z2h.Z2H_C64, "split=4:2:8:0/6:3:10:4:at8/10:5:14:4:1c", 2, (4, 6, 14)),
+                             (z2h.Z2H_C128, "split=4:2:8:0/6:3:9:3:at8/10:5:13:3:1c", 2, (4, 6, 14))):
+        if True:
+            small = z2h.z2h_plan_create_config(2, 5, dt, cfg)
+            gj = z2h.z2h_plan_describe(small)["groups"][j]
+            assert (gj["b0"], gj["hi"], gj["b1"]) == want
+            check_geometry(small)
+    for bad in ("split=12:4:12:0:h4/10:5:14:4/10:5:14:4",         # group 0 cannot split
+                "split=12:4:12:0/10:5:14:4:h3/10:5:14:4",           # two runs without :1c
+                "split=12:4:12:0/10:5:14:4:h5/10:5:14:4",           # two runs without :1c
+                "split=12:4:12:0/10:5:14:4:h10/10:5:14:4",          # high run as wide as the group
+                "split=12:4:12:0/10:5:14:4:h5/10:5:14:4/5:5:9:4",   # covers more than n bits
+                "split=12:4:12:0/10:5:14:4:1c:h5@14/10:5:14:4:1c",  # runs overlap
+                "split=12:4:12:0/10:5:14:4:1c:at10/10:5:14:4:1c",   # qubits of group 0
+                "split=12:4:12:0/10:5:14:4:1c:h5@30/10:5:14:4:1c",  # past the last qubit
                 "split=12:4:12:0/10:5:14:4:hx/10:5:14:4"):
         with pytest.raises(z2h.Z2HError):
             z2h.z2h_plan_create_config(4, 4, z2h.Z2H_C64, bad)
+    # complex128 tiles of 2^14 amplitudes: the passes fit (component
+    # exchange), the observables' whole-element transform does not
+    with pytest.raises(z2h.Z2HError):
+        z2h.z2h_plan_create_config(2, 5, z2h.Z2H_C128, "split=4:2:8:0/10:5:14:4:1c:h3@17/6:3:10:4")
 
 
 def check_full_lds(g, n, esize):
@@ -285,8 +307,10 @@ def check_geometry(plan):
         tilebits = set(tile_positions(g, n))
         assert not (local & tilebits) and (local | tilebits) == set(range(n))
         if hr:
-            # every register window lies inside one run
-            assert g["full"] and hr % R == 0 and g["b1"] >= b0 + m - c - hr
+            # two separate runs; a window across them only in component-exchange groups
+            assert g["full"] and g["b1"] > b0 + m - c - hr
+            if any(p < m - hr < p + R for p in g["p"]):
+                assert g["cx"] == 1
         covered += [gbit(g, x) for x in range(x0, x1)]
         # layouts: windows of R local bits inside the transform range, never
         # straddling the carried boundary; butterflies cover [x0, x1) once
@@ -294,7 +318,6 @@ def check_geometry(plan):
         for p, lo, hi in zip(g["p"], g["blo"], g["bhi"]):
             assert x0 <= p and p + R <= m
             assert p >= c or p + R <= c
-            assert hr == 0 or p >= m - hr or p + R <= m - hr
             bits = set(range(p + lo, p + hi))
             assert bits <= set(range(x0, x1)) and not (bits & done)
             done |= bits
@@ -307,12 +330,19 @@ def check_geometry(plan):
             assert np.array_equal(np.sort(e), np.arange(1 << m))
             slot = e + (e >> R)
             assert slot.max() < (1 << m) + (1 << (m - R))
+            # register bits as the kernels place them: [gs, gs + nlo), then
+            # (a window across the two runs of a split group) [b1, ...)
             gs = gbit(g, p)
-            # register element q is at global index i0 + (q << gs)
-            for q in (1, (1 << R) - 1):
+            xb = m - hr
+            nlo = xb - p if hr and p < xb < p + R else R
+            P = [gs + r if r < nlo else g["b1"] + r - nlo for r in range(R)]
+            assert P == [gbit(g, p + r) for r in range(R)]
+            # register element q is at global index i0 + reg_off(q)
+            for q in (1, (1 << R) - 1, (1 << R) // 2 + 1):
+                off = sum(1 << P[r] for r in range(R) if q >> r & 1)
                 for tile in (0, (1 << g["tiles_log2"]) - 1):
                     i_direct = glob(g, tile, lay_base(p, t, R) | (q << p))
-                    i_split = glob(g, tile, lay_base(p, t, R)) + (q << gs)
+                    i_split = glob(g, tile, lay_base(p, t, R)) + off
                     assert np.array_equal(i_direct, i_split)
                     assert i_direct.max() < (1 << n)
         if g["full"] and K > 1:
@@ -327,10 +357,11 @@ def check_geometry(plan):
             e = np.arange(1 << m)
             for u in (0, (1 << (g["tiles_log2"] - 1)) - 1):
                 assert np.array_equal(glob(g, 2 * u + 1, e) - glob(g, 2 * u, e), np.full(e.size, step))
-        if n <= 18:
+        if n <= 20:
             # all tiles together cover the state exactly once
             e = np.arange(1 << m)
-            allidx = np.concatenate([glob(g, tile, e) for tile in range(1 << g["tiles_log2"])])
+            tiles = np.arange(1 << g["tiles_log2"])
+            allidx = (glob(g, tiles, 0, n)[:, None] | glob(g, 0, e, n)[None, :]).ravel()
             assert np.array_equal(np.sort(allidx), np.arange(1 << n))
     assert sorted(covered) == list(range(n))
     # phase table: index popc(syndrome) * (n + 1) + w stays below (nst + 1)(n + 1)
