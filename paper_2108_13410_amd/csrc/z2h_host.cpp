@@ -494,6 +494,7 @@ static void plan_base(int Lx, int Ly, bool c128, Plan &P) {
     // contiguous range of the state, measured faster on every lattice; the
     // strided groups keep the hardware order, which measured faster for them
     P.xcd = 1;
+    P.tables = 1;
 }
 
 // A schedule configuration string: "split=G:R:m:c/G:R:m:c/..." (groups from
@@ -512,6 +513,7 @@ static z2h_status plan_from_config(Plan &P, const char *cfg, int m_pref, int m_h
     const char *q;
     if ((q = strstr(cfg, "nt=")) && sscanf(q, "nt=%d", &v) == 1) P.nt = v ? 1 : 0;
     if ((q = strstr(cfg, "xcd=")) && sscanf(q, "xcd=%d", &v) == 1) P.xcd = v & ((1 << kMaxGroups) - 1);
+    if ((q = strstr(cfg, "tables=")) && sscanf(q, "tables=%d", &v) == 1) P.tables = v ? 1 : 0;
     if ((q = strstr(cfg, "split="))) {
         GroupChoice ch[kMaxGroups];
         int K = 0;
@@ -1202,14 +1204,12 @@ size_t norm_parts(const Plan &P) {
 
 // Phase tables of kTabChunk levels, after everything else in the evolve
 // workspace, for multi-group plans whose phase passes run full-window
-// kernels on a cache-resident state (at most 64 MiB).  Such passes are
-// latency-bound and copying a ready table beats building it; on a large
-// state every one of its many workgroups would copy the whole table
-// (measured slower at 4x4: 9 GB of extra cache traffic per complex128 pass).
-constexpr size_t kTablesMaxState = (size_t)64 << 20;
-
+// kernels (",tables=0" in a schedule string turns them off).  The phase
+// kernels fetch their block's share of a ready table ahead of the tile
+// loads instead of computing sines and cosines in FP64 while the tile is
+// in flight.
 static bool tables_apply(const Plan &P) {
-    return P.K > 1 && P.geom[0].full && P.geom[P.K - 1].full && (P.esize << P.n) <= kTablesMaxState;
+    return P.tables && P.K > 1 && P.geom[0].full && P.geom[P.K - 1].full;
 }
 
 size_t ws_tables_size(const Plan &P) {
@@ -1335,7 +1335,8 @@ z2h_status z2h_plan_describe(const z2h_plan *plan, char *buf, size_t len) {
     const Plan &P = plan->P;
     std::string s = "{\"n\": " + std::to_string(P.n) + ", \"R\": " + std::to_string(P.geom[0].R) +
                     ", \"K\": " + std::to_string(P.K) + ", \"c128\": " + (P.c128 ? "1" : "0") + ", \"nt\": " + std::to_string(P.nt) +
-                    ", \"xcd\": " + std::to_string(P.xcd) + ", \"groups\": [";
+                    ", \"xcd\": " + std::to_string(P.xcd) + ", \"tables\": " + std::to_string(P.tables) +
+                    ", \"groups\": [";
     for (int j = 0; j < P.K; ++j) {
         const GroupGeom &g = P.geom[j];
         s += j ? ", " : "";

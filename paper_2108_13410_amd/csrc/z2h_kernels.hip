@@ -528,7 +528,7 @@ template <typename Real, int R, int NL, int KIND, int NT, int CX = 0, bool TAB =
 __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, const LevelOp &op, int jrec,
                                            uint64_t tile0, uint32_t t, Cx<Real> (&v)[NT][1 << R],
                                            Cx<Real> *st, const LayCtx<R> (&L0)[NT], Cx<Real> *lds,
-                                           Cx<Real> *tab, double2 *fac, double *red) {
+                                           Cx<Real> *tab, double2 *fac, double *red, int tab_done = 0) {
     const GroupGeom &g = a.geom;
     const int x1 = g.x1;
     const int p0 = x1 - R, pl = x1 - R * NL;
@@ -555,7 +555,8 @@ __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, 
                              (size_t)(a.jidx ? job_index(a.jidx, jrec) : jrec) * a.tab_stride) +
                           (size_t)(a.level - J.lev0) * entries
                     : (GTab)a.tabs + (size_t)(a.level - a.tab_lev0) * entries;
-            for (int j = (int)t; j < entries; j += blockDim.x) {
+            // (entries below tab_done were prefetched by the block)
+            for (int j = tab_done + (int)t; j < entries; j += blockDim.x) {
                 const V w = src[j];
                 tab[j] = Cx<Real>{w.x, w.y};
             }
@@ -633,6 +634,14 @@ __device__ __forceinline__ void pass_multi(const LevelArgs &a, const JobDev &J, 
 // record is read.
 constexpr int kAnyKind = -1;
 
+// KS kPhaseTab: every job of the launch has a phase pass (kPhaseB) and the
+// level's table was precomputed for a single state (a.tabs, no per-job
+// stride).  The block loads its share of the table before its tile loads,
+// so the table's arrival does not wait behind the tile's, and writes it to
+// LDS once the tile loads are in flight.
+constexpr int kPhaseTab = 8;
+constexpr int kTabPre = 3;  // table entries prefetched per thread
+
 // NT: consecutive tiles per block (1, or 2 for strided groups whose tiles
 // carry 128-byte rows: the two tiles of a block differ only in the lowest
 // tile bit, so each block reads and writes 256 contiguous bytes per row).
@@ -658,6 +667,19 @@ __device__ __forceinline__ void level_body(const LevelArgs &a) {
     // record (scalar loads) gives the state's offset first, and a block whose
     // job has no pass at this level returns before loading.
     Cx<Real> *st = base + a.jbase + (uint64_t)jb * a.jstride;
+    constexpr bool TP = KS == kPhaseTab;
+    typedef typename Vec2<Real>::type TV;
+    TV pre[TP ? kTabPre : 1];
+    const int entries = (a.lat.nst + 1) * (a.lat.n + 1);
+    if constexpr (TP) {
+        typedef const __attribute__((address_space(1))) TV *GTab;
+        const GTab src = (GTab)a.tabs + (size_t)(a.level - a.tab_lev0) * entries;
+#pragma unroll
+        for (int i = 0; i < kTabPre; ++i) {
+            const int j = (int)t + i * (int)blockDim.x;
+            if (j < entries) pre[i] = src[j];
+        }
+    }
     JobDev J;
     LevelOp op;
     const bool early = a.jmode != 0;
@@ -684,7 +706,16 @@ __device__ __forceinline__ void level_body(const LevelArgs &a) {
     double2 *fac = table_scratch(smem);
     double *red = align16<double>(tab + (a.lat.nst + 1) * W);
 
-    if constexpr (KS != kAnyKind) {
+    if constexpr (TP) {
+#pragma unroll
+        for (int i = 0; i < kTabPre; ++i) {
+            const int j = (int)t + i * (int)blockDim.x;
+            if (j < entries) tab[j] = Cx<Real>{pre[i].x, pre[i].y};
+        }
+        const int done = kTabPre * (int)blockDim.x;
+        pass_multi<Real, R, NL, kPhaseB, NT, CX, true>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red,
+                                                        done < entries ? done : entries);
+    } else if constexpr (KS != kAnyKind) {
         pass_multi<Real, R, NL, KS, NT, CX>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red);
     } else {
         switch (op.kind) {
@@ -1172,8 +1203,10 @@ static hipError_t do_level_full_ks(const LevelArgs &a, dim3 grid, size_t lds, hi
 
 template <typename Real, int R, int NL, int NT>
 static hipError_t do_level_full_nt(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
-    // precomputed tables are read by the any-kind kernels only
+    // precomputed tables: one state's tables are prefetched by the phase
+    // kernels compiled for them; per-job tables are read by the any-kind kernels
     if (a.kind_hint == kPhaseB && !a.tabs) return do_level_full_ks<Real, R, NL, kPhaseB, NT>(a, grid, lds, s);
+    if (a.kind_hint == kPhaseB && !a.tab_stride) return do_level_full_ks<Real, R, NL, kPhaseTab, NT>(a, grid, lds, s);
     if (a.kind_hint == kPlainH) return do_level_full_ks<Real, R, NL, kPlainH, NT>(a, grid, lds, s);
     return do_level_full_ks<Real, R, NL, kAnyKind, NT>(a, grid, lds, s);
 }
@@ -1199,7 +1232,7 @@ static hipError_t do_level_full(const LevelArgs &a, dim3 grid, size_t lds, hipSt
     if (a.geom.cx) {
 #define Z2H_CX_CALL(r, nl)                                                                               \
         if (R == r && NL == nl) {                                                                        \
-            if (a.kind_hint == kPhaseB && !a.tabs) return do_level_cx_ks<Real, r, nl, kPhaseB>(a, grid, lds, s); \
+            if (a.kind_hint == kPhaseB && (!a.tabs || !a.tab_stride)) return do_level_cx_ks<Real, r, nl, kPhaseB>(a, grid, lds, s); \
             if (a.kind_hint == kPlainH) return do_level_cx_ks<Real, r, nl, kPlainH>(a, grid, lds, s);    \
             return do_level_cx_ks<Real, r, nl, kAnyKind>(a, grid, lds, s);                               \
         }
@@ -1331,6 +1364,7 @@ static hipError_t prep_real() {
 #define Z2H_PREP_FULL(r, nl) \
     if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kAnyKind, 1>), kMaxLdsBytes); \
     if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kPhaseB, 1>), kMaxLdsBytes); \
+    if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kPhaseTab, 1>), kMaxLdsBytes); \
     if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kPlainH, 1>), kMaxLdsBytes);
     Z2H_FULL_LEVEL_SHAPES(Z2H_PREP_FULL)
 #undef Z2H_PREP_FULL
@@ -1338,6 +1372,7 @@ static hipError_t prep_real() {
 #define Z2H_PREP_PAIR(r, nl) \
         if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kAnyKind, 2>), kMaxLdsBytes); \
         if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kPhaseB, 2>), kMaxLdsBytes); \
+        if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kPhaseTab, 2>), kMaxLdsBytes); \
         if (e == hipSuccess) e = set_lds(reinterpret_cast<const void *>(&level_kernel_full<Real, r, nl, kPlainH, 2>), kMaxLdsBytes);
         Z2H_PAIR_SHAPES(Z2H_PREP_PAIR)
 #undef Z2H_PREP_PAIR

@@ -26,6 +26,7 @@ struct Plan {
     int device;
     int nt;                      // streaming loads/stores in the pass kernels
     int xcd;                     // bit j: XCD-major block order in the passes over group j
+    int tables;                  // phase tables precomputed per evolve call (0: built per workgroup)
 };
 
 namespace rt {

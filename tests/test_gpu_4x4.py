@@ -250,6 +250,38 @@ def test_4x4_split_run_schedule(dtype, cfg):
         assert abs(obs[0][key] - obs[1][key]) <= tol * max(1.0, abs(obs[0][key])), key
 
 
+@pytest.mark.parametrize("dtype,cfg", [
+    (z2h.Z2H_C64, "split=12:4:12:0/10:5:14:4:1c:h5@23/10:5:14:4:1c,xcd=7"),
+    (z2h.Z2H_C128, "split=12:4:12:0/10:5:13:3:1c:h7@22/10:5:13:3:1c,xcd=7")])
+def test_4x4_precomputed_tables_bitwise(dtype, cfg):
+    """Phase tables computed ahead of the passes (fetched by each block
+    before its tile) and tables built by every workgroup (",tables=0") give
+    the same bits: 6 Trotter steps of the 4x4 ramp, 2^20 sampled amplitudes
+    and the per-step norms."""
+    print(f"case 4x4 precomputed tables dtype={dtype}", flush=True)
+    plans = [z2h.z2h_plan_create_config(4, 4, dtype, cfg), z2h.z2h_plan_create_config(4, 4, dtype, cfg + ",tables=0")]
+    assert [z2h.z2h_plan_describe(p)["tables"] for p in plans] == [1, 0]
+    sz = [z2h.z2h_plan_sizes(p) for p in plans]
+    assert sz[0]["ws_evolve"] > sz[1]["ws_evolve"]
+    ws = z2h.alloc_bytes(sz[0]["ws_evolve"])
+    psi = z2h.alloc_state(plans[0])
+    job = workloads.point_4x4()
+    rng = np.random.default_rng(17)
+    idx = torch.tensor(rng.integers(0, 1 << 32, 1 << 20), dtype=torch.int64, device="cuda")
+    samples, norms = [], []
+    for plan in plans:
+        nrm = torch.zeros(6, dtype=torch.float64, device="cuda")
+        z2h.z2h_state_init(plan, psi, z2h.Z2H_INIT_PSI1)
+        z2h.z2h_evolve(plan, psi, ws, z2h.schedule(job["c0"], job["c1"], job["M"], job["T"] / job["M"], k_end=6,
+                                                   renorm=1 if dtype == z2h.Z2H_C64 else 0), norms=nrm)
+        samples.append(torch.view_as_real(psi[idx]).cpu())
+        norms.append(nrm.cpu())
+    del psi, ws
+    torch.cuda.empty_cache()
+    assert torch.equal(samples[0], samples[1])
+    assert torch.equal(norms[0], norms[1])
+
+
 def _plaquette_codewords():
     """The 2^15 sums (XOR) of plaquette masks of the 4x4 torus (library
     numbering): 15 of the 16 plaquettes are independent, the product of all
