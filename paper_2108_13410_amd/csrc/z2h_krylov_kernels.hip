@@ -76,7 +76,7 @@ struct Chunk {
 
 // v += D_Z x for the register elements of layout L (computational basis),
 // accumulating Re(conj(x) v) of the result.
-template <typename Real, int R>
+template <typename Real, int R, bool SP>
 __device__ __forceinline__ void add_diag_z(Cx<Real> (&v)[1 << R], const Cx<Real> *x, const LayCtx<R> &L,
                                            const LatticeDev &lat, double J, double h, double &acc) {
     constexpr int C = Chunk<R>::C;
@@ -88,7 +88,7 @@ __device__ __forceinline__ void add_diag_z(Cx<Real> (&v)[1 << R], const Cx<Real>
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             const int q = (c0 + i) ^ ((c0 + i) >> 1);
-            xv[i] = b[reg_off<R, true>(L, q)];
+            xv[i] = b[reg_off<R, SP>(L, q)];
         }
 #pragma unroll
         for (int i = 0; i < C; ++i) {
@@ -106,7 +106,7 @@ __device__ __forceinline__ void add_diag_z(Cx<Real> (&v)[1 << R], const Cx<Real>
 // Lanczos form of the last pass: with v = (2^-n W D_X W u) at the register
 // positions of layout L, write w = sig (v + D_Z u - alpha u) - cp p and
 // accumulate |w|^2.
-template <typename Real, int R>
+template <typename Real, int R, bool SP>
 __device__ __forceinline__ void lanczos_out(const Cx<Real> (&v)[1 << R], const Cx<Real> *u, const Cx<Real> *p,
                                             Cx<Real> *w, const LayCtx<R> &L, const LatticeDev &lat, double J,
                                             double h, double sig, double alpha, double cp, bool use_prev,
@@ -123,8 +123,8 @@ __device__ __forceinline__ void lanczos_out(const Cx<Real> (&v)[1 << R], const C
 #pragma unroll
         for (int i = 0; i < C; ++i) {
             const int q = (c0 + i) ^ ((c0 + i) >> 1);
-            uv[i] = bu[reg_off<R, true>(L, q)];
-            pv[i] = use_prev ? bp[reg_off<R, true>(L, q)] : Cx<Real>{(Real)0, (Real)0};
+            uv[i] = bu[reg_off<R, SP>(L, q)];
+            pv[i] = use_prev ? bp[reg_off<R, SP>(L, q)] : Cx<Real>{(Real)0, (Real)0};
         }
 #pragma unroll
         for (int i = 0; i < C; ++i) {
@@ -132,7 +132,7 @@ __device__ __forceinline__ void lanczos_out(const Cx<Real> (&v)[1 << R], const C
             if (idx) s ^= L.lz[__builtin_ctz(idx)];
             const Real d = (Real)(diag_value(lat.nst, lat.n, s, L.w0 + __builtin_popcount(q), J, h) - alpha);
             Cx<Real> r{rs * (v[q].x + d * uv[i].x) - rc * pv[i].x, rs * (v[q].y + d * uv[i].y) - rc * pv[i].y};
-            bw[reg_off<R, true>(L, q)] = r;
+            bw[reg_off<R, SP>(L, q)] = r;
             acc += (double)r.x * (double)r.x + (double)r.y * (double)r.y;
         }
         __builtin_amdgcn_sched_barrier(0);
@@ -141,7 +141,7 @@ __device__ __forceinline__ void lanczos_out(const Cx<Real> (&v)[1 << R], const C
 
 // PF: the next tile's elements are loaded while the current one is
 // transformed (two register tiles; used where they fit without spilling).
-template <typename Real, int R, bool PF>
+template <typename Real, int R, bool PF, bool SP>
 __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const GroupGeom &g = a.geom;
@@ -177,8 +177,8 @@ __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
     LayCtx<R> Ln;
     if constexpr (PF) {
         if (tile < tiles) {
-            lay_ctx<R, true>(Ln, g, a.lat, tile, g.p[0], t, syn0);
-            load_tile<Real, R, false, true>(vn, src, Ln);
+            lay_ctx<R, SP>(Ln, g, a.lat, tile, g.p[0], t, syn0);
+            load_tile<Real, R, false, SP>(vn, src, Ln);
         }
     }
     for (; tile < tiles; tile += gridDim.x) {
@@ -190,12 +190,12 @@ __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
             for (int q = 0; q < (1 << R); ++q) v[q] = vn[q];
             const uint64_t nt = tile + gridDim.x;
             if (nt < tiles) {
-                lay_ctx<R, true>(Ln, g, a.lat, nt, g.p[0], t, syn0);
-                load_tile<Real, R, false, true>(vn, src, Ln);
+                lay_ctx<R, SP>(Ln, g, a.lat, nt, g.p[0], t, syn0);
+                load_tile<Real, R, false, SP>(vn, src, Ln);
             }
         } else {
-            lay_ctx<R, true>(L0, g, a.lat, tile, g.p[0], t, syn0);
-            load_tile<Real, R, false, true>(v, src, L0);
+            lay_ctx<R, SP>(L0, g, a.lat, tile, g.p[0], t, syn0);
+            load_tile<Real, R, false, SP>(v, src, L0);
         }
         if (a.part_z) accz += diag_norm_z<Real, R>(v, L0, a.lat, a.JB, a.hz);
         int cur = 0;
@@ -206,7 +206,7 @@ __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
         }
         if (a.top) {
             LayCtx<R> Lm;
-            lay_ctx<R, true>(Lm, g, a.lat, tile, g.p[cur], t, true);
+            lay_ctx<R, SP>(Lm, g, a.lat, tile, g.p[cur], t, true);
             mul_diag_x<Real, R>(v, Lm, a.lat, a.JA, a.hx, a.xscale, a.part_x ? &accx : nullptr);
             for (int j = g.nlay - 1; j >= 0; --j) {
                 if (j != cur) {
@@ -218,12 +218,12 @@ __global__ void __launch_bounds__(512) ham_kernel(HamArgs a) {
         }
         if (cur != 0) exchange<Real, R>(v, lds, g.p[cur], g.p[0], t);
         if (lz) {
-            lanczos_out<Real, R>(v, x, reinterpret_cast<const Cx<Real> *>(a.p), reinterpret_cast<Cx<Real> *>(a.w),
+            lanczos_out<Real, R, SP>(v, x, reinterpret_cast<const Cx<Real> *>(a.p), reinterpret_cast<Cx<Real> *>(a.w),
                                  L0, a.lat, a.JB, a.hz, sig, alpha, cp, a.use_prev != 0, acc);
             continue;
         }
-        if (a.final_pass) add_diag_z<Real, R>(v, x, L0, a.lat, a.JB, a.hz, acc);
-        store_tile<Real, R, false, true>(v, dst, L0);
+        if (a.final_pass) add_diag_z<Real, R, SP>(v, x, L0, a.lat, a.JB, a.hz, acc);
+        store_tile<Real, R, false, SP>(v, dst, L0);
     }
     if (a.part) {
         const double s = block_sum(acc, red);
@@ -378,12 +378,12 @@ static hipError_t allow_lds(const void *fn, size_t lds) {
     return e;
 }
 
-template <typename Real, int R, bool PF>
+template <typename Real, int R, bool PF, bool SP>
 static hipError_t do_ham_pf(const HamArgs &a, unsigned workers, size_t lds, hipStream_t s) {
-    const void *fn = reinterpret_cast<const void *>(&ham_kernel<Real, R, PF>);
+    const void *fn = reinterpret_cast<const void *>(&ham_kernel<Real, R, PF, SP>);
     hipError_t e = allow_lds(fn, lds);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((ham_kernel<Real, R, PF>), dim3(workers), dim3(1u << (a.geom.m - R)), lds, s, a);
+    hipLaunchKernelGGL((ham_kernel<Real, R, PF, SP>), dim3(workers), dim3(1u << (a.geom.m - R)), lds, s, a);
     return hipGetLastError();
 }
 
@@ -394,7 +394,9 @@ template <typename Real, int R>
 static hipError_t do_ham(const HamArgs &a, unsigned workers, size_t lds, hipStream_t s) {
     if (a.geom.m - R < 6 || a.geom.m - R > 9) return hipErrorInvalidConfiguration;  // launch bounds
     constexpr bool pf = (2 * sizeof(Real) << R) <= 256 && !(sizeof(Real) == 4 && R == 5);
-    return do_ham_pf<Real, R, pf>(a, workers, lds, s);
+    // groups in two runs of qubits take the kernel with their address map
+    if (a.geom.hi) return do_ham_pf<Real, R, pf, true>(a, workers, lds, s);
+    return do_ham_pf<Real, R, pf, false>(a, workers, lds, s);
 }
 
 hipError_t launch_ham(bool c128, int R, const HamArgs &a, unsigned workers, size_t lds, hipStream_t s) {
