@@ -213,14 +213,15 @@ def test_4x4_two_tile_schedule_bitwise():
 @pytest.mark.parametrize("dtype,cfg", [
     (z2h.Z2H_C64, "split=12:4:12:0/10:5:14:4:1c:h5/10:5:14:4:1c,xcd=1"),
     (z2h.Z2H_C64, "split=12:4:12:0/10:5:14:4:1c:h5@23/10:5:14:4:1c,xcd=1"),
+    (z2h.Z2H_C64, "split=12:4:12:0/10:5:14:4:1c:h5@24/10:5:14:4:1c,xcd=7"),
     (z2h.Z2H_C128, "split=12:4:12:0/10:5:13:3:1c:h5/10:5:13:3:1c,xcd=3"),
     (z2h.Z2H_C128, "split=12:4:12:0/10:5:13:3:1c:h7@22/10:5:13:3:1c,xcd=3")])
 def test_4x4_split_run_schedule(dtype, cfg):
     """4x4 schedules whose strided groups are two runs of qubits (":h"):
     the middle group 12-16 and 27-31 with the top group 17-26, or both
     groups in two runs with register windows across them (middle 12-16 and
-    23-27, top 17-22 and 28-31; complex128: middle 12-14 and 22-28, top
-    15-21 and 29-31).  The same transforms grouped differently round
+    23-27, top 17-22 and 28-31; middle 12-16 and 24-28, top 17-23 and 29-31;
+    complex128: middle 12-14 and 22-28, top 15-21 and 29-31).  The same transforms grouped differently round
     differently, so 6 Trotter steps of the 4x4 ramp are compared with the
     planner's default schedule to the precision's rounding on 2^20 sampled
     amplitudes, and the observables likewise."""
@@ -251,7 +252,7 @@ def test_4x4_split_run_schedule(dtype, cfg):
 
 
 @pytest.mark.parametrize("dtype,cfg", [
-    (z2h.Z2H_C64, "split=12:4:12:0/10:5:14:4:1c:h5@23/10:5:14:4:1c,xcd=7"),
+    (z2h.Z2H_C64, "split=12:4:12:0/10:5:14:4:1c:h5@24/10:5:14:4:1c,xcd=7"),
     (z2h.Z2H_C128, "split=12:4:12:0/10:5:13:3:1c:h7@22/10:5:13:3:1c,xcd=7")])
 def test_4x4_precomputed_tables_bitwise(dtype, cfg):
     """Phase tables computed ahead of the passes (fetched by each block
