@@ -47,7 +47,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_scan_3x3_c64.json")
 SHIPPED_TABLE = os.path.join(ROOT, "paper_2108_13410_amd", "tuned_mi355x.txt")
 # sources the scan's pass kernels are compiled from (the traffic record is
 # keyed by their hash)
-EXACT_4X4_SPLIT = "split=12:4:12:0/10:4:13:3/10:4:13:3,xcd=7"
+EXACT_4X4_SPLIT = "split=12:4:12:0/10:4:13:3:h7@22/10:4:13:3,xcd=7"
 KERNEL_SRCS = [os.path.join(ROOT, "paper_2108_13410_amd", "csrc", f)
                for f in ("z2h_kernels.hip", "z2h_tile.h", "z2h_kernels.h", "z2h_internal.h")]
 
@@ -531,9 +531,9 @@ def exact_leg(z2h, torch):
     torch.cuda.empty_cache()
     out = {}
     c = (0.5, 0.5, 0.5, 0.0)
-    # H x makes 2K - 1 passes over K transform groups: the planner's
-    # three-group split (12 + 10 + 10 links), not a Trotter-tuned schedule
-    # with more groups
+    # H x makes 2K - 1 passes over K transform groups: a three-group split
+    # (12 + 10 + 10 links, the strided groups in two runs of qubits: 12-14 +
+    # 22-28 and 15-21 + 29-31), not a Trotter-tuned schedule with more groups
     plan = z2h.z2h_plan_create_config(4, 4, z2h.Z2H_C128, EXACT_4X4_SPLIT)
     K = len(z2h.z2h_plan_describe(plan)["groups"])
     V = 16 << 32

@@ -418,13 +418,15 @@ static z2h_status apply_split(Plan &P, const GroupChoice *ch, int K) {
         plan_layouts(g, false);
         if (hi && b1 == b0 + ga) hi = 0;  // the two runs meet: one run
         if (hi) {
-            // two separate runs: only the component-exchange pass kernels
-            // (and the observables, adjoint and Hamiltonian passes) are
-            // compiled for them, including windows across the two runs
+            // two separate runs: the general pass kernel (groups that are
+            // not whole windows), the component-exchange pass kernels, the
+            // observables, the adjoint and the Hamiltonian passes are
+            // compiled for them, including windows across the two runs; the
+            // other straight-line pass kernels are not
             g.hi = hi;
             g.b1 = b1;
-            if (!g.full || !ch[j].cx)
-                return fail(Z2H_ERR_INVALID, "group %d: a group in two runs needs whole windows and ':1c'", j);
+            if (g.full && !ch[j].cx)
+                return fail(Z2H_ERR_INVALID, "group %d: a group of whole windows in two runs needs ':1c'", j);
         }
         if ((ch[j].np != 1 && ch[j].np != 2) || (ch[j].cx && ch[j].np != 1))
             return fail(Z2H_ERR_INVALID, "group %d: bad tiles-per-block option", j);

@@ -250,7 +250,7 @@ __host__ __device__ inline LevelOp level_op(int lev, int K, int S, int k0, int o
 
 // ---------------------------------------------------------------- level kernel
 
-template <typename Real, int R, bool NT>
+template <typename Real, int R, bool NT, bool SP = false>
 __global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
     extern __shared__ __attribute__((aligned(16))) unsigned char smem[];
     const GroupGeom &g = a.geom;
@@ -294,8 +294,8 @@ __global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
     Cx<Real> *st = reinterpret_cast<Cx<Real> *>(a.states) + J.offset;
 
     LayCtx<R> L0;
-    lay_ctx<R>(L0, g, a.lat, tile, g.p[0], t, false);
-    load_tile<Real, R, NT>(v, st, L0);
+    lay_ctx<R, SP>(L0, g, a.lat, tile, g.p[0], t, false);
+    load_tile<Real, R, NT, SP>(v, st, L0);
 
     int cur = 0;
     if (preH) {
@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
     const bool need_norm = op.norm && (J.renorm || J.norm_trace);
     if (has_phase || need_norm) {
         LayCtx<R> Lm;
-        lay_ctx<R>(Lm, g, a.lat, tile, g.p[cur], t, has_phase, op.basis);
+        lay_ctx<R, SP>(Lm, g, a.lat, tile, g.p[cur], t, has_phase, op.basis);
         if (need_norm) {
             double s = block_sum(sumsq<Real, R>(v), red);
             if (t == 0 && J.norm_part) gst(J.norm_part, tile, s);
@@ -336,7 +336,7 @@ __global__ void __launch_bounds__(512) level_kernel(LevelArgs a) {
         }
     }
     if (cur != 0) exchange<Real, R>(v, lds, g.p[cur], g.p[0], t);
-    store_tile<Real, R, NT>(v, st, L0);
+    store_tile<Real, R, NT, SP>(v, st, L0);
 }
 
 // ---------------------------------------------------------------- full-window kernels
@@ -1185,6 +1185,13 @@ static hipError_t set_lds(const void *fn, size_t lds) {
 
 template <typename Real, int R, bool NT>
 static hipError_t do_level_nt(const LevelArgs &a, dim3 grid, size_t lds, hipStream_t s) {
+    if (a.geom.hi) {  // a group in two runs of qubits: the kernel with their address map
+        const void *fs = reinterpret_cast<const void *>(&level_kernel<Real, R, NT, true>);
+        hipError_t e = set_lds(fs, lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((level_kernel<Real, R, NT, true>), grid, dim3(1u << (a.geom.m - R)), lds, s, a);
+        return hipGetLastError();
+    }
     const void *fn = reinterpret_cast<const void *>(&level_kernel<Real, R, NT>);
     hipError_t e = set_lds(fn, lds);
     if (e != hipSuccess) return e;

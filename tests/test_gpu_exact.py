@@ -81,7 +81,9 @@ def test_hamiltonian_apply_full(Lx, Ly, dtype):
     (3, 4, z2h.Z2H_C128, None), (3, 4, z2h.Z2H_C64, None), (4, 4, z2h.Z2H_C64, None), (4, 4, z2h.Z2H_C128, None),
     (2, 5, z2h.Z2H_C128, "split=4:2:8:0/10:5:13:3:1c:h3@17/6:3:9:3"),
     (2, 5, z2h.Z2H_C64, "split=4:2:8:0/6:3:10:4:at8/10:5:14:4:1c"),
-    (4, 4, z2h.Z2H_C128, "split=12:4:12:0/10:5:13:3:1c:h7@22/10:5:13:3:1c,xcd=7")])
+    (4, 4, z2h.Z2H_C128, "split=12:4:12:0/10:5:13:3:1c:h7@22/10:5:13:3:1c,xcd=7"),
+    (2, 5, z2h.Z2H_C128, "split=4:2:8:0/10:4:13:3:h3@17/6:3:9:3"),
+    (4, 4, z2h.Z2H_C128, "split=12:4:12:0/10:4:13:3:h7@22/10:4:13:3,xcd=7")])
 def test_hamiltonian_apply_sampled_rows(Lx, Ly, dtype, cfg):
     """Three-group pass chains (3x4, 4x4, and groups in two runs of qubits
     with register windows across them): 4096 sampled rows, including the

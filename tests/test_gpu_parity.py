@@ -231,13 +231,17 @@ def test_component_exchange_bitwise(dtype, order):
 @pytest.mark.parametrize("dtype,order,cfg", [(C128, 0, "split=4:2:8:0/10:5:13:3:1c:h3@17/6:3:9:3"),
                                              (C64, 1, "split=4:2:8:0/10:5:14:4:1c:h3@17/6:3:10:4"),
                                              (C128, 1, "split=4:2:8:0/6:3:9:3:at8/10:5:13:3:1c"),
-                                             (C64, 0, "split=4:2:8:0/6:3:10:4:at8/10:5:14:4:1c")])
+                                             (C64, 0, "split=4:2:8:0/6:3:10:4:at8/10:5:14:4:1c"),
+                                             (C128, 0, "split=4:2:8:0/10:4:13:3:h3@17/6:3:9:3"),
+                                             (C64, 1, "split=4:2:8:0/6:3:10:4:at8/10:4:13:3")])
 def test_split_run_group(dtype, order, cfg):
     """2x5 torus (20 qubits) with a group in two runs of qubits, one of
     whose register windows holds bits of both runs: the middle group
     (qubits 4-10 and 17-19), or the last group (qubits 4-7 and 14-19, with
-    the x-basis phase and the x-basis observables on it).  State and
-    observables against the oracle."""
+    the x-basis phase and the x-basis observables on it); groups of whole
+    windows run the component-exchange kernels, the others (ten qubits in
+    windows of four) the general pass kernel.  State and observables
+    against the oracle."""
     c1 = (1.0, 0.8, 0.35, 0.25)
     M, dt = 12, 0.1
     print(f"case 2x5 {cfg} dtype={dtype} order={order}", flush=True)

@@ -236,6 +236,13 @@ def test_split_run_groups():
                 "split=12:4:12:0/10:5:14:4:hx/10:5:14:4"):
         with pytest.raises(z2h.Z2HError):
             z2h.z2h_plan_create_config(4, 4, z2h.Z2H_C64, bad)
+    # groups that are not whole windows (general pass kernel) may take two runs too
+    for dt, cfg in ((z2h.Z2H_C128, "split=12:4:12:0/10:4:13:3:h7@22/10:4:13:3"),
+                    (z2h.Z2H_C64, "split=4:2:8:0/10:4:13:3:h3@17/6:3:10:4")):
+        plan = z2h.z2h_plan_create_config(4 if dt == z2h.Z2H_C128 else 2, 4 if dt == z2h.Z2H_C128 else 5, dt, cfg)
+        gs = z2h.z2h_plan_describe(plan)["groups"]
+        assert gs[1]["hi"] and not gs[1]["full"]
+        check_geometry(plan)
     # complex128 tiles of 2^14 amplitudes: the passes fit (component
     # exchange), the observables' whole-element transform does not
     with pytest.raises(z2h.Z2HError):
@@ -307,10 +314,10 @@ def check_geometry(plan):
         tilebits = set(tile_positions(g, n))
         assert not (local & tilebits) and (local | tilebits) == set(range(n))
         if hr:
-            # two separate runs; a window across them only in component-exchange groups
-            assert g["full"] and g["b1"] > b0 + m - c - hr
-            if any(p < m - hr < p + R for p in g["p"]):
-                assert g["cx"] == 1
+            # two separate runs: groups of whole windows only with the
+            # component exchange (the other straight-line kernels keep one run)
+            assert g["b1"] > b0 + m - c - hr
+            assert not g["full"] or g["cx"] == 1
         covered += [gbit(g, x) for x in range(x0, x1)]
         # layouts: windows of R local bits inside the transform range, never
         # straddling the carried boundary; butterflies cover [x0, x1) once
