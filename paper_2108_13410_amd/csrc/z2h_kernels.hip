@@ -667,28 +667,46 @@ __device__ __forceinline__ void level_body(const LevelArgs &a) {
     // record (scalar loads) gives the state's offset first, and a block whose
     // job has no pass at this level returns before loading.
     Cx<Real> *st = base + a.jbase + (uint64_t)jb * a.jstride;
-    constexpr bool TP = KS == kPhaseTab;
+    // TP: one state's precomputed table; TA (any-kind kernels): a batch's
+    // per-job tables, fetched ahead where the job record is read first
+    constexpr bool TP = KS == kPhaseTab, TA = KS == kAnyKind;
     typedef typename Vec2<Real>::type TV;
-    TV pre[TP ? kTabPre : 1];
+    typedef const __attribute__((address_space(1))) TV *GTab;
+    TV pre[TP || TA ? kTabPre : 1];
+    bool prefetched = false;
     const int entries = (a.lat.nst + 1) * (a.lat.n + 1);
     if constexpr (TP) {
-        typedef const __attribute__((address_space(1))) TV *GTab;
         const GTab src = (GTab)a.tabs + (size_t)(a.level - a.tab_lev0) * entries;
 #pragma unroll
         for (int i = 0; i < kTabPre; ++i) {
             const int j = (int)t + i * (int)blockDim.x;
             if (j < entries) pre[i] = src[j];
         }
+        prefetched = true;
     }
     JobDev J;
     LevelOp op;
     const bool early = a.jmode != 0;
     if (early) {
-        J = job_record(a.jobs, a.jidx ? job_index(a.jidx, jb) : jb, a.job_inline);
+        const int jrec = a.jidx ? job_index(a.jidx, jb) : jb;
+        J = job_record(a.jobs, jrec, a.job_inline);
         op = a.force_plain ? LevelOp{a.group, kPlainH, 0, -1, -1, 0, 0, 0}
                            : level_op(a.level - J.lev0, a.K, J.steps, J.k_begin, J.order);
         if (op.kind == kIdle || op.group != a.group) return;  // uniform per block
         st = base + J.offset;
+        if constexpr (TA) {
+            if (a.tabs && a.tab_stride && op.kind != kPlainH) {
+                const GTab src = (GTab)((const __attribute__((address_space(1))) unsigned char *)a.tabs +
+                                        (size_t)jrec * a.tab_stride) +
+                                 (size_t)(a.level - J.lev0) * entries;
+#pragma unroll
+                for (int i = 0; i < kTabPre; ++i) {
+                    const int j = (int)t + i * (int)blockDim.x;
+                    if (j < entries) pre[i] = src[j];
+                }
+                prefetched = true;
+            }
+        }
     }
     load_tiles<Real, R, NT, CX != 0>(v, st, L0);
     if (!early) {
@@ -706,23 +724,28 @@ __device__ __forceinline__ void level_body(const LevelArgs &a) {
     double2 *fac = table_scratch(smem);
     double *red = align16<double>(tab + (a.lat.nst + 1) * W);
 
-    if constexpr (TP) {
+    int tab_done = 0;  // table entries already in LDS
+    if constexpr (TP || TA) {
+        if (prefetched) {
 #pragma unroll
-        for (int i = 0; i < kTabPre; ++i) {
-            const int j = (int)t + i * (int)blockDim.x;
-            if (j < entries) tab[j] = Cx<Real>{pre[i].x, pre[i].y};
+            for (int i = 0; i < kTabPre; ++i) {
+                const int j = (int)t + i * (int)blockDim.x;
+                if (j < entries) tab[j] = Cx<Real>{pre[i].x, pre[i].y};
+            }
+            const int done = kTabPre * (int)blockDim.x;
+            tab_done = done < entries ? done : entries;
         }
-        const int done = kTabPre * (int)blockDim.x;
-        pass_multi<Real, R, NL, kPhaseB, NT, CX, true>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red,
-                                                        done < entries ? done : entries);
+    }
+    if constexpr (TP) {
+        pass_multi<Real, R, NL, kPhaseB, NT, CX, true>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red, tab_done);
     } else if constexpr (KS != kAnyKind) {
         pass_multi<Real, R, NL, KS, NT, CX>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red);
     } else {
         switch (op.kind) {
-            case kPhaseB: pass_multi<Real, R, NL, kPhaseB, NT, CX, true>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red); break;
+            case kPhaseB: pass_multi<Real, R, NL, kPhaseB, NT, CX, true>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red, tab_done); break;
             case kPlainH: pass_multi<Real, R, NL, kPlainH, NT, CX, true>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red); break;
-            case kHalfIn: pass_multi<Real, R, NL, kHalfIn, NT, CX, true>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red); break;
-            default: pass_multi<Real, R, NL, kHalfOut, NT, CX, true>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red); break;
+            case kHalfIn: pass_multi<Real, R, NL, kHalfIn, NT, CX, true>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red, tab_done); break;
+            default: pass_multi<Real, R, NL, kHalfOut, NT, CX, true>(a, J, op, jb, tile0, t, v, st, L0, lds, tab, fac, red, tab_done); break;
         }
     }
 }
