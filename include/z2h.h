@@ -156,9 +156,10 @@ z2h_status z2h_plan_create(int32_t Lx, int32_t Ly, z2h_dtype dtype, int32_t max_
 void z2h_plan_destroy(z2h_plan *plan); /* NULL-safe */
 
 /* state_bytes = 2^n * sizeof(complex); ws_evolve_bytes = workspace needed by
- * z2h_evolve (the z passes' norm partials and, for multi-group plans with
- * states of at most 64 MiB, room for the phase tables of 1024 levels, which
- * one launch computes ahead of the pass launches that read them);
+ * z2h_evolve (the z passes' norm partials and, for multi-group plans whose
+ * phase groups are whole windows, room for the phase tables of 1024
+ * levels, which one launch computes ahead of the pass launches that read
+ * them; ",tables=0" in a schedule string leaves them out);
  * ws_observe_bytes = workspace needed by z2h_observe (includes a
  * state-sized scratch copy); ws_adjoint_bytes = workspace for z2h_adjoint
  * without its per-step part: add 64 bytes per Trotter step plus 1024. */
@@ -600,17 +601,25 @@ z2h_status z2h_autotune(int32_t Lx, int32_t Ly, z2h_dtype dtype, int32_t batch, 
                         char *best, size_t best_len, double *best_ms_per_step);
 
 /* Plan with an explicit schedule string (as returned by z2h_autotune):
- * "split=G:R:m:c/..." lists, from the lowest qubits up, each transform
- * group's width G, register window 2^R, tile bits m and carried low bits c,
- * optionally followed by ":2" (two neighbouring tiles per workgroup, in two
- * register windows per thread) or ":2s" (the same two tiles on the two
- * halves of a workgroup of twice the threads, which share one tile's LDS);
- * "uniform,m=..,c=..,R=..,g0=.." is the general planner with fixed tile
- * parameters.  Either may end in ",nt=1" (streaming loads and stores)
- * and ",xcd=<mask>" (bit j set: the workgroups of the passes over group j
- * are renumbered so that each of the eight XCDs walks a contiguous range of
- * tiles; launches whose block count is not a multiple of 8 keep the
- * hardware order; default 1, group 0 only). */
+ * "split=G:R:m:c/..." lists each transform group's width G, register window
+ * 2^R, tile bits m and carried low bits c (group 0: qubits 0..G-1, c = 0).
+ * A group may add ":2" (two neighbouring tiles per workgroup, in two
+ * register windows per thread) or ":1c" (one tile per workgroup whose
+ * layout changes move the real and then the imaginary parts through half
+ * the LDS), then ":at<Q>" (its qubits start at Q) and ":h<N>[@<Q>]" (its
+ * top N qubits are a second run at qubits Q..Q+N-1, or the highest free
+ * ones).  A group without positions takes the lowest free qubits, in two
+ * runs if they are not contiguous.  Groups in two runs need ":1c" when
+ * their width is a whole number of windows.  "uniform,m=..,c=..,R=..,g0=.."
+ * is the general planner with fixed tile parameters.  Either may end in
+ * ",nt=1" (streaming loads and stores), ",xcd=<mask>" (bit j set: the
+ * workgroups of the passes over group j are renumbered so that each of the
+ * eight XCDs walks a contiguous range of tiles; launches whose block count
+ * is not a multiple of 8 keep the hardware order; default 1, group 0 only)
+ * and ",tables=0" (z2h_evolve lets every workgroup build its phase table
+ * instead of computing the tables ahead).  Z2H_ERR_INVALID for an
+ * unreadable string or qubits taken twice or left out;
+ * Z2H_ERR_UNSUPPORTED for a group whose workgroup or LDS would not fit. */
 z2h_status z2h_plan_create_config(int32_t Lx, int32_t Ly, z2h_dtype dtype, const char *schedule,
                                   z2h_plan **out);
 
