@@ -752,6 +752,57 @@ std::vector<std::string> tune_candidates(int Lx, int Ly, bool c128) {
         }
         if (out.size() >= kMaxCands) break;
     }
+    // Three-group schedules whose strided groups exchange one component at
+    // a time: the middle group may also take part of its qubits high in the
+    // state (":h<N>@<Q>"; the top group then takes the free qubits, in two
+    // runs), so that neither strided group has all its rows at the largest
+    // strides.  Variants of the best-ranked such schedule.
+    std::vector<std::string> bases(out);
+    if (P.n >= 26) {
+        // two ten-qubit strided groups with the component exchange above a
+        // contiguous group 0 (the structure search may rank only more groups)
+        const int G0 = P.n - 20, c = c_min;
+        for (int R0 : {4, 3, 5, 2}) {
+            if (G0 % R0) continue;
+            char buf[96];
+            snprintf(buf, sizeof buf, "split=%d:%d:%d:0/10:5:%d:%d:1c/10:5:%d:%d:1c,xcd=7", G0, R0, G0, c + 10, c,
+                     c + 10, c);
+            Plan T;
+            plan_base(Lx, Ly, c128, T);
+            if (plan_from_config(T, buf, m_pref, m_hi, c_min) != Z2H_OK) continue;
+            if (std::find(out.begin(), out.end(), std::string(buf)) == out.end()) out.push_back(buf);
+            bases.insert(bases.begin(), buf);
+            break;
+        }
+    }
+    for (const std::string &base : bases) {
+        if (base.compare(0, 6, "split=") != 0) continue;
+        std::vector<std::string> grp;
+        size_t a = 6, e;
+        const size_t comma = base.find(',');
+        const std::string body = base.substr(0, comma);
+        while ((e = body.find('/', a)) != std::string::npos) {
+            grp.push_back(body.substr(a, e - a));
+            a = e + 1;
+        }
+        grp.push_back(body.substr(a));
+        auto is_cx = [](const std::string &g) { return g.size() > 3 && g.compare(g.size() - 3, 3, ":1c") == 0; };
+        if (grp.size() != 3 || !is_cx(grp[1]) || !is_cx(grp[2])) continue;
+        const int G1 = atoi(grp[1].c_str());
+        for (int hi = G1 / 2; hi <= G1 / 2 + 2 && hi < G1; ++hi)
+            for (int d = 1; d <= 3; ++d) {
+                const int q = P.n - hi - 1 - d;
+                char buf[48];
+                snprintf(buf, sizeof buf, ":h%d@%d", hi, q);
+                const std::string cfg = "split=" + grp[0] + "/" + grp[1] + buf + "/" + grp[2] + ",xcd=7";
+                Plan T;
+                plan_base(Lx, Ly, c128, T);
+                if (plan_from_config(T, cfg.c_str(), m_pref, m_hi, c_min) == Z2H_OK &&
+                    std::find(out.begin(), out.end(), cfg) == out.end())
+                    out.push_back(cfg);
+            }
+        break;
+    }
     for (int m = m_hi - 2; m <= m_hi; ++m)
         for (int c = c_min; c <= c_min + 1; ++c) {
             char buf[96];
