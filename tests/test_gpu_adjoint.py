@@ -91,6 +91,32 @@ def test_adjoint_component_exchange_plan(dtype, cfg):
     assert np.all(np.isfinite(out[0][1])) and np.abs(out[0][1]).max() > 0
 
 
+@pytest.mark.parametrize("cfg", ["split=4:2:8:0/10:5:13:3:1c:h3@17/6:3:9:3",
+                                 "split=4:2:8:0/6:3:9:3:at8/10:5:13:3:1c"])
+def test_adjoint_split_run_plan(cfg):
+    """2x5 torus, complex128: plans with a group in two runs of qubits (the
+    middle group, or the last group with the x-basis phase) give the
+    gradient of a plan with contiguous groups, to rounding."""
+    print(f"case adjoint 2x5 {cfg}", flush=True)
+    rng = np.random.default_rng(9)
+    M, dt = 6, 0.15
+    c0, c1, H = (1, 1, 0, 0), (1, 0.9, 0.35, 0.25), (1, 0.9, 0.35, 0.25)
+    sZ = (np.arange(M) + 0.5) / M + rng.normal(0, 0.01, M)
+    sX = (np.arange(M) + 0.5) / M + rng.normal(0, 0.01, M)
+    out = []
+    for c in (cfg, "split=10:5:11:0/10:5:13:3:1c"):
+        plan = z2h.z2h_plan_create_config(2, 5, z2h.Z2H_C128, c)
+        tz = torch.tensor(sZ, dtype=torch.float64, requires_grad=True)
+        tx = torch.tensor(sX, dtype=torch.float64, requires_grad=True)
+        L = EvolveEnergy.apply(tz, tx, plan, c0, c1, dt, H)
+        L.backward()
+        out.append((L.item(), tz.grad.numpy(), tx.grad.numpy()))
+    assert abs(out[0][0] - out[1][0]) < 1e-12
+    np.testing.assert_allclose(out[0][1], out[1][1], atol=1e-11)
+    np.testing.assert_allclose(out[0][2], out[1][2], atol=1e-11)
+    assert np.abs(out[0][1]).max() > 0
+
+
 @pytest.mark.slow
 def test_adjoint_3x3_config():
     """3x3 torus, M = 200 (T = 20), two schedule values per step from the
