@@ -151,6 +151,21 @@ def test_autotuner_candidates_are_valid_plans(Lx, Ly, dt):
         check_geometry(z2h.z2h_plan_create_config(Lx, Ly, dt, c))
 
 
+def test_shipped_schedules_are_candidates():
+    """The shipped table's schedules build valid plans, and the 4x4 ones
+    (groups in two runs of qubits) are among the autotuner's candidates."""
+    import os
+    table = os.path.join(os.path.dirname(z2h.__file__), "tuned_mi355x.txt")
+    rows = [l.split() for l in open(table) if l.strip() and not l.startswith("#")]
+    assert rows
+    for n, c128, _bc, cfg in rows:
+        Lx, Ly = {18: (3, 3), 32: (4, 4)}[int(n)]
+        dt = z2h.Z2H_C128 if int(c128) else z2h.Z2H_C64
+        check_geometry(z2h.z2h_plan_create_config(Lx, Ly, dt, cfg))
+        if int(n) == 32:
+            assert cfg in z2h.z2h_tune_candidates(Lx, Ly, dt), cfg
+
+
 def test_block_order_option():
     """Group 0 runs in XCD-major block order by default; ",xcd=<mask>"
     selects the groups (bits above the group count are dropped)."""
