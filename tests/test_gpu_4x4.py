@@ -34,8 +34,8 @@ SZ = np.array([[1, 0], [0, -1]], complex)
 class Run:
     """One 4x4 state on the GPU (32 or 64 GiB) with its workspace."""
 
-    def __init__(self, dtype, Lx=4, Ly=4):
-        self.plan = z2h.z2h_plan_create(Lx, Ly, dtype)
+    def __init__(self, dtype, Lx=4, Ly=4, cfg=None):
+        self.plan = z2h.z2h_plan_create_config(Lx, Ly, dtype, cfg) if cfg else z2h.z2h_plan_create(Lx, Ly, dtype)
         sz = z2h.z2h_plan_sizes(self.plan)
         self.psi = z2h.alloc_state(self.plan)
         self.ws = z2h.alloc_bytes(max(sz["ws_evolve"] + 65536, sz["ws_observe"]))
@@ -57,6 +57,22 @@ class Run:
         torch.cuda.empty_cache()
 
 
+def _shipped_4x4():
+    """The 4x4 schedules of the shipped table, which bench.py times (strided
+    groups in two runs of qubits)."""
+    import os
+    out = {}
+    for line in open(os.path.join(os.path.dirname(z2h.__file__), "tuned_mi355x.txt")):
+        f = line.split()
+        if len(f) == 4 and f[0] == "32" and f[2] == "1":
+            out[z2h.Z2H_C128 if f[1] == "1" else z2h.Z2H_C64] = f[3]
+    return out
+
+
+SHIPPED_4X4 = _shipped_4x4()
+PLANS_4X4 = [(z2h.Z2H_C64, None), (z2h.Z2H_C128, None), (z2h.Z2H_C64, "shipped"), (z2h.Z2H_C128, "shipped")]
+
+
 def _popcount(a):
     a = a.astype(np.uint64)
     c = np.zeros(a.shape, np.int64)
@@ -65,10 +81,10 @@ def _popcount(a):
     return c
 
 
-@pytest.mark.parametrize("dtype", [z2h.Z2H_C64, z2h.Z2H_C128])
-def test_4x4_zero_field_phase(dtype):
-    print(f"case 4x4 zero field dtype={dtype}", flush=True)
-    r = Run(dtype)
+@pytest.mark.parametrize("dtype,plan", PLANS_4X4)
+def test_4x4_zero_field_phase(dtype, plan):
+    print(f"case 4x4 zero field dtype={dtype} plan={plan}", flush=True)
+    r = Run(dtype, cfg=SHIPPED_4X4[dtype] if plan else None)
     JA, JB, M, dt = 1.0, 0.8, 4, 0.1
     ob = r.ramp((JA, JB, 0, 0), (JA, JB, 0, 0), M, dt)
     tol = 1e-12 if dtype == z2h.Z2H_C128 else 2e-6
@@ -91,11 +107,13 @@ def test_4x4_zero_field_phase(dtype):
     r.free()
 
 
-@pytest.mark.parametrize("dtype", [z2h.Z2H_C64, z2h.Z2H_C128])
-def test_4x4_product_state(dtype):
-    """JA = JB = 0 from |0...0>: each link evolves on its own."""
-    print(f"case 4x4 product dtype={dtype}", flush=True)
-    r = Run(dtype)
+@pytest.mark.parametrize("dtype,plan", PLANS_4X4)
+def test_4x4_product_state(dtype, plan):
+    """JA = JB = 0 from |0...0>: each link evolves on its own (the planner's
+    schedule and the shipped one, whose strided groups are two runs of
+    qubits)."""
+    print(f"case 4x4 product dtype={dtype} plan={plan}", flush=True)
+    r = Run(dtype, cfg=SHIPPED_4X4[dtype] if plan else None)
     c0, c1, M, dt = (0, 0, 0.05, 0.3), (0, 0, 0.6, -0.1), 6, 0.2
     ob = r.ramp(c0, c1, M, dt, init=z2h.Z2H_INIT_ZERO)
     u = np.array([1, 0], complex)
@@ -346,13 +364,14 @@ def test_4x4_x_diagonal_dynamics(dtype):
     r.free()
 
 
-def test_4x4_star_sector_conserved():
+@pytest.mark.parametrize("plan", [None, "shipped"])
+def test_4x4_star_sector_conserved(plan):
     """h_z = 0 (Sec. IV): every term commutes with the stars and with the
     't Hooft loops, and psi_1 is their +1 eigenstate, so through the full
     mixed dynamics <A_v> = 1 and <V_1> = <V_2> = 1 at 32 qubits (complex64,
     renormalised each step)."""
-    print("case 4x4 star sector c64", flush=True)
-    r = Run(z2h.Z2H_C64)
+    print(f"case 4x4 star sector c64 plan={plan}", flush=True)
+    r = Run(z2h.Z2H_C64, cfg=SHIPPED_4X4[z2h.Z2H_C64] if plan else None)
     ob = r.ramp((1.0, 1.0, 0.0, 0.0), (0.9, 1.2, 0.45, 0.0), 10, 0.15, renorm=1)
     assert abs(ob["sumA"] - 16) < 16 * 2e-5
     assert abs(ob["xloop"][0] - 1) < 2e-5 and abs(ob["xloop"][1] - 1) < 2e-5
