@@ -705,7 +705,7 @@ def main():
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the batched scan shards by job with no communication, "
-              "and multi-GPU runs are not part of this build; use --gpus 1", file=sys.stderr)
+              "and multi-GPU runs are not implemented; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
